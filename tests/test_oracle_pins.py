@@ -1,0 +1,295 @@
+"""Pins for the CPU oracle: the paper's worked example, brute force on tiny
+inputs, closed forms, invariants and the per-level block bound.  CPU only."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+import synth
+from tests import treecheck
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_fig1():
+    spec = {}
+    rows = {"unpruned": [], "pruned": []}
+    leaves = {}
+    with open(os.path.join(GOLDEN, "fig1_abrainadrain.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            if tok[0] in ("text", "tau", "leaf", "b1"):
+                spec[tok[0]] = tok[1]
+            elif tok[1] == "leaves":
+                leaves[tok[0]] = tok[2].encode()
+            else:
+                kind = tok[0]
+                b = int(tok[4])
+                i = tok.index("marked")
+                j = tok.index("ptr")
+                marked = [int(x) for x in tok[i + 1:j]]
+                ptr = [tuple(int(v) for v in p.split(":")) for p in tok[j + 1:]]
+                rows[kind].append((b, marked, ptr))
+    return spec, rows, leaves
+
+
+def test_fig1_worked_example():
+    """Section 4, Figure 1 (unpruned reading; see the fixture's header)."""
+    spec, rows, leaves = _load_fig1()
+    t = oracle.build_tree(spec["text"].encode(), int(spec["tau"]), int(spec["leaf"]),
+                          b1=int(spec["b1"]), exact_split=False)
+    assert t.h == 3
+    for (b, marked, ptr), L in zip(rows["unpruned"], t.levels):
+        assert L.b == b
+        assert L.marked.tolist() == marked
+        assert list(zip(L.ptr_block.tolist(), L.ptr_off.tolist())) == ptr
+    assert t.leaves.tobytes() == leaves["unpruned"]
+    treecheck.check(treecheck.from_oracle(t, exact_split=False), spec["text"].encode())
+
+
+def _brute_equal(T, tau, leaf, b1, exact):
+    t = oracle.build_tree(T, tau, leaf, b1=b1, exact_split=exact)
+    lv, leaves = brute.build(T, tau, leaf, b1, exact_split=exact)
+    assert len(lv) == t.h
+    for a, L in zip(lv, t.levels):
+        assert a["b"] == L.b and a["c"] == L.c
+        assert a["marked"] == L.marked.tolist() or L is t.levels[-1]
+        assert a["ptr"] == list(zip(L.ptr_block.tolist(), L.ptr_off.tolist()))
+    assert leaves == t.leaves.tobytes()
+
+
+@pytest.mark.parametrize("sigma,nmax", [(2, 11), (3, 7)])
+def test_brute_force_exhaustive(sigma, nmax):
+    """Every text over a tiny alphabet: C oracle (memmem) == dictionary brute
+    force, for tau in {2,3}, leaf in {1,2} and every admissible b1 = leaf*tau^k."""
+    alph = b"ab" if sigma == 2 else b"abc"
+    cases = 0
+    for n in range(1, nmax + 1):
+        for word in itertools.product(alph, repeat=n):
+            T = bytes(word)
+            for tau in (2, 3):
+                for leaf in (1, 2):
+                    b1 = leaf
+                    while True:
+                        _brute_equal(T, tau, leaf, b1, True)
+                        cases += 1
+                        if b1 >= n:
+                            break
+                        b1 *= tau
+    assert cases > 10000
+
+
+def test_brute_force_general_split():
+    """General ceil(b/tau) split (Figure 1 style) on random small texts."""
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        n = int(rng.integers(1, 30))
+        T = bytes(rng.integers(97, 97 + int(rng.integers(1, 4)), n).astype(np.uint8))
+        tau = int(rng.integers(2, 5))
+        b1 = int(rng.integers(1, n + 1))
+        leaf = int(rng.integers(1, 3))
+        if b1 < leaf:
+            b1 = leaf
+        _brute_equal(T, tau, leaf, b1, False)
+
+
+def test_search_modes_agree():
+    """memmem over T == literal double loop == search restricted to level runs
+    (the 'leftmost on this level' reading of Section 4)."""
+    texts = [synth.cfg1_text(1 << 14), synth.random_text(3000, 4, 5),
+             synth.periodic_text(2048, 7, 1), bytes(b"ab" * 700),
+             synth.markov_versions(1 << 14, 1024, 16, 5e-3, 16, 9)]
+    for T in texts:
+        T = bytes(T)
+        for tau, leaf in ((2, 4), (3, 2), (4, 16)):
+            a = oracle.build_tree(T, tau, leaf, search=oracle.SEARCH_MEMMEM)
+            b = oracle.build_tree(T, tau, leaf, search=oracle.SEARCH_RUNS)
+            assert a.canonical == b.canonical
+            if len(T) <= 4096:
+                c = oracle.build_tree(T, tau, leaf, search=oracle.SEARCH_NAIVE)
+                assert a.canonical == c.canonical
+
+
+def test_unary_text():
+    """T = a^n (n >= 3*b1): blocks 0 and 1 are marked, every other block points
+    at (0, 0); every later level has 2*tau blocks; 2*tau leaves."""
+    for tau, leaf, n in ((2, 1, 200), (3, 2, 500), (4, 4, 1000)):
+        b1 = leaf
+        while b1 * tau * 3 <= n:
+            b1 *= tau
+        T = b"a" * n
+        t = oracle.build_tree(T, tau, leaf, b1=b1)
+        for li, L in enumerate(t.levels[:-1]):
+            assert L.marked[:2].tolist() == [1, 1] and not L.marked[2:].any()
+            assert (L.ptr_block == 0).all() and (L.ptr_off == 0).all()
+            if li > 0:
+                assert L.c == 2 * tau
+        assert t.levels[-1].c == 2 * tau
+        treecheck.check(treecheck.from_oracle(t), T)
+
+
+def test_all_distinct_text():
+    """A permutation of the byte values: every block on every level is marked."""
+    rng = np.random.default_rng(3)
+    for n in (256, 200, 77):
+        T = bytes(rng.permutation(256)[:n].astype(np.uint8))
+        for tau, leaf in ((2, 1), (3, 2), (4, 4)):
+            t = oracle.build_tree(T, tau, leaf)
+            for L in t.levels[:-1]:
+                assert L.u == 0 and L.marked.all()
+                assert L.c == -(-n // L.b)
+            assert t.leaves.tobytes() == T
+
+
+def test_period_two_text():
+    """(ab)^m with tau = 3 and leaf = 1 (odd block lengths): blocks 0 and 1 are
+    marked; even blocks j >= 2 point at (0, 0) and odd blocks j >= 3 at (0, 1)."""
+    for m in (60, 121):
+        T = b"ab" * m
+        n = len(T)
+        b1 = 1
+        while b1 * 3 * 3 <= n:
+            b1 *= 3
+        t = oracle.build_tree(T, 3, 1, b1=b1)
+        for L in t.levels[:-1]:
+            assert L.marked[:2].tolist() == [1, 1] and not L.marked[2:].any()
+            js = np.arange(2, L.c)
+            assert L.ptr_block.tolist() == [0] * (L.c - 2)
+            assert L.ptr_off.tolist() == [int(j % 2) for j in js]
+        treecheck.check(treecheck.from_oracle(t), T)
+
+
+@pytest.mark.parametrize("name", ["cfg1_16k", "markov", "random", "periodic"])
+def test_invariants(name):
+    T = {
+        "cfg1_16k": lambda: synth.cfg1_text(1 << 14),
+        "markov": lambda: synth.markov_versions(50000, 4096, 12, 2e-3, 32, 21),
+        "random": lambda: synth.random_text(20000, 4, 8),
+        "periodic": lambda: synth.periodic_text(30001, 97, 2),
+    }[name]()
+    T = bytes(T)
+    for tau, leaf, s in ((2, 16, 1), (4, 16, 1), (3, 5, 1), (2, 8, 64)):
+        t = oracle.build_tree(T, tau, leaf, s_hint=s)
+        treecheck.check(treecheck.from_oracle(t), T)
+
+
+def test_blocks_per_level_bound():
+    """Section 4, lemma on blocks per level: c_l <= 3*z*tau for l >= 2, with z
+    from a brute-force LZ77 parse."""
+    rng = np.random.default_rng(5)
+    texts = [synth.cfg1_text(1500, seed=3), bytes(b"abcab" * 100), synth.random_text(700, 2, 4)]
+    for _ in range(20):
+        texts.append(synth.markov_versions(int(rng.integers(50, 900)), 40, 8, 0.02, 4,
+                                           int(rng.integers(1 << 30))))
+    for T in texts:
+        T = bytes(T)
+        z = brute.lz77_z(T)
+        for tau, leaf in ((2, 1), (3, 2), (4, 1)):
+            t = oracle.build_tree(T, tau, leaf)
+            for L in t.levels[1:]:
+                assert L.c <= 3 * z * tau
+
+
+def test_plan():
+    """Level plan: b1 = leaf*tau^k with the largest k such that b1 <= n/s."""
+    assert oracle.plan(1 << 20, 2, 16) == (1 << 20, 17)
+    assert oracle.plan(1 << 28, 4, 16) == (1 << 28, 13)
+    assert oracle.plan(1 << 31, 2, 16) == (1 << 31, 28)
+    assert oracle.plan(1 << 20, 2, 16, s_hint=10000) == (64, 3)
+    assert oracle.plan(10, 2, 16) == (16, 1)
+    assert oracle.plan(0, 2, 16) == (16, 1)
+    assert oracle.plan(100, 3, 2, root_block_len=54) == (54, 4)
+    with pytest.raises(ValueError):
+        oracle.plan(100, 3, 2, root_block_len=50)
+    with pytest.raises(ValueError):
+        oracle.plan(100, 1, 2)
+
+
+def test_empty_and_tiny():
+    t = oracle.build_tree(b"", 2, 16)
+    assert t.h == 1 and t.levels[0].c == 0 and t.leaves.size == 0
+    t = oracle.build_tree(b"x", 2, 1)
+    assert t.h == 1 and t.leaves.tobytes() == b"x"
+
+
+# ---- Karp-Rabin fingerprints (Section 2, phi; Section 5.3, the two update rules)
+
+P = oracle.P61
+
+
+def test_prefix_fp_definition():
+    """P[e] - P[s]*x^(e-s) equals the defining sum of T[i]*x^(e-1-i) over the
+    window, evaluated with Python integers."""
+    rng = np.random.default_rng(1)
+    for n in (1, 2, 17, 300):
+        T = rng.integers(0, 256, n).astype(np.uint8)
+        x = int(rng.integers(256, P - 1))
+        Pa = oracle.prefix_fp(T, x)
+        for _ in range(30):
+            s = int(rng.integers(0, n))
+            e = int(rng.integers(s, n + 1))
+            want = sum(int(T[i]) * pow(x, e - 1 - i, P) for i in range(s, e)) % P
+            got = (int(Pa[e]) - int(Pa[s]) * pow(x, e - s, P)) % P
+            assert got == want
+            assert oracle.window_fp(T, s, e - s, x) == want
+
+
+def test_prefix_fp_geometric_closed_form():
+    """A constant text c^n has P[n] = c*(x^n - 1)/(x - 1) mod p."""
+    for c, n, x in ((1, 1000, 3), (200, 4097, 123456789012345), (255, 1, P - 2)):
+        T = np.full(n, c, np.uint8)
+        want = c * (pow(x, n, P) - 1) * pow(x - 1, P - 2, P) % P
+        assert int(oracle.prefix_fp(T, x)[n]) == want
+
+
+def test_rolling_identities():
+    """The one-step roll (Section 5.3, conventional relation) and the 16-step
+    jump used by the SIMD kernel (Section 5.3, first equation)."""
+    rng = np.random.default_rng(2)
+    T = rng.integers(0, 256, 500).astype(np.uint8)
+    x = 0x1234567890ABCDE % P
+    for L in (1, 5, 16, 40):
+        for s in range(1, 500 - L - 16):
+            e = s + L - 1
+            f = oracle.window_fp(T, s, L, x)
+            prev = oracle.window_fp(T, s - 1, L, x)
+            assert f == (prev * x - int(T[s - 1]) * pow(x, L, P) + int(T[e])) % P
+            if s >= 16 and L >= 16:
+                back = oracle.window_fp(T, s - 16, L, x)
+                head = oracle.window_fp(T, s - 16, 16, x)
+                tail = oracle.window_fp(T, e - 15, 16, x)
+                assert f == (back * pow(x, 16, P) - head * pow(x, L, P) + tail) % P
+            if s > 60:
+                break
+
+
+# ---- counted-prefix queries (Section 1)
+
+def test_rank_select_access_against_numpy():
+    rng = np.random.default_rng(4)
+    T = synth.cfg1_text(1 << 15)
+    n = T.size
+    pos = rng.integers(0, n + 1, 5000).astype(np.uint64)
+    cs = rng.choice(np.frombuffer(b"ACGTZ", np.uint8), 5000)
+    got = oracle.rank(T, cs, pos)
+    for c in np.unique(cs):
+        cum = np.concatenate([[0], np.cumsum(T == c)])
+        sel = cs == c
+        assert (got[sel] == cum[pos[sel].astype(np.int64)]).all()
+    ks = rng.integers(0, 9000, 5000).astype(np.uint64)
+    got = oracle.select(T, cs, ks)
+    for c in np.unique(cs):
+        where = np.flatnonzero(T == c)
+        sel = np.flatnonzero(cs == c)
+        for q in sel:
+            k = int(ks[q])
+            want = int(where[k - 1]) if 1 <= k <= where.size else 2**64 - 1
+            assert int(got[q]) == want
+    ap = rng.integers(0, n, 1000).astype(np.uint64)
+    assert (oracle.access(T, ap) == T[ap.astype(np.int64)]).all()
