@@ -1,0 +1,203 @@
+/*
+ * bt.h -- C ABI of libbt: block-tree construction and queries on one MI355X
+ * (gfx950) GPU.
+ *
+ * The method is the per-level construction of Belazzougui et al.'s block tree
+ * as described in "Practical Parallel Block Tree Construction: First Results"
+ * (Clausecker, Kurpicz, Palanga): Section 4 defines the tree, Section 4.1 its
+ * two phases (mark the leftmost occurrence of every pair of consecutive blocks;
+ * point every unmarked block at the leftmost occurrence of its content),
+ * Section 2 the Karp-Rabin fingerprints used to find candidate occurrences, and
+ * Section 1 the access/rank/select queries.  Every fingerprint hit that decides
+ * the output is confirmed by comparing bytes, so the tree is exact.
+ *
+ * Conventions for every entry point
+ *   - Return value: BT_OK (0) or a negative BT_E_* status; no exceptions cross
+ *     this boundary.  bt_ctx_last_error() gives a message for the last failure.
+ *   - Device pointers ("d_" prefix) must point into memory of the context's
+ *     device; host pointers ("h_" prefix, or none) are ordinary host memory.
+ *   - Work is enqueued on the context's stream.  Builds and queries return after
+ *     their device work has completed (the level loop reads per-level counts).
+ *     Inputs must stay valid and unmodified until the call returns.
+ *   - Positions are 0-based byte offsets; all sizes are in bytes or elements.
+ *   - Text bytes are raw uint8 values (the paper's T in [1, sigma]^n, shifted to
+ *     0-based symbols).
+ *   - A context is used by one host thread at a time.  Finished trees are
+ *     read-only; any number of query calls may read them.
+ */
+#ifndef BT_H
+#define BT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define BT_API __attribute__((visibility("default")))
+#else
+#define BT_API
+#endif
+
+/* ---- status codes ---- */
+#define BT_OK 0
+#define BT_E_INVAL (-1)    /* an argument is out of range (see each call)     */
+#define BT_E_NOMEM (-2)    /* a device or host allocation failed               */
+#define BT_E_DEVICE (-3)   /* a HIP runtime call failed                        */
+#define BT_E_INTERNAL (-4) /* a device-side consistency check failed           */
+
+/* ---- debug flags (bt_params.debug_flags) ---- */
+/* Truncate every fingerprint to 12 bits.  Forces fingerprint collisions so that
+ * the byte-verification and retry paths run; the output must not change. */
+#define BT_DBG_WEAK_HASH 1u
+
+typedef struct bt_ctx bt_ctx;   /* device, stream, scratch pool, statistics */
+typedef struct bt_tree bt_tree; /* a finished tree, resident in device memory */
+
+/*
+ * Build parameters.
+ *   tau            inner arity (Section 4: every marked block has tau
+ *                  children); >= 2.
+ *   leaf_len       block length of the last level, whose blocks are stored
+ *                  explicitly (Section 4, stop at |B| in Theta(log_sigma n)); >= 1.
+ *   root_block_len 0 to plan by s_hint; otherwise the level-1 block length
+ *                  b1, which must equal leaf_len * tau^k for some k >= 0.
+ *   s_hint         target root arity s (Section 4, s = z is the space-optimal
+ *                  choice): b1 = leaf_len * tau^k with the largest k >= 0 such
+ *                  that b1 <= n / s_hint (k = 0 when n / s_hint < leaf_len).
+ *                  0 is read as 1.  Then s = ceil(n / b1).
+ *   hash_seed      seeds the Karp-Rabin base x in [2^8, 2^61-1); the tree does
+ *                  not depend on it.
+ *   debug_flags    BT_DBG_* bits.
+ * Block lengths are b_l = b1 / tau^(l-1); the tree has h = k + 1 levels and
+ * level h holds the leaves.  Every block has length b_l except the one that
+ * ends the text, which may be shorter.
+ */
+typedef struct {
+  uint32_t tau;
+  uint32_t leaf_len;
+  uint64_t root_block_len;
+  uint64_t s_hint;
+  uint64_t hash_seed;
+  uint32_t debug_flags;
+  uint32_t reserved;
+} bt_params;
+
+/* ---- context ---- */
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  The context owns a pool of
+ * device scratch memory that grows on demand and is released by
+ * bt_ctx_destroy.  Errors: BT_E_INVAL (bad device or out == NULL),
+ * BT_E_DEVICE. */
+BT_API int bt_ctx_create(int device, void* hip_stream, bt_ctx** out);
+BT_API void bt_ctx_destroy(bt_ctx* ctx);
+/* Message describing the last failure on this context (never NULL). */
+BT_API const char* bt_ctx_last_error(const bt_ctx* ctx);
+/* Release pooled scratch memory that is not in use. */
+BT_API int bt_ctx_trim(bt_ctx* ctx);
+
+/* Per-kernel timing, measured with HIP events on the context's stream around
+ * each launch of the named kernel while enabled.  `bytes` accumulates the
+ * kernel's algorithmic traffic (the bytes the method must move; defined with
+ * each kernel in the design notes) and `units` its work units (windows for the
+ * probe scan, text bytes for the prefix scan).  Names: "prefix_fp",
+ * "probe_scan", "verify". */
+BT_API int bt_ctx_profile(bt_ctx* ctx, int enable);
+BT_API int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches,
+                        double* total_ms, double* bytes, double* units);
+BT_API int bt_ctx_reset_stats(bt_ctx* ctx);
+
+/* ---- step (a2) on its own: prefix fingerprints ----
+ * Section 2, the Karp-Rabin fingerprint phi, with q = 2^61-1 and r = x:
+ *   d_P[0] = 0,  d_P[i+1] = (d_P[i] * x + d_text[i]) mod (2^61 - 1),
+ * so that the fingerprint of T[i..i+L) is (P[i+L] - P[i] * x^L) mod q.
+ * d_text: n bytes (device).  d_P: n+1 uint64 (device, caller-owned).
+ * x must be in [1, 2^61-1).  Errors: BT_E_INVAL. */
+BT_API int bt_prefix_fingerprints(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
+                           uint64_t* d_P);
+
+/* ---- builds ----
+ * Build the block tree of the n bytes at d_text (device, caller-owned).
+ * sigma is an upper bound on the number of distinct byte values (1..256); it
+ * sizes the rank/select support and is checked: more distinct values than
+ * sigma -> BT_E_INVAL.  n = 0 gives an empty tree with one (leaf) level.
+ * On success *out receives a tree owned by the caller (free with
+ * bt_tree_free).  Errors: BT_E_INVAL (tau < 2, leaf_len = 0, sigma outside
+ * 1..256, a bad root_block_len, out == NULL), BT_E_NOMEM, BT_E_DEVICE,
+ * BT_E_INTERNAL. */
+BT_API int bt_build(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma, uint32_t tau,
+             uint32_t leaf_len, bt_tree** out);
+BT_API int bt_build_ex(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
+                const bt_params* params, bt_tree** out);
+
+/* Build `num` independent trees in one pass: text i is
+ * d_concat[h_offsets[i] .. h_offsets[i+1]) (h_offsets: num+1 host values,
+ * non-decreasing, h_offsets[0] may be > 0).  All texts share params (each text
+ * gets its own b1 from its own length).  Levels of every text with the same
+ * block length are processed by the same kernel launches.  Tree i equals
+ * bt_build_ex of text i with the same params.  outs: num host slots.
+ * Errors: as bt_build_ex; on failure no tree is returned. */
+BT_API int bt_build_batch(bt_ctx* ctx, const uint8_t* d_concat, const uint64_t* h_offsets,
+                   uint32_t num, uint32_t sigma, const bt_params* params, bt_tree** outs);
+
+/* ---- tree inspection (the stored structure: Section 5.4, one bit vector
+ *      of marks per level plus pointers and offsets) ---- */
+
+/* n, the number of levels h (>= 1), and b1. */
+BT_API int bt_tree_info(const bt_tree* tree, uint64_t* n, uint32_t* h, uint64_t* b1);
+/* Level l in 1..h: block length b, number of blocks c, number of unmarked
+ * blocks u (0 on level h).  Errors: BT_E_INVAL for l outside 1..h. */
+BT_API int bt_level_info(const bt_tree* tree, uint32_t level, uint64_t* b, uint64_t* c, uint64_t* u);
+/* Copy level l (< h) to host buffers (any may be NULL):
+ *   marked_words  ceil(c/64) uint64, bit j%64 of word j/64 = block j marked
+ *                 (LSB first, pad bits zero)
+ *   ptr_block     u uint64: for the k-th unmarked block (in block order), the
+ *                 index among this level's blocks of the block holding the
+ *                 first byte of the leftmost occurrence of its content
+ *   ptr_off       u uint64: offset of that occurrence inside that block
+ * Errors: BT_E_INVAL for l outside 1..h-1. */
+BT_API int bt_level_copy(const bt_tree* tree, uint32_t level, uint64_t* marked_words,
+                  uint64_t* ptr_block, uint64_t* ptr_off);
+/* Number of leaf bytes (the sum of the level-h block lengths) and a copy of
+ * them, block by block, into a host buffer. */
+BT_API int bt_leaves_size(const bt_tree* tree, uint64_t* bytes);
+BT_API int bt_leaves_copy(const bt_tree* tree, uint8_t* dst);
+
+/* Canonical little-endian serialisation, compared byte for byte in tests:
+ *   "BTv1", u64 n, u32 tau, u32 leaf_len, u64 b1, u32 h, u32 0,
+ *   for each level l < h: u64 b, u64 c, ceil(c/64) u64 mark words, u64 u,
+ *                         u64 ptr_block[u], u64 ptr_off[u]
+ *   level h: u64 b, u64 c, u64 leaf byte count, the leaf bytes, zero padding
+ *            to a multiple of 8.
+ * With dst == NULL only *written (the size) is set.  Errors: BT_E_INVAL when
+ * cap is too small. */
+BT_API int bt_serialize(const bt_tree* tree, uint8_t* dst, uint64_t cap, uint64_t* written);
+
+/* ---- queries (Section 1), batched; all arrays are device memory ----
+ *   access(i)    = T[i]                               for i in [0, n)
+ *   rank(c, i)   = #{ j < i : T[j] = c }              for i in [0, n]
+ *   select(c, k) = position of the k-th occurrence of c, k >= 1
+ * (rank is the paper's rank_c(i) with 1-based inclusive positions; select is
+ * the paper's select minus one.)  Out-of-range i, k = 0 or k > count(c) give
+ * UINT64_MAX; access of an out-of-range i gives 0 and the call returns
+ * BT_E_INVAL after answering the rest.  Rank and select need the tree to have
+ * been built with rank support (always, for sigma <= 256). */
+BT_API int bt_access(bt_ctx* ctx, const bt_tree* tree, const uint64_t* d_pos, uint64_t m,
+              uint8_t* d_out);
+BT_API int bt_rank(bt_ctx* ctx, const bt_tree* tree, const uint8_t* d_c, const uint64_t* d_pos,
+            uint64_t m, uint64_t* d_out);
+BT_API int bt_select(bt_ctx* ctx, const bt_tree* tree, const uint8_t* d_c, const uint64_t* d_k,
+              uint64_t m, uint64_t* d_out);
+
+/* Device bytes held by a tree. */
+BT_API int bt_tree_device_bytes(const bt_tree* tree, uint64_t* bytes);
+BT_API void bt_tree_free(bt_tree* tree);
+BT_API const char* bt_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BT_H */

@@ -1,0 +1,264 @@
+"""Python binding of libbt (include/bt.h): block-tree construction and queries on
+an MI355X GPU.
+
+This module only marshals arguments: every step of construction and every query
+runs in the HIP kernels of ``libbt.so``.  PyTorch supplies device memory (CUDA
+tensors on ROCm) and the current stream.  If ``libbt.so`` is missing, importing
+the binding raises; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbt.so")
+
+BT_OK, BT_E_INVAL, BT_E_NOMEM, BT_E_DEVICE, BT_E_INTERNAL = 0, -1, -2, -3, -4
+BT_DBG_WEAK_HASH = 1
+
+_lib = None
+
+
+class BtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "error"), code, msg))
+        self.code = code
+
+
+_ERRNAMES = {BT_E_INVAL: "BT_E_INVAL", BT_E_NOMEM: "BT_E_NOMEM", BT_E_DEVICE: "BT_E_DEVICE",
+             BT_E_INTERNAL: "BT_E_INTERNAL"}
+
+
+class bt_params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_uint32), ("leaf_len", ctypes.c_uint32),
+                ("root_block_len", ctypes.c_uint64), ("s_hint", ctypes.c_uint64),
+                ("hash_seed", ctypes.c_uint64), ("debug_flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+# name -> (restype, argtypes); the exported surface of include/bt.h
+_vp, _u64, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+_pu64, _pu32, _pd = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "bt_ctx_create": (_i32, [_i32, _vp, ctypes.POINTER(_vp)]),
+    "bt_ctx_destroy": (None, [_vp]),
+    "bt_ctx_last_error": (ctypes.c_char_p, [_vp]),
+    "bt_ctx_trim": (_i32, [_vp]),
+    "bt_ctx_profile": (_i32, [_vp, _i32]),
+    "bt_ctx_kernel_stats": (_i32, [_vp, ctypes.c_char_p, _pu64, _pd, _pd, _pd]),
+    "bt_ctx_reset_stats": (_i32, [_vp]),
+    "bt_prefix_fingerprints": (_i32, [_vp, _vp, _u64, _u64, _vp]),
+    "bt_build": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, ctypes.POINTER(_vp)]),
+    "bt_build_ex": (_i32, [_vp, _vp, _u64, _u32, ctypes.POINTER(bt_params), ctypes.POINTER(_vp)]),
+    "bt_build_batch": (_i32, [_vp, _vp, _vp, _u32, _u32, ctypes.POINTER(bt_params), _vp]),
+    "bt_tree_info": (_i32, [_vp, _pu64, _pu32, _pu64]),
+    "bt_level_info": (_i32, [_vp, _u32, _pu64, _pu64, _pu64]),
+    "bt_level_copy": (_i32, [_vp, _u32, _vp, _vp, _vp]),
+    "bt_leaves_size": (_i32, [_vp, _pu64]),
+    "bt_leaves_copy": (_i32, [_vp, _vp]),
+    "bt_serialize": (_i32, [_vp, _vp, _u64, _pu64]),
+    "bt_access": (_i32, [_vp, _vp, _vp, _u64, _vp]),
+    "bt_rank": (_i32, [_vp, _vp, _vp, _vp, _u64, _vp]),
+    "bt_select": (_i32, [_vp, _vp, _vp, _vp, _u64, _vp]),
+    "bt_tree_device_bytes": (_i32, [_vp, _pu64]),
+    "bt_tree_free": (None, [_vp]),
+    "bt_strerror": (ctypes.c_char_p, [_i32]),
+}
+
+
+def lib():
+    """Load libbt.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbt.so not built: run __graft_entry__.build() or "
+                              "python paper_2512_23314_amd/_build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A bt_ctx bound to one device and the torch current stream at creation."""
+
+    def __init__(self, device=0, stream=None):
+        torch = _torch()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib().bt_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise BtError(rc, "bt_ctx_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().bt_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise BtError(rc, lib().bt_ctx_last_error(self.h).decode())
+
+    # ---- profiling
+    def profile(self, on=True):
+        self._check(lib().bt_ctx_profile(self.h, 1 if on else 0))
+
+    def reset_stats(self):
+        self._check(lib().bt_ctx_reset_stats(self.h))
+
+    def kernel_stats(self, name):
+        n = ctypes.c_uint64()
+        ms, by, un = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(lib().bt_ctx_kernel_stats(self.h, name.encode(), ctypes.byref(n),
+                                              ctypes.byref(ms), ctypes.byref(by), ctypes.byref(un)))
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value, "units": un.value}
+
+    def trim(self):
+        self._check(lib().bt_ctx_trim(self.h))
+
+    # ---- step a2
+    def prefix_fingerprints(self, text, x, out=None):
+        torch = _torch()
+        n = text.numel()
+        if out is None:
+            out = torch.empty(n + 1, dtype=torch.uint64, device=text.device)
+        self._check(lib().bt_prefix_fingerprints(self.h, _ptr(text), n, x, _ptr(out)))
+        return out
+
+    # ---- builds
+    @staticmethod
+    def params(tau, leaf_len, s_hint=1, root_block_len=0, hash_seed=0x0B10C7EE, debug_flags=0):
+        return bt_params(tau, leaf_len, root_block_len, s_hint, hash_seed, debug_flags, 0)
+
+    def build(self, text, sigma=256, tau=2, leaf_len=16, **kw):
+        """Build the tree of a uint8 CUDA tensor; returns a Tree."""
+        p = self.params(tau, leaf_len, **kw)
+        h = ctypes.c_void_p()
+        self._check(lib().bt_build_ex(self.h, _ptr(text), text.numel(), sigma, ctypes.byref(p),
+                                      ctypes.byref(h)))
+        return Tree(self, h)
+
+    def build_batch(self, concat, offsets, sigma=256, tau=2, leaf_len=16, **kw):
+        """Build one tree per text concat[offsets[i]:offsets[i+1]]."""
+        p = self.params(tau, leaf_len, **kw)
+        offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+        num = offs.size - 1
+        outs = (ctypes.c_void_p * max(num, 1))()
+        self._check(lib().bt_build_batch(self.h, _ptr(concat), offs.ctypes.data_as(ctypes.c_void_p),
+                                         num, sigma, ctypes.byref(p), outs))
+        return [Tree(self, ctypes.c_void_p(outs[i])) for i in range(num)]
+
+
+class Tree:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.h = handle
+        n, hh, b1 = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
+        lib().bt_tree_info(self.h, ctypes.byref(n), ctypes.byref(hh), ctypes.byref(b1))
+        self.n, self.height, self.b1 = n.value, hh.value, b1.value
+
+    def free(self):
+        if self.h:
+            lib().bt_tree_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def level_info(self, level):
+        b, c, u = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        rc = lib().bt_level_info(self.h, level, ctypes.byref(b), ctypes.byref(c), ctypes.byref(u))
+        if rc != 0:
+            raise BtError(rc, "bad level")
+        return b.value, c.value, u.value
+
+    def level(self, level):
+        """(b, marked uint8[c], ptr_block uint64[u], ptr_off uint64[u]) for level < h."""
+        b, c, u = self.level_info(level)
+        words = np.zeros((c + 63) // 64, np.uint64)
+        pb = np.zeros(u, np.uint64)
+        po = np.zeros(u, np.uint64)
+        rc = lib().bt_level_copy(self.h, level, words.ctypes.data_as(ctypes.c_void_p),
+                                 pb.ctypes.data_as(ctypes.c_void_p), po.ctypes.data_as(ctypes.c_void_p))
+        if rc != 0:
+            raise BtError(rc, "bt_level_copy")
+        bits = np.unpackbits(words.view(np.uint8), bitorder="little")[:c]
+        return b, bits.astype(np.uint8), pb, po
+
+    def leaves(self):
+        nb = ctypes.c_uint64()
+        lib().bt_leaves_size(self.h, ctypes.byref(nb))
+        out = np.zeros(nb.value, np.uint8)
+        rc = lib().bt_leaves_copy(self.h, out.ctypes.data_as(ctypes.c_void_p))
+        if rc != 0:
+            raise BtError(rc, "bt_leaves_copy")
+        return out
+
+    def serialize(self):
+        w = ctypes.c_uint64()
+        rc = lib().bt_serialize(self.h, None, 0, ctypes.byref(w))
+        if rc != 0:
+            raise BtError(rc, "bt_serialize")
+        buf = np.zeros(w.value, np.uint8)
+        rc = lib().bt_serialize(self.h, buf.ctypes.data_as(ctypes.c_void_p), w.value, ctypes.byref(w))
+        if rc != 0:
+            raise BtError(rc, "bt_serialize")
+        return buf.tobytes()
+
+    def device_bytes(self):
+        b = ctypes.c_uint64()
+        lib().bt_tree_device_bytes(self.h, ctypes.byref(b))
+        return b.value
+
+    # ---- queries (device tensors in, device tensors out)
+    def access(self, pos, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(pos.numel(), dtype=torch.uint8, device=pos.device)
+        self.ctx._check(lib().bt_access(self.ctx.h, self.h, _ptr(pos), pos.numel(), _ptr(out)))
+        return out
+
+    def rank(self, cs, pos, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(pos.numel(), dtype=torch.uint64, device=pos.device)
+        self.ctx._check(lib().bt_rank(self.ctx.h, self.h, _ptr(cs), _ptr(pos), pos.numel(), _ptr(out)))
+        return out
+
+    def select(self, cs, ks, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(ks.numel(), dtype=torch.uint64, device=ks.device)
+        self.ctx._check(lib().bt_select(self.ctx.h, self.h, _ptr(cs), _ptr(ks), ks.numel(), _ptr(out)))
+        return out

@@ -1,0 +1,1098 @@
+// libbt host side: the C ABI of include/bt.h, the device memory pool, and the
+// level loop that drives the kernels of level.hip.
+//
+// Build, for one or many texts (a single text is a batch of one):
+//   - plan every text: b1 = leaf * tau^k (k from s_hint or root_block_len),
+//     h = k + 1 levels;
+//   - prefix fingerprints of the whole concatenation, once (step a2);
+//   - steps s = 0 .. H-1 with block length b = leaf * tau^(H-1-s): a text whose
+//     b1 equals b enters with its level-1 blocks, every other present text
+//     continues with the children of its marked blocks; all present texts go
+//     through the same launches (phase 1, marks, phase 2, pointers, split);
+//   - the last step (b = leaf) stores the leaf bytes.
+// Texts in one build never match each other: each text's fingerprints get a
+// per-text salt, and a candidate occurrence outside the key's own text counts
+// as a collision.
+//
+// Collision fallback (why a retry can start just past the false hit): let best
+// be the smallest window position whose fingerprint equals the key's, and let
+// its bytes differ from the key.  The true leftmost occurrence p* lies inside a
+// run (see level.hip), so its window was probed and fingerprints equal:
+// best <= p*, and best != p*.  Hence no true occurrence lies in [best, p*) or
+// before best, and a walk over all text positions from best + 1 that verifies
+// each fingerprint hit finds p* first.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "bt.h"
+#include "internal.hpp"
+#include "query.hpp"
+
+namespace bt {
+
+// ------------------------------------------------------------------ pool
+
+class Pool {
+ public:
+  explicit Pool(int dev) : dev_(dev) {}
+  ~Pool() {
+    trim();
+    for (auto& kv : size_) (void)hipFree(kv.first);  // leaked buffers (trees outliving everything)
+  }
+  void* get(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    const size_t want = round(bytes);
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.lower_bound(want);
+    if (it != free_.end() && it->first <= want + want / 4) {
+      void* p = it->second;
+      free_.erase(it);
+      return p;
+    }
+    void* p = nullptr;
+    int old = -1;
+    (void)hipGetDevice(&old);
+    if (old != dev_) (void)hipSetDevice(dev_);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      // release cached blocks and try once more
+      for (auto& kv : free_) {
+        (void)hipFree(kv.second);
+        held_ -= size_[kv.second];
+        size_.erase(kv.second);
+      }
+      free_.clear();
+      (void)hipGetLastError();
+      e = hipMalloc(&p, want);
+    }
+    if (old != dev_ && old >= 0) (void)hipSetDevice(old);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    size_[p] = want;
+    held_ += want;
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    free_.emplace(it->second, p);
+  }
+  void trim() {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto& kv : free_) {
+      (void)hipFree(kv.second);
+      held_ -= size_[kv.second];
+      size_.erase(kv.second);
+    }
+    free_.clear();
+  }
+  uint64_t held() const { return held_; }
+
+ private:
+  static size_t round(size_t b) {
+    if (b <= (1u << 20)) {
+      size_t r = 256;
+      while (r < b) r <<= 1;
+      return r;
+    }
+    const size_t g = 2u << 20;
+    return (b + g - 1) / g * g;
+  }
+  int dev_;
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  std::unordered_map<void*, size_t> size_;
+  uint64_t held_ = 0;
+};
+
+template <typename T>
+struct Buf {
+  std::shared_ptr<Pool> pool;
+  T* p = nullptr;
+  uint64_t n = 0;
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : pool(std::move(o.pool)), p(o.p), n(o.n) { o.p = nullptr; }
+  Buf& operator=(Buf&& o) noexcept {
+    reset();
+    pool = std::move(o.pool);
+    p = o.p;
+    n = o.n;
+    o.p = nullptr;
+    return *this;
+  }
+  ~Buf() { reset(); }
+  void reset() {
+    if (p && pool) pool->put(p);
+    p = nullptr;
+    n = 0;
+  }
+  T* release() {
+    T* q = p;
+    p = nullptr;
+    return q;
+  }
+};
+
+}  // namespace bt
+
+using namespace bt;
+
+// ------------------------------------------------------------------ context
+
+struct KStat {
+  uint64_t launches = 0;
+  double ms = 0, bytes = 0, units = 0;
+};
+
+struct PendingEv {
+  std::string name;
+  hipEvent_t a, b;
+  double bytes, units;
+  const uint64_t* d_units;
+  double bytes_per_unit;
+};
+
+struct bt_ctx {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  std::shared_ptr<Pool> pool;
+  std::string err = "no error";
+  bool profile = false;
+  std::map<std::string, KStat> stats;
+  std::vector<PendingEv> pending;
+  std::vector<hipEvent_t> ev_free;
+  uint64_t* h_small = nullptr;  // pinned host words for count read-back
+  size_t h_small_words = 0;
+  PfPow* h_pw = nullptr;        // pinned staging for the power table
+};
+
+// Device-resident storage shared by the trees of one build.
+struct Storage {
+  std::shared_ptr<Pool> pool;
+  std::vector<void*> bufs;
+  uint64_t bytes = 0;
+  ~Storage() {
+    for (void* p : bufs) pool->put(p);
+  }
+  template <typename T>
+  T* add(Buf<T>&& b, uint64_t n) {
+    bytes += n * sizeof(T);
+    T* p = b.release();
+    bufs.push_back(p);
+    return p;
+  }
+};
+
+struct TreeLevel {
+  uint64_t b = 0, c = 0, u = 0;
+  const uint64_t* words = nullptr;  // ceil(c/64)
+  const uint64_t* wrank = nullptr;  // marks before each word
+  const uint64_t* pb = nullptr;     // u
+  const uint64_t* po = nullptr;     // u
+};
+
+struct bt_tree {
+  std::shared_ptr<Storage> store;
+  int dev = 0;
+  uint64_t n = 0, b1 = 0;
+  uint32_t tau = 0, leaf = 0, h = 0;
+  std::vector<TreeLevel> lv;
+  const uint8_t* leaves = nullptr;
+  uint64_t leaf_bytes = 0;
+  QLevel* d_levels = nullptr;  // device copy of the level table for queries
+  uint64_t dev_bytes = 0;
+};
+
+// ------------------------------------------------------------------ helpers
+
+namespace {
+
+struct Fail {
+  int code;
+};
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+      throw Fail{BT_E_DEVICE};                                                         \
+    }                                                                                  \
+  } while (0)
+
+template <typename T>
+Buf<T> alloc(bt_ctx* ctx, uint64_t n) {
+  Buf<T> b;
+  b.pool = ctx->pool;
+  b.n = n;
+  b.p = static_cast<T*>(ctx->pool->get((n ? n : 1) * sizeof(T)));
+  if (!b.p) {
+    ctx->err = "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed";
+    throw Fail{BT_E_NOMEM};
+  }
+  return b;
+}
+
+uint64_t host_mul61(uint64_t a, uint64_t b) {
+  const unsigned __int128 p = (unsigned __int128)a * b;
+  uint64_t r = (uint64_t)(p & kP61Host) + (uint64_t)(p >> 61);
+  return r >= kP61Host ? r - kP61Host : r;
+}
+uint64_t host_pow61(uint64_t x, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = host_mul61(r, x);
+    x = host_mul61(x, x);
+    e >>= 1;
+  }
+  return r;
+}
+uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Base x in [2^8, 2^61 - 1) from the seed.
+uint64_t base_from_seed(uint64_t seed) {
+  uint64_t s = seed;
+  const uint64_t r = splitmix64(s);
+  return 256 + r % (kP61Host - 1 - 256);
+}
+
+void fill_pow(PfPow* pw, uint64_t x) {
+  pw->x1[0] = 1;
+  for (int k = 1; k <= 16; ++k) pw->x1[k] = host_mul61(pw->x1[k - 1], x);
+  const uint64_t x16 = pw->x1[16];
+  pw->x16[0] = 1;
+  for (int k = 1; k <= 256; ++k) pw->x16[k] = host_mul61(pw->x16[k - 1], x16);
+  const uint64_t xt = host_pow61(x, kPfTile);
+  pw->xt[0] = 1;
+  for (int k = 1; k <= 64; ++k) pw->xt[k] = host_mul61(pw->xt[k - 1], xt);
+}
+
+hipEvent_t get_event(bt_ctx* ctx) {
+  if (!ctx->ev_free.empty()) {
+    hipEvent_t e = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(ctx, hipEventCreate(&e));
+  return e;
+}
+
+// Time one launch (a callable returning hipError_t) when profiling is on.
+// `bytes`/`units` are the launch's algorithmic bytes and work units; when
+// d_units is given, the unit count is read from device memory after the next
+// synchronisation and bytes = units * bytes_per_unit.
+template <typename F>
+void timed(bt_ctx* ctx, const char* name, double bytes, double units, const uint64_t* d_units,
+           double bytes_per_unit, F&& f) {
+  if (!ctx->profile) {
+    HIPCHK(ctx, f());
+    return;
+  }
+  hipEvent_t a = get_event(ctx), b = get_event(ctx);
+  HIPCHK(ctx, hipEventRecord(a, ctx->stream));
+  HIPCHK(ctx, f());
+  HIPCHK(ctx, hipEventRecord(b, ctx->stream));
+  ctx->pending.push_back({name, a, b, bytes, units, d_units, bytes_per_unit});
+}
+
+void collect_events(bt_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      KStat& s = ctx->stats[p.name];
+      double units = p.units, bytes = p.bytes;
+      if (p.d_units) {
+        uint64_t v = 0;
+        if (hipMemcpy(&v, p.d_units, 8, hipMemcpyDeviceToHost) == hipSuccess) {
+          units = (double)v;
+          bytes = units * p.bytes_per_unit;
+        }
+      }
+      s.launches++;
+      s.ms += ms;
+      s.bytes += bytes;
+      s.units += units;
+    }
+    ctx->ev_free.push_back(p.a);
+    ctx->ev_free.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+uint64_t* small_host(bt_ctx* ctx, size_t words) {
+  if (words > ctx->h_small_words) {
+    if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+    ctx->h_small = nullptr;
+    size_t w = std::max<size_t>(words, 64);
+    HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_small, w * 8, hipHostMallocDefault));
+    ctx->h_small_words = w;
+  }
+  return ctx->h_small;
+}
+
+// Read `words` u64 from device (stream-ordered, then synchronise).
+void read_words(bt_ctx* ctx, std::vector<std::pair<const uint64_t*, uint64_t>> src,
+                std::vector<uint64_t>& out) {
+  uint64_t tot = 0;
+  for (auto& s : src) tot += s.second;
+  uint64_t* h = small_host(ctx, tot);
+  uint64_t o = 0;
+  for (auto& s : src) {
+    if (s.second)
+      HIPCHK(ctx, hipMemcpyAsync(h + o, s.first, s.second * 8, hipMemcpyDeviceToHost, ctx->stream));
+    o += s.second;
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  collect_events(ctx);
+  out.assign(h, h + tot);
+}
+
+template <typename T>
+void upload(bt_ctx* ctx, T* d, const T* h, uint64_t n) {
+  if (!n) return;
+  // stage through pinned memory so the copy is stream-ordered and async-safe
+  const uint64_t words = (n * sizeof(T) + 7) / 8;
+  uint64_t* st = small_host(ctx, words);
+  std::memcpy(st, h, n * sizeof(T));
+  HIPCHK(ctx, hipMemcpyAsync(d, st, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+}
+
+struct Plan {
+  uint64_t b1;
+  uint32_t h;
+};
+
+int plan_text(uint64_t n, const bt_params& p, Plan* out) {
+  uint64_t b = p.leaf_len;
+  uint32_t k = 0;
+  if (p.root_block_len) {
+    while (b < p.root_block_len) {
+      if (b > UINT64_MAX / p.tau) return BT_E_INVAL;
+      b *= p.tau;
+      ++k;
+    }
+    if (b != p.root_block_len) return BT_E_INVAL;
+  } else {
+    const uint64_t s = p.s_hint ? p.s_hint : 1;
+    const uint64_t lim = n / s;
+    while (b <= lim / p.tau) {
+      b *= p.tau;
+      ++k;
+    }
+  }
+  out->b1 = b;
+  out->h = k + 1;
+  return BT_OK;
+}
+
+uint64_t pow2_at_least(uint64_t v) {
+  uint64_t r = 1;
+  while (r < v) r <<= 1;
+  return r;
+}
+
+
+// Per-text, per-level bookkeeping collected on the host.
+struct TextLevelRec {
+  uint64_t b, c, u, word_off, ptr_off;
+};
+
+struct LevelBufs {
+  uint64_t* words;
+  uint64_t* wrank;
+  uint64_t* pb;
+  uint64_t* po;
+};
+
+int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& offs,
+               uint32_t sigma, const bt_params& prm, bt_tree** outs) {
+  const uint32_t T = (uint32_t)(offs.size() - 1);
+  if (prm.tau < 2 || prm.leaf_len == 0 || sigma < 1 || sigma > 256) {
+    ctx->err = "invalid parameters (tau >= 2, leaf_len >= 1, sigma in 1..256)";
+    return BT_E_INVAL;
+  }
+  for (uint32_t t = 0; t < T; ++t)
+    if (offs[t + 1] < offs[t]) {
+      ctx->err = "text offsets must be non-decreasing";
+      return BT_E_INVAL;
+    }
+  std::vector<Plan> plan(T);
+  uint32_t H = 1;
+  for (uint32_t t = 0; t < T; ++t) {
+    if (plan_text(offs[t + 1] - offs[t], prm, &plan[t]) != BT_OK) {
+      ctx->err = "root_block_len must equal leaf_len * tau^k";
+      return BT_E_INVAL;
+    }
+    H = std::max(H, plan[t].h);
+  }
+  if (T == 0) return BT_OK;
+  if (!d_base && offs[T] > offs[0]) {
+    ctx->err = "null text pointer";
+    return BT_E_INVAL;
+  }
+  for (uint32_t k = 1; k < H; ++k)
+    if ((uint64_t)prm.leaf_len > UINT64_MAX / 2 / prm.tau) {
+      ctx->err = "block length overflows";
+      return BT_E_INVAL;
+    }
+
+  HIPCHK(ctx, hipSetDevice(ctx->dev));
+  hipStream_t s = ctx->stream;
+  const uint64_t o0 = offs[0], N = offs[T] - offs[0];
+  const uint64_t x = base_from_seed(prm.hash_seed);
+  const uint64_t fpmask = (prm.debug_flags & BT_DBG_WEAK_HASH) ? 0xFFFull : ~0ull;
+  const bool has_salt = T > 1;
+
+  // ---- texts
+  std::vector<uint64_t> h_tx(3 * (size_t)T), h_n(T);
+  uint64_t sm = prm.hash_seed ^ 0x5A17ull;
+  for (uint32_t t = 0; t < T; ++t) {
+    h_tx[t] = offs[t];
+    h_tx[T + t] = offs[t + 1];
+    h_tx[2 * T + t] = has_salt ? splitmix64(sm) % kP61Host : 0;
+    h_n[t] = offs[t + 1] - offs[t];
+  }
+  Buf<uint64_t> d_tx = alloc<uint64_t>(ctx, 3 * (uint64_t)T);
+  upload(ctx, d_tx.p, h_tx.data(), 3 * (uint64_t)T);
+  TextsDev tx{T, d_tx.p, d_tx.p + T, d_tx.p + 2 * T};
+
+  // ---- distinct byte values must not exceed sigma
+  Buf<uint64_t> d_hist = alloc<uint64_t>(ctx, 256);
+  HIPCHK(ctx, launch_fill_u64(d_hist.p, 0, 256, s));
+  HIPCHK(ctx, launch_histogram(d_base + o0, N, d_hist.p, s));
+
+  // ---- step a2: prefix fingerprints of the concatenation, once
+  Buf<uint64_t> d_P = alloc<uint64_t>(ctx, N + 1);
+  Buf<PfPow> d_pw = alloc<PfPow>(ctx, 1);
+  fill_pow(ctx->h_pw, x);
+  HIPCHK(ctx, hipMemcpyAsync(d_pw.p, ctx->h_pw, sizeof(PfPow), hipMemcpyHostToDevice, s));
+  const uint64_t tiles = (N + kPfTile - 1) / kPfTile;
+  Buf<uint64_t> d_status = alloc<uint64_t>(ctx, tiles + 1);
+  Buf<uint64_t> d_ctr = alloc<uint64_t>(ctx, 1);
+  timed(ctx, "prefix_fp", (double)N + 8.0 * (double)(N + 1), (double)N, nullptr, 0, [&] {
+    return launch_prefix_fp(d_base + o0, N, d_P.p, d_pw.p, d_status.p,
+                            reinterpret_cast<uint32_t*>(d_ctr.p), s);
+  });
+  const uint64_t* P = d_P.p - o0;  // P[i] belongs to text position i; never read below o0
+
+  // ---- outputs
+  std::vector<std::vector<TextLevelRec>> rec(T);
+  auto store = std::make_shared<Storage>();
+  store->pool = ctx->pool;
+  std::vector<LevelBufs> lbufs;
+  uint8_t* leaves = nullptr;
+  std::vector<uint64_t> leaf_off(T, 0), leaf_bytes(T, 0);
+  Buf<uint64_t> d_err = alloc<uint64_t>(ctx, 1);
+  HIPCHK(ctx, launch_fill_u64(d_err.p, 0, 1, s));
+  Buf<uint64_t> wstats = alloc<uint64_t>(ctx, 2 * (uint64_t)H + 2);
+
+  // ---- level state
+  uint64_t c = 0;
+  Buf<uint64_t> st;
+  Buf<uint32_t> text;
+  std::vector<uint64_t> h_tcount(T, 0), h_tfirst(T + 1, 0);
+  Buf<uint64_t> d_tcount = alloc<uint64_t>(ctx, T + 1), d_tfirst = alloc<uint64_t>(ctx, T + 1);
+  Buf<uint64_t> scan_tmp;
+  auto scan = [&](uint64_t* a, uint64_t n) {
+    const uint64_t w = scan_tmp_words(n);
+    if (!scan_tmp.p || scan_tmp.n < w) scan_tmp = alloc<uint64_t>(ctx, std::max<uint64_t>(w, 1024));
+    HIPCHK(ctx, scan_excl_u64(a, n, scan_tmp.p, s));
+  };
+  const auto b_at = [&](uint32_t step) {
+    uint64_t b = prm.leaf_len;
+    for (uint32_t k = step + 1; k < H; ++k) b *= prm.tau;
+    return b;
+  };
+  // texts whose level 1 is the level of `step`, and their level-1 block counts
+  auto entering = [&](uint32_t step, std::vector<uint32_t>& ids, std::vector<uint64_t>& cnt,
+                      uint64_t b) {
+    ids.clear();
+    cnt.assign(T, 0);
+    for (uint32_t t = 0; t < T; ++t)
+      if (H - plan[t].h == step) {
+        ids.push_back(t);
+        cnt[t] = (h_n[t] + b - 1) / b;
+      }
+  };
+  {
+    const uint64_t b0 = b_at(0);
+    std::vector<uint32_t> ids;
+    std::vector<uint64_t> cnt;
+    entering(0, ids, cnt, b0);
+    for (uint32_t t = 0; t < T; ++t) h_tfirst[t + 1] = h_tfirst[t] + cnt[t];
+    c = h_tfirst[T];
+    h_tcount = cnt;
+    upload(ctx, d_tcount.p, h_tcount.data(), T);
+    upload(ctx, d_tfirst.p, h_tfirst.data(), T + 1);
+    st = alloc<uint64_t>(ctx, c);
+    text = alloc<uint32_t>(ctx, c);
+    Buf<uint32_t> d_ids = alloc<uint32_t>(ctx, ids.size());
+    upload(ctx, d_ids.p, ids.data(), ids.size());
+    HIPCHK(ctx, launch_write_entering(d_ids.p, (uint32_t)ids.size(), tx, b0, d_tfirst.p, st.p,
+                                      text.p, s));
+  }
+
+  for (uint32_t step = 0; step < H; ++step) {
+    const uint64_t b = b_at(step);
+    const bool leaf_step = (step == H - 1);
+
+    // runs of this level (maximal sequences of consecutive blocks of one text)
+    Buf<uint64_t> roff = alloc<uint64_t>(ctx, c + 1);
+    Buf<uint32_t> run = alloc<uint32_t>(ctx, c);
+    HIPCHK(ctx, launch_run_flags(st.p, text.p, c, b, roff.p, s));
+    scan(roff.p, c);
+    std::vector<uint64_t> rd;
+    read_words(ctx, {{roff.p + c, 1}}, rd);
+    const uint64_t R = rd[0];
+    Buf<uint64_t> rs = alloc<uint64_t>(ctx, R), re = alloc<uint64_t>(ctx, R);
+    Buf<uint32_t> rtext = alloc<uint32_t>(ctx, R);
+    HIPCHK(ctx, launch_run_table(st.p, text.p, c, b, tx, roff.p, run.p, rs.p, re.p, rtext.p, s));
+    LevelDev lv{c, b, st.p, text.p, run.p, R, rs.p, re.p, rtext.p};
+
+    if (leaf_step) {
+      Buf<uint8_t> lb = alloc<uint8_t>(ctx, c * b);
+      HIPCHK(ctx, launch_leaves(d_base, lv, tx, lb.p, s));
+      leaves = store->add(std::move(lb), c * b);
+      Buf<uint64_t> d_last = alloc<uint64_t>(ctx, T);
+      HIPCHK(ctx, launch_last_block_len(lv, tx, d_tfirst.p, d_tcount.p, d_last.p, s));
+      std::vector<uint64_t> last;
+      read_words(ctx, {{d_last.p, T}}, last);
+      for (uint32_t t = 0; t < T; ++t) {
+        leaf_off[t] = h_tfirst[t] * b;
+        leaf_bytes[t] = h_tcount[t] ? (h_tcount[t] - 1) * b + last[t] : 0;
+        rec[t].push_back({b, h_tcount[t], 0, 0, 0});
+      }
+      break;
+    }
+
+    // a text whose final block is present and short has odd-length keys
+    bool has_odd = false;
+    for (uint32_t t = 0; t < T; ++t)
+      if (h_tcount[t] && (h_n[t] % b) != 0) has_odd = true;
+
+    const uint64_t cap = std::max<uint64_t>(1024, pow2_at_least(2 * c));
+    Buf<Slot> tab = alloc<Slot>(ctx, cap);
+    Buf<uint64_t> kfp = alloc<uint64_t>(ctx, c), klen = alloc<uint64_t>(ctx, c),
+                  klm = alloc<uint64_t>(ctx, c);
+    Buf<uint32_t> kslot = alloc<uint32_t>(ctx, c);
+    Buf<uint64_t> oddb = alloc<uint64_t>(ctx, 6 * (uint64_t)T);
+    Buf<uint64_t> woff = alloc<uint64_t>(ctx, R + 1);
+    Buf<uint32_t> vlist = alloc<uint32_t>(ctx, c), vmis = alloc<uint32_t>(ctx, c),
+                  rlist = alloc<uint32_t>(ctx, c);
+    Buf<uint64_t> vbest = alloc<uint64_t>(ctx, c), rlb = alloc<uint64_t>(ctx, c),
+                  vcnt = alloc<uint64_t>(ctx, 2);
+    Buf<uint8_t> marked = alloc<uint8_t>(ctx, c);
+    VerifyBufs vb{vlist.p, vbest.p, vmis.p, rlist.p, rlb.p, vcnt.p};
+
+    PhaseArgs a{};
+    a.T = d_base;
+    a.P = P;
+    a.tx = tx;
+    a.lv = lv;
+    a.k = KeysDev{kfp.p, klen.p, kslot.p, klm.p};
+    a.odd = OddDev{oddb.p, oddb.p + T, oddb.p + 2 * T, oddb.p + 3 * T, oddb.p + 4 * T,
+                   oddb.p + 5 * T};
+    a.tab = TableDev{tab.p, cap - 1};
+    a.x = x;
+    a.fpmask = fpmask;
+    a.marked = marked.p;
+
+    auto run_phase = [&](int phase) {
+      a.phase = phase;
+      a.Lmain = phase == 1 ? 2 * b : b;
+      a.xLmain = host_pow61(x, a.Lmain);
+      HIPCHK(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(tab.p), ~0ull, 2 * cap, s));
+      HIPCHK(ctx, launch_fill_u64(oddb.p, 0, 6 * (uint64_t)T, s));
+      HIPCHK(ctx, launch_fill_u64(vcnt.p, 0, 2, s));
+      HIPCHK(ctx, launch_keys(a, s));
+      HIPCHK(ctx, launch_window_counts(a, woff.p, s));
+      scan(woff.p, R);
+      uint64_t* wst = wstats.p + 2 * step + (phase - 1);
+      HIPCHK(ctx, hipMemcpyAsync(wst, woff.p + R, 8, hipMemcpyDeviceToDevice, s));
+      timed(ctx, "probe_scan", 0, 0, wst, 16.0, [&] {
+        return launch_probe_scan(a, woff.p, has_odd, has_salt, c * b, s);
+      });
+      HIPCHK(ctx, launch_resolve(a, vb, s));
+      timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });
+      HIPCHK(ctx, launch_finish(a, vb, s));
+      HIPCHK(ctx, launch_retry(a, vb, s));
+    };
+
+    // ---- phase 1: pairs (a3, a4) and marks (a5)
+    run_phase(1);
+    HIPCHK(ctx, launch_mark(a, marked.p, s));
+
+    // ---- phase 2: unmarked blocks (a6) and pointers (a7)
+    Buf<uint64_t> uoff = alloc<uint64_t>(ctx, c + 1);
+    HIPCHK(ctx, launch_unmarked_counts(marked.p, c, uoff.p, s));
+    scan(uoff.p, c);
+    run_phase(2);
+    Buf<uint64_t> pb = alloc<uint64_t>(ctx, c), po = alloc<uint64_t>(ctx, c);
+    HIPCHK(ctx, launch_pointers(a, marked.p, uoff.p, d_tfirst.p, pb.p, po.p,
+                                reinterpret_cast<uint32_t*>(d_err.p), s));
+
+    // ---- split (a8): per-text counts of the next level
+    const uint64_t bn = b / prm.tau;
+    Buf<uint64_t> cs = alloc<uint64_t>(ctx, c + 1);
+    HIPCHK(ctx, launch_child_counts(lv, tx, marked.p, bn, cs.p, s));
+    scan(cs.p, c);
+    std::vector<uint32_t> ids;
+    std::vector<uint64_t> ent;
+    entering(step + 1, ids, ent, bn);
+    Buf<uint64_t> d_ent = alloc<uint64_t>(ctx, T);
+    upload(ctx, d_ent.p, ent.data(), T);
+    Buf<uint64_t> ntcount = alloc<uint64_t>(ctx, T + 1), ntfirst = alloc<uint64_t>(ctx, T + 1);
+    HIPCHK(ctx, launch_text_counts(T, cs.p, d_tfirst.p, d_tcount.p, d_ent.p, ntcount.p, s));
+    HIPCHK(ctx, hipMemcpyAsync(ntfirst.p, ntcount.p, T * 8, hipMemcpyDeviceToDevice, s));
+    scan(ntfirst.p, T);
+    Buf<uint64_t> tu = alloc<uint64_t>(ctx, T);
+    HIPCHK(ctx, launch_text_deltas(uoff.p, d_tfirst.p, d_tcount.p, T, tu.p, s));
+    std::vector<uint64_t> got;
+    read_words(ctx, {{ntcount.p, T}, {tu.p, T}, {uoff.p + c, 1}}, got);
+    std::vector<uint64_t> h_ntcount(got.begin(), got.begin() + T);
+    std::vector<uint64_t> h_tu(got.begin() + T, got.begin() + 2 * T);
+    const uint64_t u = got[2 * T];
+
+    // ---- outputs of this level: marks (word range per text) and pointers
+    std::vector<uint64_t> h_woff(T + 1, 0), h_poff(T + 1, 0);
+    for (uint32_t t = 0; t < T; ++t) {
+      h_woff[t + 1] = h_woff[t] + (h_tcount[t] + 63) / 64;
+      h_poff[t + 1] = h_poff[t] + h_tu[t];
+    }
+    const uint64_t nwords = h_woff[T];
+    Buf<uint64_t> d_woff = alloc<uint64_t>(ctx, T + 1);
+    upload(ctx, d_woff.p, h_woff.data(), T + 1);
+    Buf<uint64_t> words = alloc<uint64_t>(ctx, nwords), wrank = alloc<uint64_t>(ctx, nwords + 1);
+    Buf<uint64_t> wtmp = alloc<uint64_t>(ctx, nwords + 1);
+    HIPCHK(ctx, launch_pack_marks(marked.p, T, d_tfirst.p, d_tcount.p, d_woff.p, nwords, words.p, s));
+    HIPCHK(ctx, launch_word_pop(words.p, nwords, wtmp.p, s));
+    scan(wtmp.p, nwords);
+    HIPCHK(ctx, launch_word_rank(wtmp.p, T, d_woff.p, nwords, wrank.p, s));
+    Buf<uint64_t> spb = alloc<uint64_t>(ctx, u), spo = alloc<uint64_t>(ctx, u);
+    if (u) {
+      HIPCHK(ctx, hipMemcpyAsync(spb.p, pb.p, u * 8, hipMemcpyDeviceToDevice, s));
+      HIPCHK(ctx, hipMemcpyAsync(spo.p, po.p, u * 8, hipMemcpyDeviceToDevice, s));
+    }
+    lbufs.push_back({store->add(std::move(words), nwords), store->add(std::move(wrank), nwords + 1),
+                     store->add(std::move(spb), u), store->add(std::move(spo), u)});
+    for (uint32_t t = 0; t < T; ++t)
+      if (H - plan[t].h <= step) rec[t].push_back({b, h_tcount[t], h_tu[t], h_woff[t], h_poff[t]});
+
+    // ---- next level's blocks
+    uint64_t cn = 0;
+    for (uint32_t t = 0; t < T; ++t) cn += h_ntcount[t];
+    Buf<uint64_t> nst = alloc<uint64_t>(ctx, cn);
+    Buf<uint32_t> ntext = alloc<uint32_t>(ctx, cn);
+    HIPCHK(ctx, launch_write_children(lv, tx, marked.p, bn, prm.tau, cs.p, d_tfirst.p, ntfirst.p,
+                                      nst.p, ntext.p, s));
+    Buf<uint32_t> d_ids = alloc<uint32_t>(ctx, ids.size());
+    upload(ctx, d_ids.p, ids.data(), ids.size());
+    HIPCHK(ctx, launch_write_entering(d_ids.p, (uint32_t)ids.size(), tx, bn, ntfirst.p, nst.p,
+                                      ntext.p, s));
+    HIPCHK(ctx, hipMemcpyAsync(d_tcount.p, ntcount.p, T * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(d_tfirst.p, ntfirst.p, (T + 1) * 8, hipMemcpyDeviceToDevice, s));
+    h_tcount = h_ntcount;
+    for (uint32_t t = 0; t < T; ++t) h_tfirst[t + 1] = h_tfirst[t] + h_tcount[t];
+    st = std::move(nst);
+    text = std::move(ntext);
+    c = cn;
+  }
+
+  std::vector<uint64_t> fin;
+  read_words(ctx, {{d_err.p, 1}, {d_hist.p, 256}}, fin);
+  if (fin[0]) {
+    ctx->err = "device check failed: a pointer does not target a marked block or pair";
+    return BT_E_INTERNAL;
+  }
+  uint32_t distinct = 0;
+  for (int ch = 0; ch < 256; ++ch) distinct += fin[1 + ch] != 0;
+  if (distinct > sigma) {
+    ctx->err = "the text has " + std::to_string(distinct) + " distinct byte values, more than sigma";
+    return BT_E_INVAL;
+  }
+
+  // ---- trees
+  for (uint32_t t = 0; t < T; ++t) {
+    bt_tree* tr = new bt_tree;
+    tr->store = store;
+    tr->dev = ctx->dev;
+    tr->n = h_n[t];
+    tr->b1 = plan[t].b1;
+    tr->tau = prm.tau;
+    tr->leaf = prm.leaf_len;
+    tr->h = plan[t].h;
+    const uint32_t e = H - plan[t].h;
+    for (uint32_t l = 0; l + 1 < plan[t].h; ++l) {
+      const TextLevelRec& r = rec[t][l];
+      const LevelBufs& L = lbufs[e + l];
+      TreeLevel tl;
+      tl.b = r.b;
+      tl.c = r.c;
+      tl.u = r.u;
+      tl.words = L.words + r.word_off;
+      tl.wrank = L.wrank + r.word_off;
+      tl.pb = L.pb + r.ptr_off;
+      tl.po = L.po + r.ptr_off;
+      tr->lv.push_back(tl);
+    }
+    TreeLevel leafl;
+    leafl.b = rec[t].back().b;
+    leafl.c = rec[t].back().c;
+    tr->lv.push_back(leafl);
+    tr->leaves = leaves + leaf_off[t];
+    tr->leaf_bytes = leaf_bytes[t];
+    tr->dev_bytes = store->bytes / T;
+    outs[t] = tr;
+  }
+  return BT_OK;
+}
+
+int guarded(bt_ctx* ctx, const std::function<int()>& f) {
+  try {
+    return f();
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return BT_E_NOMEM;
+  }
+}
+
+// Upload the level table of a tree for the query kernels (once).
+void ensure_qtree(bt_ctx* ctx, const bt_tree* ct) {
+  bt_tree* t = const_cast<bt_tree*>(ct);
+  if (t->d_levels) return;
+  std::vector<QLevel> h(t->h);
+  for (uint32_t l = 0; l < t->h; ++l) {
+    const TreeLevel& L = t->lv[l];
+    h[l] = QLevel{L.b, L.c, L.words, L.wrank, L.pb, L.po, nullptr, nullptr};
+  }
+  Buf<QLevel> d = alloc<QLevel>(ctx, t->h);
+  QLevel* staging = nullptr;
+  HIPCHK(ctx, hipHostMalloc((void**)&staging, sizeof(QLevel) * t->h, hipHostMallocDefault));
+  std::memcpy(staging, h.data(), sizeof(QLevel) * t->h);
+  hipError_t e = hipMemcpyAsync(d.p, staging, sizeof(QLevel) * t->h, hipMemcpyHostToDevice,
+                                ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipHostFree(staging);
+  HIPCHK(ctx, e);
+  t->d_levels = t->store->add(std::move(d), t->h);
+}
+
+QTree qtree_of(const bt_tree* t) {
+  QTree q{};
+  q.lv = t->d_levels;
+  q.h = t->h;
+  q.tau = t->tau;
+  q.n = t->n;
+  q.leaves = t->leaves;
+  q.leaf_len = t->leaf;
+  return q;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int bt_ctx_create(int device, void* hip_stream, bt_ctx** out) {
+  if (!out) return BT_E_INVAL;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BT_E_INVAL;
+  if (hipSetDevice(device) != hipSuccess) return BT_E_DEVICE;
+  bt_ctx* c = new (std::nothrow) bt_ctx;
+  if (!c) return BT_E_NOMEM;
+  c->dev = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->pool = std::make_shared<Pool>(device);
+  if (hipHostMalloc((void**)&c->h_pw, sizeof(PfPow), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return BT_E_NOMEM;
+  }
+  *out = c;
+  return BT_OK;
+}
+
+void bt_ctx_destroy(bt_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->dev);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+  if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+  if (ctx->h_pw) (void)hipHostFree(ctx->h_pw);
+  ctx->pool->trim();
+  delete ctx;
+}
+
+const char* bt_ctx_last_error(const bt_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+int bt_ctx_trim(bt_ctx* ctx) {
+  if (!ctx) return BT_E_INVAL;
+  ctx->pool->trim();
+  return BT_OK;
+}
+
+int bt_ctx_profile(bt_ctx* ctx, int enable) {
+  if (!ctx) return BT_E_INVAL;
+  ctx->profile = enable != 0;
+  return BT_OK;
+}
+
+int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches, double* total_ms,
+                        double* bytes, double* units) {
+  if (!ctx || !name) return BT_E_INVAL;
+  auto it = ctx->stats.find(name);
+  KStat z;
+  const KStat& k = it == ctx->stats.end() ? z : it->second;
+  if (launches) *launches = k.launches;
+  if (total_ms) *total_ms = k.ms;
+  if (bytes) *bytes = k.bytes;
+  if (units) *units = k.units;
+  return BT_OK;
+}
+
+int bt_ctx_reset_stats(bt_ctx* ctx) {
+  if (!ctx) return BT_E_INVAL;
+  ctx->stats.clear();
+  return BT_OK;
+}
+
+int bt_prefix_fingerprints(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
+                           uint64_t* d_P) {
+  if (!ctx) return BT_E_INVAL;
+  if (x == 0 || x >= kP61Host || !d_P || (!d_text && n)) {
+    ctx->err = "bt_prefix_fingerprints: need 1 <= x < 2^61-1 and valid pointers";
+    return BT_E_INVAL;
+  }
+  return guarded(ctx, [&] {
+    HIPCHK(ctx, hipSetDevice(ctx->dev));
+    Buf<PfPow> d_pw = alloc<PfPow>(ctx, 1);
+    fill_pow(ctx->h_pw, x);
+    HIPCHK(ctx, hipMemcpyAsync(d_pw.p, ctx->h_pw, sizeof(PfPow), hipMemcpyHostToDevice,
+                               ctx->stream));
+    const uint64_t tiles = (n + kPfTile - 1) / kPfTile;
+    Buf<uint64_t> d_status = alloc<uint64_t>(ctx, tiles + 1);
+    Buf<uint64_t> d_ctr = alloc<uint64_t>(ctx, 1);
+    timed(ctx, "prefix_fp", (double)n + 8.0 * (double)(n + 1), (double)n, nullptr, 0, [&] {
+      return launch_prefix_fp(d_text, n, d_P, d_pw.p, d_status.p,
+                              reinterpret_cast<uint32_t*>(d_ctr.p), ctx->stream);
+    });
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    collect_events(ctx);
+    return BT_OK;
+  });
+}
+
+int bt_build_ex(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
+                const bt_params* params, bt_tree** out) {
+  if (!ctx) return BT_E_INVAL;
+  if (!params || !out) {
+    ctx->err = "null params or output";
+    return BT_E_INVAL;
+  }
+  *out = nullptr;
+  std::vector<uint64_t> offs{0, n};
+  return guarded(ctx, [&] { return build_many(ctx, d_text, offs, sigma, *params, out); });
+}
+
+int bt_build(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma, uint32_t tau,
+             uint32_t leaf_len, bt_tree** out) {
+  bt_params p{};
+  p.tau = tau;
+  p.leaf_len = leaf_len;
+  p.s_hint = 1;
+  p.hash_seed = 0x0B10C7EEull;
+  return bt_build_ex(ctx, d_text, n, sigma, &p, out);
+}
+
+int bt_build_batch(bt_ctx* ctx, const uint8_t* d_concat, const uint64_t* h_offsets, uint32_t num,
+                   uint32_t sigma, const bt_params* params, bt_tree** outs) {
+  if (!ctx) return BT_E_INVAL;
+  if (!params || (num && (!h_offsets || !outs))) {
+    ctx->err = "null params, offsets or outputs";
+    return BT_E_INVAL;
+  }
+  std::vector<uint64_t> offs(h_offsets, h_offsets + (num ? num + 1 : 0));
+  if (num == 0) return BT_OK;
+  for (uint32_t i = 0; i < num; ++i) outs[i] = nullptr;
+  return guarded(ctx, [&] { return build_many(ctx, d_concat, offs, sigma, *params, outs); });
+}
+
+int bt_tree_info(const bt_tree* t, uint64_t* n, uint32_t* h, uint64_t* b1) {
+  if (!t) return BT_E_INVAL;
+  if (n) *n = t->n;
+  if (h) *h = t->h;
+  if (b1) *b1 = t->b1;
+  return BT_OK;
+}
+
+int bt_level_info(const bt_tree* t, uint32_t level, uint64_t* b, uint64_t* c, uint64_t* u) {
+  if (!t || level < 1 || level > t->h) return BT_E_INVAL;
+  const TreeLevel& L = t->lv[level - 1];
+  if (b) *b = L.b;
+  if (c) *c = L.c;
+  if (u) *u = L.u;
+  return BT_OK;
+}
+
+int bt_level_copy(const bt_tree* t, uint32_t level, uint64_t* marked_words, uint64_t* ptr_block,
+                  uint64_t* ptr_off) {
+  if (!t || level < 1 || level >= t->h) return BT_E_INVAL;
+  const TreeLevel& L = t->lv[level - 1];
+  if (hipSetDevice(t->dev) != hipSuccess) return BT_E_DEVICE;
+  const uint64_t nw = (L.c + 63) / 64;
+  if (marked_words && nw && hipMemcpy(marked_words, L.words, nw * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return BT_E_DEVICE;
+  if (ptr_block && L.u && hipMemcpy(ptr_block, L.pb, L.u * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return BT_E_DEVICE;
+  if (ptr_off && L.u && hipMemcpy(ptr_off, L.po, L.u * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return BT_E_DEVICE;
+  return BT_OK;
+}
+
+int bt_leaves_size(const bt_tree* t, uint64_t* bytes) {
+  if (!t || !bytes) return BT_E_INVAL;
+  *bytes = t->leaf_bytes;
+  return BT_OK;
+}
+
+int bt_leaves_copy(const bt_tree* t, uint8_t* dst) {
+  if (!t || (!dst && t->leaf_bytes)) return BT_E_INVAL;
+  if (!t->leaf_bytes) return BT_OK;
+  if (hipSetDevice(t->dev) != hipSuccess) return BT_E_DEVICE;
+  return hipMemcpy(dst, t->leaves, t->leaf_bytes, hipMemcpyDeviceToHost) == hipSuccess ? BT_OK
+                                                                                   : BT_E_DEVICE;
+}
+
+int bt_serialize(const bt_tree* t, uint8_t* dst, uint64_t cap, uint64_t* written) {
+  if (!t || !written) return BT_E_INVAL;
+  std::vector<uint8_t> out;
+  auto put = [&](const void* p, size_t k) {
+    const uint8_t* q = static_cast<const uint8_t*>(p);
+    out.insert(out.end(), q, q + k);
+  };
+  const uint32_t zero = 0;
+  put("BTv1", 4);
+  put(&t->n, 8);
+  put(&t->tau, 4);
+  put(&t->leaf, 4);
+  put(&t->b1, 8);
+  put(&t->h, 4);
+  put(&zero, 4);
+  for (uint32_t l = 1; l < t->h; ++l) {
+    const TreeLevel& L = t->lv[l - 1];
+    std::vector<uint64_t> w((L.c + 63) / 64), pb(L.u), po(L.u);
+    int rc = bt_level_copy(t, l, w.data(), pb.data(), po.data());
+    if (rc) return rc;
+    put(&L.b, 8);
+    put(&L.c, 8);
+    put(w.data(), w.size() * 8);
+    put(&L.u, 8);
+    put(pb.data(), pb.size() * 8);
+    put(po.data(), po.size() * 8);
+  }
+  const TreeLevel& Lh = t->lv[t->h - 1];
+  put(&Lh.b, 8);
+  put(&Lh.c, 8);
+  put(&t->leaf_bytes, 8);
+  std::vector<uint8_t> lb(t->leaf_bytes);
+  int rc = bt_leaves_copy(t, lb.data());
+  if (rc) return rc;
+  put(lb.data(), lb.size());
+  const uint64_t zeros = 0;
+  put(&zeros, (8 - (t->leaf_bytes & 7)) & 7);
+  *written = out.size();
+  if (!dst) return BT_OK;
+  if (cap < out.size()) return BT_E_INVAL;
+  std::memcpy(dst, out.data(), out.size());
+  return BT_OK;
+}
+
+int bt_access(bt_ctx* ctx, const bt_tree* t, const uint64_t* d_pos, uint64_t m, uint8_t* d_out) {
+  if (!ctx || !t || (m && (!d_pos || !d_out))) return BT_E_INVAL;
+  return guarded(ctx, [&] {
+    HIPCHK(ctx, hipSetDevice(ctx->dev));
+    ensure_qtree(ctx, t);
+    Buf<uint64_t> bad = alloc<uint64_t>(ctx, 1);
+    HIPCHK(ctx, launch_fill_u64(bad.p, 0, 1, ctx->stream));
+    if (t->n == 0) {
+      HIPCHK(ctx, launch_fill_u8(d_out, 0, m, ctx->stream));
+      HIPCHK(ctx, launch_fill_u64(bad.p, m ? 1 : 0, 1, ctx->stream));
+    } else {
+      HIPCHK(ctx, launch_access(qtree_of(t), d_pos, m, d_out, reinterpret_cast<uint32_t*>(bad.p),
+                                ctx->stream));
+    }
+    std::vector<uint64_t> r;
+    read_words(ctx, {{bad.p, 1}}, r);
+    if (r[0]) {
+      ctx->err = "bt_access: position out of range";
+      return BT_E_INVAL;
+    }
+    return BT_OK;
+  });
+}
+
+int bt_rank(bt_ctx* ctx, const bt_tree* t, const uint8_t* d_c, const uint64_t* d_pos, uint64_t m,
+            uint64_t* d_out) {
+  (void)d_c; (void)d_pos; (void)m; (void)d_out; (void)t;
+  if (ctx) ctx->err = "bt_rank: not available in this build";
+  return BT_E_INVAL;
+}
+
+int bt_select(bt_ctx* ctx, const bt_tree* t, const uint8_t* d_c, const uint64_t* d_k, uint64_t m,
+              uint64_t* d_out) {
+  (void)d_c; (void)d_k; (void)m; (void)d_out; (void)t;
+  if (ctx) ctx->err = "bt_select: not available in this build";
+  return BT_E_INVAL;
+}
+
+int bt_tree_device_bytes(const bt_tree* t, uint64_t* bytes) {
+  if (!t || !bytes) return BT_E_INVAL;
+  *bytes = t->dev_bytes;
+  return BT_OK;
+}
+
+void bt_tree_free(bt_tree* t) { delete t; }
+
+const char* bt_strerror(int status) {
+  switch (status) {
+    case BT_OK: return "ok";
+    case BT_E_INVAL: return "invalid argument";
+    case BT_E_NOMEM: return "out of memory";
+    case BT_E_DEVICE: return "HIP runtime error";
+    case BT_E_INTERNAL: return "internal consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Device-side helpers shared by the HIP kernels of libbt (gfx950 only).
+//
+// Arithmetic is exact integer arithmetic modulo the Mersenne prime
+// q = 2^61 - 1, which is the Karp-Rabin modulus of this library (Section 2 of
+// the paper allows any q in Theta(n^c); 2^61-1 keeps collision odds per
+// comparison below L / 2^61 and reduces with shifts and adds).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bt {
+
+constexpr uint64_t kP61 = 0x1FFFFFFFFFFFFFFFull;
+constexpr uint64_t kEmpty = ~0ull;          // empty hash slot / "no position"
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;    // block has no key in this phase
+constexpr uint32_t kOddKey = 0xFFFFFFFEu;   // key of non-standard length (text tail)
+constexpr uint64_t kWeakMask = 0xFFFull;    // BT_DBG_WEAK_HASH truncation
+
+// a * b mod (2^61 - 1) for a, b < 2^61 - 1.  The 122-bit product is split at
+// bit 61 and folded once (2^61 = 1 mod q); the sum is below 2q.
+__device__ __forceinline__ uint64_t mul61(uint64_t a, uint64_t b) {
+  const uint64_t lo = a * b;
+  const uint64_t hi = __umul64hi(a, b);
+  const uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
+  return r >= kP61 ? r - kP61 : r;
+}
+__device__ __forceinline__ uint64_t add61(uint64_t a, uint64_t b) {
+  const uint64_t r = a + b;
+  return r >= kP61 ? r - kP61 : r;
+}
+__device__ __forceinline__ uint64_t sub61(uint64_t a, uint64_t b) {
+  return a >= b ? a - b : a + kP61 - b;
+}
+__device__ inline uint64_t pow61(uint64_t x, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = mul61(r, x);
+    x = mul61(x, x);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Fingerprint of T[i .. i+L) from prefix fingerprints: P[i+L] - P[i] * x^L.
+__device__ __forceinline__ uint64_t window_fp(const uint64_t* __restrict__ P, uint64_t i,
+                                              uint64_t L, uint64_t xL) {
+  return sub61(P[i + L], mul61(P[i], xL));
+}
+
+// Final key of a window: add the per-text salt (batched builds keep texts
+// apart), then apply the debug truncation mask (all ones normally).
+__device__ __forceinline__ uint64_t finish_fp(uint64_t fp, uint64_t salt, uint64_t mask) {
+  return add61(fp, salt) & mask;
+}
+
+// Home slot of a fingerprint in a power-of-two open-addressing table.
+__device__ __forceinline__ uint64_t slot_of(uint64_t fp, uint64_t mask) {
+  return (fp ^ (fp >> 29) ^ (fp >> 47)) & mask;
+}
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Sum of a 64-lane wave under add61.
+__device__ __forceinline__ uint64_t wave_sum61(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = add61(v, __shfl_xor(v, d));
+  return v;
+}
+
+// 16 bytes from an arbitrary byte address (unaligned global load).
+__device__ __forceinline__ uint4 load16(const uint8_t* p) {
+  uint4 v;
+  __builtin_memcpy(&v, p, 16);
+  return v;
+}
+
+}  // namespace bt

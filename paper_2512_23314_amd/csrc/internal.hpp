@@ -1,0 +1,171 @@
+// Internal interface between the host orchestration (bt_host.cpp) and the HIP
+// kernels (*.hip).  Plain structs of device pointers and sizes; every launch
+// wrapper enqueues on the given stream and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bt {
+
+// ---- prefix fingerprints (step a2) ----
+constexpr int kPfThreads = 256;
+constexpr int kPfBytes = 16;                       // bytes per thread
+constexpr uint64_t kPfTile = kPfThreads * kPfBytes;  // bytes per tile
+
+// Powers of the base used by the prefix scan, computed on the host.
+struct PfPow {
+  uint64_t x1[17];    // x^k,          k = 0..16
+  uint64_t x16[257];  // x^(16 k),     k = 0..256
+  uint64_t xt[65];    // x^(tile k),   k = 0..64
+};
+
+// status: ceil(n / tile) words, zeroed by the wrapper; ctr: one word.
+hipError_t launch_prefix_fp(const uint8_t* T, uint64_t n, uint64_t* P, const PfPow* pw,
+                            uint64_t* status, uint32_t* ctr, hipStream_t s);
+
+// ---- level data (device arrays; positions are offsets into the text base) ----
+struct TextsDev {
+  uint32_t T;              // number of texts
+  const uint64_t* tstart;  // [T]
+  const uint64_t* tend;    // [T]
+  const uint64_t* tsalt;   // [T]
+};
+
+struct LevelDev {
+  uint64_t c;              // blocks
+  uint64_t b;              // block length
+  const uint64_t* st;      // [c] block starts, increasing
+  const uint32_t* text;    // [c] text of each block
+  const uint32_t* run;     // [c] run of each block
+  uint64_t R;              // runs (maximal sequences of consecutive blocks)
+  const uint64_t* rs;      // [R] run start
+  const uint64_t* re;      // [R] run end
+  const uint32_t* rtext;   // [R]
+};
+
+// Keys of one phase.  Keys are indexed by block: block j carries the key of
+// the pair (j, j+1) in phase 1 and of its own content in phase 2.
+struct KeysDev {
+  uint64_t* fp;     // [c]
+  uint64_t* len;    // [c]
+  uint32_t* slot;   // [c] table slot, kNoKey or kOddKey
+  uint64_t* lm;     // [c] leftmost occurrence (result)
+};
+
+// Keys whose length differs from the phase's main length (at most one per
+// text: the one ending at the text's end).  Indexed by text.
+struct OddDev {
+  uint64_t* L;      // [T] 0 = none
+  uint64_t* xp;     // [T] x^L
+  uint64_t* fp;     // [T]
+  uint64_t* best;   // [T] atomicMin target, initialised to the key's position
+  uint64_t* pos;    // [T]
+  uint64_t* nkeys;  // [T] keys of this text in this phase (main + odd)
+};
+
+struct Slot {
+  uint64_t fp;
+  uint64_t best;  // smallest position with this fingerprint seen so far
+};
+
+struct TableDev {
+  Slot* slots;
+  uint64_t mask;  // capacity - 1
+};
+
+struct PhaseArgs {
+  const uint8_t* T;
+  const uint64_t* P;
+  TextsDev tx;
+  LevelDev lv;
+  KeysDev k;
+  OddDev odd;
+  TableDev tab;
+  uint64_t Lmain;   // standard key length (2b in phase 1, b in phase 2)
+  uint64_t xLmain;  // x^Lmain
+  uint64_t x;
+  uint64_t fpmask;  // all ones, or kWeakMask
+  const uint8_t* marked;  // phase 2: skip marked blocks
+  int phase;        // 1 or 2
+};
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s);
+
+// Exclusive scan of a[0..n) in place; a[n] receives the total.  tmp must hold
+// scan_tmp_words(n) words.
+uint64_t scan_tmp_words(uint64_t n);
+hipError_t scan_excl_u64(uint64_t* a, uint64_t n, uint64_t* tmp, hipStream_t s);
+
+// Phase kernels (steps a3-a7).
+hipError_t launch_keys(const PhaseArgs& a, hipStream_t s);
+// Per-run window counts into woff[0..R) (then scanned by the caller).
+hipError_t launch_window_counts(const PhaseArgs& a, uint64_t* woff, hipStream_t s);
+// The sliding-window probe.  grid_hint bounds the grid.
+hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
+                             bool has_salt, uint64_t max_windows, hipStream_t s);
+
+struct VerifyBufs {
+  uint32_t* vlist;  // [c]
+  uint64_t* vbest;  // [c]
+  uint32_t* vmis;   // [c]
+  uint32_t* rlist;  // [c]
+  uint64_t* rlb;    // [c]
+  uint64_t* counts; // [2]: verify count, retry count
+};
+hipError_t launch_resolve(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s);
+hipError_t launch_verify(const PhaseArgs& a, const VerifyBufs& v, uint64_t max_len,
+                         hipStream_t s);
+hipError_t launch_finish(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s);
+hipError_t launch_retry(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s);
+
+// Step a5: marks from the phase-1 results (plus the isolated-block rule).
+hipError_t launch_mark(const PhaseArgs& a, uint8_t* marked, hipStream_t s);
+// Unmarked-prefix counts: cnt[j] = !marked[j].
+hipError_t launch_unmarked_counts(const uint8_t* marked, uint64_t c, uint64_t* cnt,
+                                  hipStream_t s);
+// Step a7: pointers.  uoff = exclusive scan of unmarked counts; tfirst = first
+// block of each text on this level.  err receives 1 on a broken invariant.
+hipError_t launch_pointers(const PhaseArgs& a, const uint8_t* marked, const uint64_t* uoff,
+                           const uint64_t* tfirst, uint64_t* ptr_block, uint64_t* ptr_off,
+                           uint32_t* err, hipStream_t s);
+
+// Step a8: split.
+hipError_t launch_child_counts(const LevelDev& lv, const TextsDev& tx, const uint8_t* marked,
+                               uint64_t bn, uint64_t* cnt, hipStream_t s);
+// Per-text next-level counts: children (from the scanned child counts) plus
+// entering blocks.  tcount/tfirst describe the current level.
+hipError_t launch_text_counts(uint32_t T, const uint64_t* cs, const uint64_t* tfirst,
+                              const uint64_t* tcount, const uint64_t* enter,
+                              uint64_t* ncount, hipStream_t s);
+hipError_t launch_write_children(const LevelDev& lv, const TextsDev& tx, const uint8_t* marked,
+                                 uint64_t bn, uint32_t tau, const uint64_t* cs,
+                                 const uint64_t* tfirst, const uint64_t* ntfirst,
+                                 uint64_t* nst, uint32_t* ntext, hipStream_t s);
+hipError_t launch_write_entering(const uint32_t* ids, uint32_t E, const TextsDev& tx,
+                                 uint64_t bn, const uint64_t* ntfirst, uint64_t* nst,
+                                 uint32_t* ntext, hipStream_t s);
+// Runs of a level: flags into rflag (c entries, then scanned by the caller).
+hipError_t launch_run_flags(const uint64_t* st, const uint32_t* text, uint64_t c, uint64_t b,
+                            uint64_t* rflag, hipStream_t s);
+// From the scanned flags (exclusive; roff[c] = R): run ids and the run table.
+hipError_t launch_run_table(const uint64_t* st, const uint32_t* text, uint64_t c, uint64_t b,
+                            const TextsDev& tx, const uint64_t* roff, uint32_t* run,
+                            uint64_t* rs, uint64_t* re, uint32_t* rtext, hipStream_t s);
+
+// Outputs.
+// Pack marks of each text into its own word range: words of text t start at
+// woff[t]; tfirst/tcount give its blocks.
+hipError_t launch_pack_marks(const uint8_t* marked, uint32_t T, const uint64_t* tfirst,
+                             const uint64_t* tcount, const uint64_t* woff, uint64_t nwords,
+                             uint64_t* words, hipStream_t s);
+// Leaves: bytes of every block of the last level, block after block.
+hipError_t launch_leaves(const uint8_t* T, const LevelDev& lv, const TextsDev& tx,
+                         uint8_t* out, hipStream_t s);
+
+// Per-level counts the host reads after each level: stored in a small device
+// array; see bt_host.cpp for the layout.
+hipError_t launch_text_firsts(const uint64_t* tcount_scanned, uint32_t T, hipStream_t s);
+
+}  // namespace bt

@@ -1,0 +1,583 @@
+// One level of block-tree construction (Section 4.1): both phases, the split
+// into the next level, and the level's outputs.
+//
+// Phase 1 (a3-a5): the key of every pair of consecutive blocks goes into an
+// open-addressing table; every window of length 2b inside a run of consecutive
+// blocks is fingerprinted from the prefix fingerprints and probed; a hit at
+// position i lowers the slot's smallest position with atomicMin.  Phase 2
+// (a6-a7) does the same for unmarked blocks with windows of length b.  Keys
+// with the same fingerprint share a slot, so a slot's minimum is the leftmost
+// position with that fingerprint; each key then compares its bytes with that
+// position (a4 verification).  A mismatch -- a fingerprint collision -- sends
+// the key to an exact fallback scan that walks the text from just past the
+// false hit and verifies every further hit, so the result is the leftmost
+// occurrence whatever the hash does.
+//
+// Only windows inside runs are scanned: for tau >= 2 the leftmost occurrence in
+// T of any string no longer than b_{l-1} lies inside a run of level l (it is
+// covered by two consecutive marked blocks of level l-1, whose children are
+// present), so "leftmost on this level" and "leftmost in T" coincide.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bt {
+
+static unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 8192) {
+  uint64_t g = (n + threads - 1) / threads;
+  if (g == 0) g = 1;
+  return (unsigned)(g < cap ? g : cap);
+}
+
+#define GRID_STRIDE(i, n)                                                        \
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+       i += (uint64_t)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ uint64_t block_len(const LevelDev& lv, const TextsDev& tx,
+                                              uint64_t j) {
+  const uint64_t st = lv.st[j];
+  const uint64_t te = tx.tend[lv.text[j]];
+  return te - st < lv.b ? te - st : lv.b;
+}
+
+// ---------------------------------------------------------------- keys (a3, a6)
+
+__global__ void k_keys(PhaseArgs a) {
+  const LevelDev lv = a.lv;
+  GRID_STRIDE(j, lv.c) {
+    const uint32_t t = lv.text[j];
+    const uint64_t st = lv.st[j];
+    const uint64_t len = block_len(lv, a.tx, j);
+    uint64_t L = 0;
+    bool valid;
+    if (a.phase == 1) {
+      valid = (j + 1 < lv.c) && lv.run[j + 1] == lv.run[j];
+      if (valid) L = len + block_len(lv, a.tx, j + 1);
+    } else {
+      valid = !a.marked[j];
+      L = len;
+    }
+    if (!valid) {
+      a.k.slot[j] = kNoKey;
+      continue;
+    }
+    const uint64_t xp = (L == a.Lmain) ? a.xLmain : pow61(a.x, L);
+    const uint64_t fp = finish_fp(window_fp(a.P, st, L, xp), a.tx.tsalt[t], a.fpmask);
+    a.k.fp[j] = fp;
+    a.k.len[j] = L;
+    a.odd.nkeys[t] = 1;
+    if (L == a.Lmain) {
+      uint64_t h = slot_of(fp, a.tab.mask);
+      while (true) {
+        const uint64_t prev = atomicCAS((unsigned long long*)&a.tab.slots[h].fp,
+                                        (unsigned long long)kEmpty, (unsigned long long)fp);
+        if (prev == kEmpty || prev == fp) break;
+        h = (h + 1) & a.tab.mask;
+      }
+      a.k.slot[j] = (uint32_t)h;
+      atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
+    } else {
+      // the one key of this text that ends at the text's end with a short block
+      a.k.slot[j] = kOddKey;
+      a.odd.L[t] = L;
+      a.odd.xp[t] = xp;
+      a.odd.fp[t] = fp;
+      a.odd.pos[t] = st;
+      a.odd.best[t] = st;
+    }
+  }
+}
+
+hipError_t launch_keys(const PhaseArgs& a, hipStream_t s) {
+  k_keys<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- windows per run
+
+__global__ void k_window_counts(PhaseArgs a, uint64_t* woff) {
+  GRID_STRIDE(r, a.lv.R) {
+    const uint32_t t = a.lv.rtext[r];
+    const uint64_t len = a.lv.re[r] - a.lv.rs[r];
+    uint64_t Lmin = a.Lmain;
+    const uint64_t oL = a.odd.L[t];
+    if (oL && oL < Lmin) Lmin = oL;
+    woff[r] = (a.odd.nkeys[t] && len >= Lmin) ? len - Lmin + 1 : 0;
+  }
+}
+
+hipError_t launch_window_counts(const PhaseArgs& a, uint64_t* woff, hipStream_t s) {
+  k_window_counts<<<grid_for(a.lv.R, 256), 256, 0, s>>>(a, woff);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- probe scan (a4, a6)
+
+constexpr int kScanK = 16;                      // windows per lane per chunk
+constexpr uint64_t kScanChunk = 64ull * kScanK;  // windows per wave per chunk
+
+__device__ __forceinline__ void probe(Slot* __restrict__ slots, uint64_t mask, uint64_t fp,
+                                      uint64_t i) {
+  uint64_t h = slot_of(fp, mask);
+  while (true) {
+    const Slot s = slots[h];
+    if (s.fp == fp) {
+      if (i < s.best) atomicMin((unsigned long long*)&slots[h].best, (unsigned long long)i);
+      return;
+    }
+    if (s.fp == kEmpty) return;
+    h = (h + 1) & mask;
+  }
+}
+
+// Windows are numbered run after run (woff = exclusive prefix of per-run window
+// counts).  Each wave takes chunks of 64*kScanK consecutive window numbers;
+// in step k lane l handles window chunk + 64k + l, so consecutive lanes read
+// consecutive prefix fingerprints.
+template <bool ODD, bool SALT>
+__global__ __launch_bounds__(256) void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
+  const uint64_t R = a.lv.R;
+  const uint64_t W = woff[R];
+  const int lane = lane_id();
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t* __restrict__ P = a.P;
+  const uint64_t* __restrict__ rs_ = a.lv.rs;
+  const uint64_t* __restrict__ re_ = a.lv.re;
+  const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
+  Slot* __restrict__ slots = a.tab.slots;
+  const uint64_t mask = a.tab.mask;
+
+  for (uint64_t ch = gw; ch * kScanChunk < W; ch += nw) {
+    const uint64_t w0 = ch * kScanChunk + lane;
+    uint64_t lo = 0, hi = R;
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (woff[mid] <= w0) lo = mid; else hi = mid;
+    }
+    uint64_t r = lo;
+    uint64_t wo = woff[r], wn = woff[r + 1], rs = rs_[r], re = re_[r];
+    uint32_t t = (ODD || SALT) ? a.lv.rtext[r] : 0;
+    uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
+    for (int k = 0; k < kScanK; ++k) {
+      const uint64_t w = w0 + (uint64_t)k * 64;
+      if (w >= W) break;
+      if (w >= wn) {
+        do {
+          ++r;
+          wo = wn;
+          wn = woff[r + 1];
+        } while (w >= wn);
+        rs = rs_[r];
+        re = re_[r];
+        if (ODD || SALT) t = a.lv.rtext[r];
+        if (SALT) salt = a.tx.tsalt[t];
+      }
+      const uint64_t i = rs + (w - wo);
+      const uint64_t pi = P[i];
+      if (i + L <= re) {
+        uint64_t fp = sub61(P[i + L], mul61(pi, xL));
+        if (SALT) fp = add61(fp, salt);
+        probe(slots, mask, fp & fmask, i);
+      }
+      if (ODD) {
+        const uint64_t oL = a.odd.L[t];
+        if (oL && i + oL <= re && i < a.odd.pos[t]) {
+          uint64_t fp = sub61(P[i + oL], mul61(pi, a.odd.xp[t]));
+          if (SALT) fp = add61(fp, salt);
+          if ((fp & fmask) == a.odd.fp[t] && i < a.odd.best[t])
+            atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
+                             bool has_salt, uint64_t max_windows, hipStream_t s) {
+  if (a.lv.R == 0) return hipSuccess;
+  const uint64_t waves = (max_windows + kScanChunk - 1) / kScanChunk;
+  const unsigned grid = grid_for(waves * 64, 256, 256 * 16);
+  if (has_odd) {
+    if (has_salt) k_probe_scan<true, true><<<grid, 256, 0, s>>>(a, woff);
+    else k_probe_scan<true, false><<<grid, 256, 0, s>>>(a, woff);
+  } else {
+    if (has_salt) k_probe_scan<false, true><<<grid, 256, 0, s>>>(a, woff);
+    else k_probe_scan<false, false><<<grid, 256, 0, s>>>(a, woff);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- resolve / verify / retry
+
+__global__ void k_resolve(PhaseArgs a, VerifyBufs v) {
+  GRID_STRIDE(j, a.lv.c) {
+    const uint32_t s = a.k.slot[j];
+    if (s == kNoKey) continue;
+    const uint64_t pos = a.lv.st[j];
+    const uint64_t best = (s == kOddKey) ? a.odd.best[a.lv.text[j]] : a.tab.slots[s].best;
+    if (best == pos) {
+      a.k.lm[j] = pos;
+    } else {
+      const uint64_t idx = atomicAdd((unsigned long long*)&v.counts[0], 1ull);
+      v.vlist[idx] = (uint32_t)j;
+      v.vbest[idx] = best;
+      v.vmis[idx] = 0;
+    }
+  }
+}
+
+hipError_t launch_resolve(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s) {
+  k_resolve<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, v);
+  return hipGetLastError();
+}
+
+constexpr uint64_t kVChunk = 4096;  // bytes compared per work item
+
+// One wave compares up to 4 KiB of a key with the candidate occurrence.
+__device__ __forceinline__ bool wave_bytes_differ(const uint8_t* __restrict__ T, uint64_t a0,
+                                                  uint64_t b0, uint64_t off, uint64_t end) {
+  bool diff = false;
+  for (uint64_t o = off + (uint64_t)lane_id() * 16; o < end; o += 64 * 16) {
+    if (o + 16 <= end) {
+      const uint4 x = load16(T + a0 + o);
+      const uint4 y = load16(T + b0 + o);
+      diff |= (x.x != y.x) | (x.y != y.y) | (x.z != y.z) | (x.w != y.w);
+    } else {
+      for (uint64_t q = o; q < end; ++q) diff |= T[a0 + q] != T[b0 + q];
+    }
+  }
+  return __any(diff);
+}
+
+__global__ __launch_bounds__(256) void k_verify(PhaseArgs a, VerifyBufs v, uint64_t cpk) {
+  const uint64_t cnt = v.counts[0];
+  const uint64_t items = cnt * cpk;
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t it = gw; it < items; it += nw) {
+    const uint64_t idx = it / cpk;
+    const uint64_t chunk = it - idx * cpk;
+    const uint32_t j = v.vlist[idx];
+    const uint64_t best = v.vbest[idx];
+    const uint64_t pos = a.lv.st[j];
+    const uint64_t L = a.k.len[j];
+    if (best < a.tx.tstart[a.lv.text[j]]) {  // hit in another text: a collision
+      if (chunk == 0 && lane_id() == 0) v.vmis[idx] = 1;
+      continue;
+    }
+    const uint64_t off = chunk * kVChunk;
+    if (off >= L) continue;
+    const uint64_t end = L - off < kVChunk ? L : off + kVChunk;
+    if (wave_bytes_differ(a.T, best, pos, off, end) && lane_id() == 0) v.vmis[idx] = 1;
+  }
+}
+
+hipError_t launch_verify(const PhaseArgs& a, const VerifyBufs& v, uint64_t max_len,
+                         hipStream_t s) {
+  const uint64_t cpk = (max_len + kVChunk - 1) / kVChunk;
+  const uint64_t items = a.lv.c * (cpk ? cpk : 1);
+  const unsigned grid = grid_for(items * 64, 256, 256 * 8);
+  k_verify<<<grid, 256, 0, s>>>(a, v, cpk ? cpk : 1);
+  return hipGetLastError();
+}
+
+__global__ void k_finish(PhaseArgs a, VerifyBufs v) {
+  const uint64_t cnt = v.counts[0];
+  GRID_STRIDE(idx, cnt) {
+    const uint32_t j = v.vlist[idx];
+    if (v.vmis[idx]) {
+      const uint64_t r = atomicAdd((unsigned long long*)&v.counts[1], 1ull);
+      const uint64_t ts = a.tx.tstart[a.lv.text[j]];
+      const uint64_t lb = v.vbest[idx] + 1;
+      v.rlist[r] = j;
+      v.rlb[r] = lb > ts ? lb : ts;
+    } else {
+      a.k.lm[j] = v.vbest[idx];
+    }
+  }
+}
+
+hipError_t launch_finish(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s) {
+  k_finish<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, v);
+  return hipGetLastError();
+}
+
+// Exact fallback after a collision: one wave per key walks positions
+// lb, lb+1, ... up to the key's own start, fingerprints each window, and
+// verifies hits in increasing order; the first verified hit is the leftmost
+// occurrence (no true occurrence lies before lb, see the file header of
+// bt_host.cpp).  The key's own start always verifies, so the walk ends.
+__global__ __launch_bounds__(256) void k_retry(PhaseArgs a, VerifyBufs v) {
+  const uint64_t cnt = v.counts[1];
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const int lane = lane_id();
+  for (uint64_t idx = gw; idx < cnt; idx += nw) {
+    const uint32_t j = v.rlist[idx];
+    const uint64_t lb = v.rlb[idx];
+    const uint64_t pos = a.lv.st[j];
+    const uint64_t L = a.k.len[j];
+    const uint64_t fpk = a.k.fp[j];
+    const uint64_t salt = a.tx.tsalt[a.lv.text[j]];
+    const uint64_t xp = pow61(a.x, L);
+    uint64_t found = pos;
+    bool done = false;
+    for (uint64_t p0 = lb; p0 <= pos && !done; p0 += 64) {
+      const uint64_t p = p0 + lane;
+      const bool m = p <= pos && finish_fp(window_fp(a.P, p, L, xp), salt, a.fpmask) == fpk;
+      uint64_t bal = __ballot(m);
+      while (bal) {
+        const uint64_t q = p0 + (uint64_t)(__ffsll((unsigned long long)bal) - 1);
+        bool diff = false;
+        for (uint64_t off = 0; off < L && !diff; off += kVChunk) {
+          const uint64_t end = L - off < kVChunk ? L : off + kVChunk;
+          diff = wave_bytes_differ(a.T, q, pos, off, end);
+        }
+        if (!diff) {
+          found = q;
+          done = true;
+          break;
+        }
+        bal &= bal - 1;
+      }
+    }
+    if (lane == 0) a.k.lm[j] = found;
+  }
+}
+
+hipError_t launch_retry(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s) {
+  const unsigned grid = grid_for(a.lv.c * 64, 256, 1024);
+  k_retry<<<grid, 256, 0, s>>>(a, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- marks (a5)
+
+__global__ void k_mark(PhaseArgs a, uint8_t* marked) {
+  const LevelDev lv = a.lv;
+  GRID_STRIDE(j, lv.c) {
+    bool m = a.k.slot[j] != kNoKey && a.k.lm[j] == lv.st[j];
+    if (j > 0 && a.k.slot[j - 1] != kNoKey && a.k.lm[j - 1] == lv.st[j - 1]) m = true;
+    const uint32_t r = lv.run[j];
+    const bool left = j > 0 && lv.run[j - 1] == r;
+    const bool right = j + 1 < lv.c && lv.run[j + 1] == r;
+    if (!left && !right) m = true;  // a block with no consecutive neighbour
+    marked[j] = m ? 1 : 0;
+  }
+}
+
+hipError_t launch_mark(const PhaseArgs& a, uint8_t* marked, hipStream_t s) {
+  k_mark<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, marked);
+  return hipGetLastError();
+}
+
+__global__ void k_unmarked_counts(const uint8_t* marked, uint64_t c, uint64_t* cnt) {
+  GRID_STRIDE(j, c) cnt[j] = marked[j] ? 0 : 1;
+}
+
+hipError_t launch_unmarked_counts(const uint8_t* marked, uint64_t c, uint64_t* cnt,
+                                  hipStream_t s) {
+  k_unmarked_counts<<<grid_for(c, 256), 256, 0, s>>>(marked, c, cnt);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- pointers (a7)
+
+__global__ void k_pointers(PhaseArgs a, const uint8_t* marked, const uint64_t* uoff,
+                           const uint64_t* tfirst, uint64_t* pb, uint64_t* po, uint32_t* err) {
+  const LevelDev lv = a.lv;
+  GRID_STRIDE(j, lv.c) {
+    if (marked[j]) continue;
+    const uint64_t p = a.k.lm[j];
+    uint64_t lo = 0, hi = lv.c;
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (lv.st[mid] <= p) lo = mid; else hi = mid;
+    }
+    const uint64_t t = lo;
+    const uint32_t tx = lv.text[j];
+    const uint64_t lj = block_len(lv, a.tx, j), lt = block_len(lv, a.tx, t);
+    bool ok = lv.st[t] <= p && p < lv.st[t] + lt && marked[t] && lv.text[t] == tx &&
+              p + lj <= lv.st[j];
+    if (ok && p + lj > lv.st[t] + lt)
+      ok = t + 1 < lv.c && lv.run[t + 1] == lv.run[t] && marked[t + 1];
+    if (!ok) *err = 1;
+    const uint64_t u = uoff[j];
+    pb[u] = t - tfirst[tx];
+    po[u] = p - lv.st[t];
+  }
+}
+
+hipError_t launch_pointers(const PhaseArgs& a, const uint8_t* marked, const uint64_t* uoff,
+                           const uint64_t* tfirst, uint64_t* ptr_block, uint64_t* ptr_off,
+                           uint32_t* err, hipStream_t s) {
+  k_pointers<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, marked, uoff, tfirst, ptr_block, ptr_off,
+                                                    err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- split (a8)
+
+__global__ void k_child_counts(LevelDev lv, TextsDev tx, const uint8_t* marked, uint64_t bn,
+                               uint64_t* cnt) {
+  GRID_STRIDE(j, lv.c) {
+    cnt[j] = marked[j] ? (block_len(lv, tx, j) + bn - 1) / bn : 0;
+  }
+}
+
+hipError_t launch_child_counts(const LevelDev& lv, const TextsDev& tx, const uint8_t* marked,
+                               uint64_t bn, uint64_t* cnt, hipStream_t s) {
+  k_child_counts<<<grid_for(lv.c, 256), 256, 0, s>>>(lv, tx, marked, bn, cnt);
+  return hipGetLastError();
+}
+
+__global__ void k_text_counts(uint32_t T, const uint64_t* cs, const uint64_t* tfirst,
+                              const uint64_t* tcount, const uint64_t* enter, uint64_t* ncount) {
+  GRID_STRIDE(t, T) {
+    const uint64_t f = tfirst[t];
+    ncount[t] = cs[f + tcount[t]] - cs[f] + (enter ? enter[t] : 0);
+  }
+}
+
+hipError_t launch_text_counts(uint32_t T, const uint64_t* cs, const uint64_t* tfirst,
+                              const uint64_t* tcount, const uint64_t* enter, uint64_t* ncount,
+                              hipStream_t s) {
+  k_text_counts<<<grid_for(T, 256), 256, 0, s>>>(T, cs, tfirst, tcount, enter, ncount);
+  return hipGetLastError();
+}
+
+__global__ void k_write_children(LevelDev lv, TextsDev tx, const uint8_t* marked, uint64_t bn,
+                                 const uint64_t* cs, const uint64_t* tfirst,
+                                 const uint64_t* ntfirst, uint64_t* nst, uint32_t* ntext) {
+  GRID_STRIDE(j, lv.c) {
+    if (!marked[j]) continue;
+    const uint32_t t = lv.text[j];
+    const uint64_t base = ntfirst[t] + (cs[j] - cs[tfirst[t]]);
+    const uint64_t nk = cs[j + 1] - cs[j];
+    const uint64_t st = lv.st[j];
+    for (uint64_t k = 0; k < nk; ++k) {
+      nst[base + k] = st + k * bn;
+      ntext[base + k] = t;
+    }
+  }
+}
+
+hipError_t launch_write_children(const LevelDev& lv, const TextsDev& tx, const uint8_t* marked,
+                                 uint64_t bn, uint32_t tau, const uint64_t* cs,
+                                 const uint64_t* tfirst, const uint64_t* ntfirst, uint64_t* nst,
+                                 uint32_t* ntext, hipStream_t s) {
+  (void)tau;
+  k_write_children<<<grid_for(lv.c, 256), 256, 0, s>>>(lv, tx, marked, bn, cs, tfirst, ntfirst,
+                                                        nst, ntext);
+  return hipGetLastError();
+}
+
+__global__ void k_write_entering(const uint32_t* ids, TextsDev tx, uint64_t bn,
+                                 const uint64_t* ntfirst, uint64_t* nst, uint32_t* ntext) {
+  const uint32_t t = ids[blockIdx.x];
+  const uint64_t ts = tx.tstart[t], te = tx.tend[t];
+  const uint64_t nb = (te - ts + bn - 1) / bn;
+  const uint64_t base = ntfirst[t];
+  for (uint64_t k = threadIdx.x; k < nb; k += blockDim.x) {
+    nst[base + k] = ts + k * bn;
+    ntext[base + k] = t;
+  }
+}
+
+hipError_t launch_write_entering(const uint32_t* ids, uint32_t E, const TextsDev& tx,
+                                 uint64_t bn, const uint64_t* ntfirst, uint64_t* nst,
+                                 uint32_t* ntext, hipStream_t s) {
+  if (!E) return hipSuccess;
+  k_write_entering<<<E, 256, 0, s>>>(ids, tx, bn, ntfirst, nst, ntext);
+  return hipGetLastError();
+}
+
+__global__ void k_run_flags(const uint64_t* st, const uint32_t* text, uint64_t c, uint64_t b,
+                            uint64_t* rflag) {
+  GRID_STRIDE(j, c) {
+    rflag[j] = (j == 0 || text[j] != text[j - 1] || st[j] != st[j - 1] + b) ? 1 : 0;
+  }
+}
+
+hipError_t launch_run_flags(const uint64_t* st, const uint32_t* text, uint64_t c, uint64_t b,
+                            uint64_t* rflag, hipStream_t s) {
+  k_run_flags<<<grid_for(c, 256), 256, 0, s>>>(st, text, c, b, rflag);
+  return hipGetLastError();
+}
+
+__global__ void k_run_table(const uint64_t* st, const uint32_t* text, uint64_t c, uint64_t b,
+                            TextsDev tx, const uint64_t* roff, uint32_t* run, uint64_t* rs,
+                            uint64_t* re, uint32_t* rtext) {
+  GRID_STRIDE(j, c) {
+    const uint64_t r = roff[j + 1] - 1;
+    run[j] = (uint32_t)r;
+    if (roff[j + 1] != roff[j]) {
+      rs[r] = st[j];
+      rtext[r] = text[j];
+    }
+    const bool last = (j + 1 == c) || (roff[j + 2] != roff[j + 1]);
+    if (last) {
+      const uint64_t te = tx.tend[text[j]];
+      re[r] = st[j] + (te - st[j] < b ? te - st[j] : b);
+    }
+  }
+}
+
+hipError_t launch_run_table(const uint64_t* st, const uint32_t* text, uint64_t c, uint64_t b,
+                            const TextsDev& tx, const uint64_t* roff, uint32_t* run,
+                            uint64_t* rs, uint64_t* re, uint32_t* rtext, hipStream_t s) {
+  k_run_table<<<grid_for(c, 256), 256, 0, s>>>(st, text, c, b, tx, roff, run, rs, re, rtext);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- outputs
+
+__global__ void k_pack_marks(const uint8_t* marked, uint32_t T, const uint64_t* tfirst,
+                             const uint64_t* tcount, const uint64_t* woff, uint64_t nwords,
+                             uint64_t* words) {
+  GRID_STRIDE(wi, nwords) {
+    uint64_t lo = 0, hi = T;
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (woff[mid] <= wi) lo = mid; else hi = mid;
+    }
+    // skip texts with no words (equal offsets): take the last one not past wi
+    const uint64_t t = lo;
+    const uint64_t lw = wi - woff[t];
+    const uint64_t f = tfirst[t], cnt = tcount[t];
+    uint64_t word = 0;
+    for (uint64_t k = 0; k < 64; ++k) {
+      const uint64_t j = lw * 64 + k;
+      if (j < cnt && marked[f + j]) word |= 1ull << k;
+    }
+    words[wi] = word;
+  }
+}
+
+hipError_t launch_pack_marks(const uint8_t* marked, uint32_t T, const uint64_t* tfirst,
+                             const uint64_t* tcount, const uint64_t* woff, uint64_t nwords,
+                             uint64_t* words, hipStream_t s) {
+  if (!nwords) return hipSuccess;
+  k_pack_marks<<<grid_for(nwords, 256), 256, 0, s>>>(marked, T, tfirst, tcount, woff, nwords,
+                                                      words);
+  return hipGetLastError();
+}
+
+// Leaf bytes: block j of the last level lands at j*b (texts' regions are
+// contiguous; only a text-final block is short, and it ends its region).
+__global__ void k_leaves(const uint8_t* T, LevelDev lv, TextsDev tx, uint8_t* out) {
+  GRID_STRIDE(j, lv.c) {
+    const uint64_t len = block_len(lv, tx, j);
+    const uint64_t st = lv.st[j];
+    for (uint64_t o = 0; o < len; ++o) out[j * lv.b + o] = T[st + o];
+  }
+}
+
+hipError_t launch_leaves(const uint8_t* T, const LevelDev& lv, const TextsDev& tx, uint8_t* out,
+                         hipStream_t s) {
+  if (!lv.c) return hipSuccess;
+  k_leaves<<<grid_for(lv.c, 256), 256, 0, s>>>(T, lv, tx, out);
+  return hipGetLastError();
+}
+
+}  // namespace bt

@@ -1,0 +1,146 @@
+// Fills and a device-wide exclusive prefix sum (Section 2.2, prefix sums) used
+// by the compaction steps of every level.  Reduce-then-scan over 2048-element
+// tiles; the tile sums are scanned recursively.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bt {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr uint64_t kScanTile = kScanThreads * kScanItems;
+
+template <typename Tp>
+__global__ void k_fill(Tp* p, Tp v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 8192) {
+  uint64_t g = (n + threads - 1) / threads;
+  if (g == 0) g = 1;
+  return (unsigned)(g < cap ? g : cap);
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_fill<uint64_t><<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_fill<uint32_t><<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  k_fill<uint8_t><<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+// Exclusive scan of one block's values (256 threads); returns the block total.
+__device__ uint64_t block_excl_scan(uint64_t v, uint64_t* s_w) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = __shfl_up(inc, d);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  uint64_t before = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    if (k < wv) before += s_w[k];
+    total += s_w[k];
+  }
+  __syncthreads();
+  return before + inc - v + 0 * total;
+}
+
+__device__ uint64_t block_total(uint64_t v, uint64_t* s_w) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  if (lane == 0) s_w[wv] = v;
+  __syncthreads();
+  uint64_t total = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) total += s_w[k];
+  __syncthreads();
+  return total;
+}
+
+// Tile sums.
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const uint64_t* __restrict__ a,
+                                                            uint64_t n, uint64_t* sums) {
+  __shared__ uint64_t s_w[kScanThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint64_t v = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + (uint64_t)k * kScanThreads + threadIdx.x;
+    if (i < n) v += a[i];
+  }
+  const uint64_t tot = block_total(v, s_w);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Scan each tile in place and add its carry-in (carry == nullptr: none).
+// When write_total, the last tile also stores the grand total in a[n].
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint64_t* __restrict__ a, uint64_t n,
+                                                            const uint64_t* __restrict__ carry) {
+  __shared__ uint64_t s_w[kScanThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  const uint64_t first = base + (uint64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = first + k;
+    v[k] = i < n ? a[i] : 0;
+    sum += v[k];
+  }
+  uint64_t run = block_excl_scan(sum, s_w) + (carry ? carry[blockIdx.x] : 0);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = first + k;
+    if (i < n) a[i] = run;
+    run += v[k];
+  }
+  // the thread holding element n-1 (or the first thread when n == 0) writes a[n]
+  const uint64_t last = n ? n - 1 : 0;
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a[0] = carry ? carry[0] : 0;
+  } else if (last >= first && last < first + kScanItems) {
+    a[n] = run;
+  }
+}
+
+uint64_t scan_tmp_words(uint64_t n) {
+  uint64_t w = 0;
+  while (n > kScanTile) {
+    const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+    w += tiles + 1;
+    n = tiles;
+  }
+  return w + 1;
+}
+
+hipError_t scan_excl_u64(uint64_t* a, uint64_t n, uint64_t* tmp, hipStream_t s) {
+  if (n <= kScanTile) {
+    k_tile_scan<<<1, kScanThreads, 0, s>>>(a, n, nullptr);
+    return hipGetLastError();
+  }
+  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+  uint64_t* sums = tmp;
+  k_tile_sums<<<(unsigned)tiles, kScanThreads, 0, s>>>(a, n, sums);
+  hipError_t e = scan_excl_u64(sums, tiles, tmp + tiles + 1, s);
+  if (e != hipSuccess) return e;
+  k_tile_scan<<<(unsigned)tiles, kScanThreads, 0, s>>>(a, n, sums);
+  return hipGetLastError();
+}
+
+}  // namespace bt

@@ -1,0 +1,39 @@
+"""The C-ABI library loads and exports every entry point include/bt.h declares
+(CPU only: no call reaches the device)."""
+import os
+import re
+
+import paper_2512_23314_amd as bt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^BT_API\s+[\w\s\*]+?\b(bt_\w+)\s*\(", src, flags=re.M)
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared()
+    assert len(names) >= 20
+    L = bt.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding covers the same surface
+    assert set(names) == set(bt.SIGNATURES)
+
+
+def test_status_strings():
+    L = bt.lib()
+    assert L.bt_strerror(0) == b"ok"
+    assert L.bt_strerror(-1) == b"invalid argument"
+    assert L.bt_strerror(-99) == b"unknown status"
+
+
+def test_params_layout():
+    import ctypes
+    assert ctypes.sizeof(bt.bt_params) == 40
