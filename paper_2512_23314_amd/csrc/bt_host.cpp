@@ -605,6 +605,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint64_t> vbest = alloc<uint64_t>(ctx, c), rlb = alloc<uint64_t>(ctx, c),
                   vcnt = alloc<uint64_t>(ctx, 2);
     Buf<uint8_t> marked = alloc<uint8_t>(ctx, c);
+    // key filter: about 32 bits per key, 2^12 .. 2^19 bits
+    uint32_t fbits = 12;
+    while (fbits < 19 && (1ull << fbits) < 32 * c) ++fbits;
+    Buf<uint32_t> filt = alloc<uint32_t>(ctx, (1ull << fbits) / 32);
     VerifyBufs vb{vlist.p, vbest.p, vmis.p, rlist.p, rlb.p, vcnt.p};
 
     PhaseArgs a{};
@@ -619,6 +623,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.x = x;
     a.fpmask = fpmask;
     a.marked = marked.p;
+    a.filt = filt.p;
+    a.filt_bits = fbits;
 
     auto run_phase = [&](int phase) {
       a.phase = phase;
@@ -627,6 +633,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       HIPCHK(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(tab.p), ~0ull, 2 * cap, s));
       HIPCHK(ctx, launch_fill_u64(oddb.p, 0, 6 * (uint64_t)T, s));
       HIPCHK(ctx, launch_fill_u64(vcnt.p, 0, 2, s));
+      HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
       HIPCHK(ctx, launch_keys(a, s));
       HIPCHK(ctx, launch_window_counts(a, woff.p, s));
       scan(woff.p, R);

@@ -58,11 +58,19 @@ __device__ __forceinline__ uint64_t slot_of(uint64_t fp, uint64_t mask) {
   return (fp ^ (fp >> 29) ^ (fp >> 47)) & mask;
 }
 
+// Bit of a fingerprint in a filter of 2^bits bits (independent of slot_of's
+// low bits for large tables).
+__device__ __forceinline__ uint64_t filter_bit(uint64_t fp, uint32_t bits) {
+  return (fp ^ (fp >> 31)) & ((1ull << bits) - 1);
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Relaxed device-scope store: the word carries its own payload, so no other
+// memory needs ordering with it (a release here would write back the L2).
+__device__ __forceinline__ void st_relaxed(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }

@@ -87,6 +87,8 @@ struct PhaseArgs {
   uint64_t fpmask;  // all ones, or kWeakMask
   const uint8_t* marked;  // phase 2: skip marked blocks
   int phase;        // 1 or 2
+  uint32_t* filt;   // bit filter of the main-length keys' fingerprints
+  uint32_t filt_bits;  // log2 of its size in bits (12..19)
 };
 
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);

@@ -75,6 +75,8 @@ __global__ void k_keys(PhaseArgs a) {
       }
       a.k.slot[j] = (uint32_t)h;
       atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
+      const uint64_t fb = filter_bit(fp, a.filt_bits);
+      atomicOr(&a.filt[fb >> 5], 1u << (fb & 31));
     } else {
       // the one key of this text that ends at the text's end with a short block
       a.k.slot[j] = kOddKey;
@@ -133,8 +135,25 @@ __device__ __forceinline__ void probe(Slot* __restrict__ slots, uint64_t mask, u
 // counts).  Each wave takes chunks of 64*kScanK consecutive window numbers;
 // in step k lane l handles window chunk + 64k + l, so consecutive lanes read
 // consecutive prefix fingerprints.
+//
+// Before touching the table, a window's fingerprint is tested against a bit
+// filter of the phase's keys (one bit per key, set by k_keys) that every
+// workgroup first copies into LDS.  A clear bit proves that no key has this
+// fingerprint; only the remaining windows make the random table access, which
+// is what bounds the scan once the table outgrows the L1.
+constexpr int kProbeThreads = 1024;
+
 template <bool ODD, bool SALT>
-__global__ __launch_bounds__(256) void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
+__global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
+                                                             const uint64_t* __restrict__ woff) {
+  extern __shared__ uint32_t s_filt[];
+  {
+    const uint32_t nq = (uint32_t)(1ull << (a.filt_bits - 7));  // uint4 words
+    const uint4* src = reinterpret_cast<const uint4*>(a.filt);
+    uint4* dst = reinterpret_cast<uint4*>(s_filt);
+    for (uint32_t q = threadIdx.x; q < nq; q += blockDim.x) dst[q] = src[q];
+    __syncthreads();
+  }
   const uint64_t R = a.lv.R;
   const uint64_t W = woff[R];
   const int lane = lane_id();
@@ -144,6 +163,7 @@ __global__ __launch_bounds__(256) void k_probe_scan(PhaseArgs a, const uint64_t*
   const uint64_t* __restrict__ rs_ = a.lv.rs;
   const uint64_t* __restrict__ re_ = a.lv.re;
   const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
+  const uint32_t fbits = a.filt_bits;
   Slot* __restrict__ slots = a.tab.slots;
   const uint64_t mask = a.tab.mask;
 
@@ -177,7 +197,9 @@ __global__ __launch_bounds__(256) void k_probe_scan(PhaseArgs a, const uint64_t*
       if (i + L <= re) {
         uint64_t fp = sub61(P[i + L], mul61(pi, xL));
         if (SALT) fp = add61(fp, salt);
-        probe(slots, mask, fp & fmask, i);
+        fp &= fmask;
+        const uint64_t fb = filter_bit(fp, fbits);
+        if ((s_filt[fb >> 5] >> (fb & 31)) & 1) probe(slots, mask, fp, i);
       }
       if (ODD) {
         const uint64_t oL = a.odd.L[t];
@@ -196,13 +218,15 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
                              bool has_salt, uint64_t max_windows, hipStream_t s) {
   if (a.lv.R == 0) return hipSuccess;
   const uint64_t waves = (max_windows + kScanChunk - 1) / kScanChunk;
-  const unsigned grid = grid_for(waves * 64, 256, 256 * 16);
+  // two 1024-thread workgroups per CU at most (LDS: two filters of up to 64 KiB)
+  const unsigned grid = grid_for(waves * 64, kProbeThreads, 512);
+  const size_t lds = (size_t)1 << (a.filt_bits - 3);
   if (has_odd) {
-    if (has_salt) k_probe_scan<true, true><<<grid, 256, 0, s>>>(a, woff);
-    else k_probe_scan<true, false><<<grid, 256, 0, s>>>(a, woff);
+    if (has_salt) k_probe_scan<true, true><<<grid, kProbeThreads, lds, s>>>(a, woff);
+    else k_probe_scan<true, false><<<grid, kProbeThreads, lds, s>>>(a, woff);
   } else {
-    if (has_salt) k_probe_scan<false, true><<<grid, 256, 0, s>>>(a, woff);
-    else k_probe_scan<false, false><<<grid, 256, 0, s>>>(a, woff);
+    if (has_salt) k_probe_scan<false, true><<<grid, kProbeThreads, lds, s>>>(a, woff);
+    else k_probe_scan<false, false><<<grid, kProbeThreads, lds, s>>>(a, woff);
   }
   return hipGetLastError();
 }

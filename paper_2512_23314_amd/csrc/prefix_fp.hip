@@ -5,14 +5,15 @@
 // The recurrence is a prefix operation under the associative combine
 // (h1, len1) o (h2, len2) = (h1 * x^len2 + h2, len1 + len2) (Section 2.2, the
 // all-prefix operation).  One workgroup of 256 threads owns a 4096-byte tile:
-//   1. each thread folds its 16 bytes by Horner's rule;
+//   1. each thread folds its 16 bytes by Horner's rule, as four independent
+//      4-byte chains joined with x^4 (short dependency chains);
 //   2. a wave64 shuffle scan and a 4-entry LDS pass give every thread the
 //      fingerprint of the tile prefix before it;
 //   3. the tile's carry-in comes from a decoupled look-back over the tile
 //      status words (one 64-bit word per tile: value in bits 0..60, flag bits
 //      61 (aggregate ready) and 62 (inclusive prefix ready));
-//   4. each thread re-runs Horner from its prefix and stages the 16 outputs in
-//      LDS so that the global stores are contiguous across the wave.
+//   4. each thread re-runs the four chains from its prefix and stages the 16
+//      outputs in LDS so that the global stores are contiguous across the wave.
 // Tile order comes from an atomic counter, so every tile a workgroup waits on
 // was taken by a workgroup that started earlier.
 #include "common.hpp"
@@ -53,10 +54,24 @@ __global__ __launch_bounds__(kPfThreads) void k_prefix_fp(const uint8_t* __restr
       if (pos + k < n) w[k >> 2] |= (uint32_t)T[pos + k] << (8 * (k & 3));
   }
 
-  // 1. thread aggregate
-  uint64_t h = 0;
+  // 1. thread aggregate, as four independent 4-byte Horner chains combined by
+  //    g_{c+1} = g_c * x^4 + h_c (short dependency chains keep the VALU busy)
+  const auto byte_at = [&](int k) { return (uint64_t)((w[k >> 2] >> (8 * (k & 3))) & 0xFF); };
+  uint64_t hc[4];
 #pragma unroll
-  for (int k = 0; k < kPfBytes; ++k) h = add61(mul61(h, x), (w[k >> 2] >> (8 * (k & 3))) & 0xFF);
+  for (int c = 0; c < 4; ++c) {
+    uint64_t v = byte_at(4 * c);
+#pragma unroll
+    for (int k = 1; k < 4; ++k) v = add61(mul61(v, x), byte_at(4 * c + k));
+    hc[c] = v;
+  }
+  const uint64_t x4 = pw->x1[4];
+  uint64_t g[4];
+  g[0] = 0;
+  g[1] = hc[0];
+  g[2] = add61(mul61(g[1], x4), hc[1]);
+  g[3] = add61(mul61(g[2], x4), hc[2]);
+  const uint64_t h = add61(mul61(g[3], x4), hc[3]);
 
   // 2. wave inclusive scan: I = sum_{u <= lane} h_u x^(16 (lane - u))
   uint64_t I = h;
@@ -81,9 +96,9 @@ __global__ __launch_bounds__(kPfThreads) void k_prefix_fp(const uint8_t* __restr
   if (wv == 0) {
     uint64_t excl = 0;
     if (tile == 0) {
-      if (lane == 0) st_release(&status[0], kFlagInc | agg);
+      if (lane == 0) st_relaxed(&status[0], kFlagInc | agg);
     } else {
-      if (lane == 0) st_release(&status[tile], kFlagAgg | agg);
+      if (lane == 0) st_relaxed(&status[tile], kFlagAgg | agg);
       uint64_t mult = 1;
       int64_t look = (int64_t)tile - 1;
       while (true) {
@@ -100,18 +115,22 @@ __global__ __launch_bounds__(kPfThreads) void k_prefix_fp(const uint8_t* __restr
         mult = mul61(mult, pw->xt[64]);
         look -= 64;
       }
-      if (lane == 0) st_release(&status[tile], kFlagInc | add61(mul61(excl, pw->xt[1]), agg));
+      if (lane == 0) st_relaxed(&status[tile], kFlagInc | add61(mul61(excl, pw->xt[1]), agg));
     }
     if (lane == 0) s_excl = excl;
   }
   __syncthreads();
 
-  // 4. outputs P[pos+1 .. pos+16]
-  uint64_t C = add61(mul61(s_excl, pw->x16[t]), local);
+  // 4. outputs P[pos+1 .. pos+16]: chain c restarts from C * x^(4c) + g_c
+  const uint64_t C = add61(mul61(s_excl, pw->x16[t]), local);
 #pragma unroll
-  for (int k = 0; k < kPfBytes; ++k) {
-    C = add61(mul61(C, x), (w[k >> 2] >> (8 * (k & 3))) & 0xFF);
-    s_out[t * 17 + k] = C;
+  for (int c = 0; c < 4; ++c) {
+    uint64_t v = c ? add61(mul61(C, pw->x1[4 * c]), g[c]) : C;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v = add61(mul61(v, x), byte_at(4 * c + k));
+      s_out[t * 17 + 4 * c + k] = v;
+    }
   }
   __syncthreads();
 #pragma unroll
