@@ -605,10 +605,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint64_t> vbest = alloc<uint64_t>(ctx, c), rlb = alloc<uint64_t>(ctx, c),
                   vcnt = alloc<uint64_t>(ctx, 2);
     Buf<uint8_t> marked = alloc<uint8_t>(ctx, c);
-    // key filter: about 32 bits per key, 2^12 .. 2^19 bits
+    // LDS key filter of up to 2^18 bits, sized per phase from the key count
+    Buf<uint32_t> filt = alloc<uint32_t>(ctx, (1ull << 18) / 32);
+    bool use_filter = true;
     uint32_t fbits = 12;
-    while (fbits < 19 && (1ull << fbits) < 32 * c) ++fbits;
-    Buf<uint32_t> filt = alloc<uint32_t>(ctx, (1ull << fbits) / 32);
     VerifyBufs vb{vlist.p, vbest.p, vmis.p, rlist.p, rlb.p, vcnt.p};
 
     PhaseArgs a{};
@@ -624,23 +624,30 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.fpmask = fpmask;
     a.marked = marked.p;
     a.filt = filt.p;
-    a.filt_bits = fbits;
 
-    auto run_phase = [&](int phase) {
+    // nkeys: keys of the phase (pairs of consecutive blocks, or unmarked blocks)
+    auto run_phase = [&](int phase, uint64_t nkeys) {
       a.phase = phase;
       a.Lmain = phase == 1 ? 2 * b : b;
       a.xLmain = host_pow61(x, a.Lmain);
+      // about 32 filter bits per key; two bits per key while there are at least
+      // 8 bits per key, one while there is at least one, else no filter
+      fbits = 12;
+      while (fbits < 18 && (1ull << fbits) < 32 * nkeys) ++fbits;
+      use_filter = nkeys <= (1ull << fbits);
+      a.filt_bits = use_filter ? fbits : 0;
+      a.filt_two = 8 * nkeys <= (1ull << fbits);
       HIPCHK(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(tab.p), ~0ull, 2 * cap, s));
       HIPCHK(ctx, launch_fill_u64(oddb.p, 0, 6 * (uint64_t)T, s));
       HIPCHK(ctx, launch_fill_u64(vcnt.p, 0, 2, s));
-      HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
+      if (use_filter) HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
       HIPCHK(ctx, launch_keys(a, s));
       HIPCHK(ctx, launch_window_counts(a, woff.p, s));
       scan(woff.p, R);
       uint64_t* wst = wstats.p + 2 * step + (phase - 1);
       HIPCHK(ctx, hipMemcpyAsync(wst, woff.p + R, 8, hipMemcpyDeviceToDevice, s));
       timed(ctx, "probe_scan", 0, 0, wst, 16.0, [&] {
-        return launch_probe_scan(a, woff.p, has_odd, has_salt, c * b, s);
+        return launch_probe_scan(a, woff.p, has_odd, has_salt, c * b, use_filter, s);
       });
       HIPCHK(ctx, launch_resolve(a, vb, s));
       timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });
@@ -649,14 +656,16 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     };
 
     // ---- phase 1: pairs (a3, a4) and marks (a5)
-    run_phase(1);
+    run_phase(1, c - R);
     HIPCHK(ctx, launch_mark(a, marked.p, s));
 
     // ---- phase 2: unmarked blocks (a6) and pointers (a7)
     Buf<uint64_t> uoff = alloc<uint64_t>(ctx, c + 1);
     HIPCHK(ctx, launch_unmarked_counts(marked.p, c, uoff.p, s));
     scan(uoff.p, c);
-    run_phase(2);
+    std::vector<uint64_t> uu;
+    read_words(ctx, {{uoff.p + c, 1}}, uu);
+    run_phase(2, uu[0]);
     Buf<uint64_t> pb = alloc<uint64_t>(ctx, c), po = alloc<uint64_t>(ctx, c);
     HIPCHK(ctx, launch_pointers(a, marked.p, uoff.p, d_tfirst.p, pb.p, po.p,
                                 reinterpret_cast<uint32_t*>(d_err.p), s));

@@ -58,10 +58,12 @@ __device__ __forceinline__ uint64_t slot_of(uint64_t fp, uint64_t mask) {
   return (fp ^ (fp >> 29) ^ (fp >> 47)) & mask;
 }
 
-// Bit of a fingerprint in a filter of 2^bits bits (independent of slot_of's
-// low bits for large tables).
+// The two bits of a fingerprint in a key filter of 2^bits bits.
 __device__ __forceinline__ uint64_t filter_bit(uint64_t fp, uint32_t bits) {
   return (fp ^ (fp >> 31)) & ((1ull << bits) - 1);
+}
+__device__ __forceinline__ uint64_t filter_bit2(uint64_t fp, uint32_t bits) {
+  return ((fp >> 17) ^ (fp >> 41) ^ (fp * 0x9E3779B1ull >> 20)) & ((1ull << bits) - 1);
 }
 
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {

@@ -88,7 +88,8 @@ struct PhaseArgs {
   const uint8_t* marked;  // phase 2: skip marked blocks
   int phase;        // 1 or 2
   uint32_t* filt;   // bit filter of the main-length keys' fingerprints
-  uint32_t filt_bits;  // log2 of its size in bits (12..19)
+  uint32_t filt_bits;  // log2 of its size in bits (12..18); 0 = no filter
+  uint32_t filt_two;   // 1: two bits per key, 0: one
 };
 
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
@@ -104,9 +105,10 @@ hipError_t scan_excl_u64(uint64_t* a, uint64_t n, uint64_t* tmp, hipStream_t s);
 hipError_t launch_keys(const PhaseArgs& a, hipStream_t s);
 // Per-run window counts into woff[0..R) (then scanned by the caller).
 hipError_t launch_window_counts(const PhaseArgs& a, uint64_t* woff, hipStream_t s);
-// The sliding-window probe.  grid_hint bounds the grid.
+// The sliding-window probe.  max_windows bounds the grid; filter selects the
+// variant that tests an LDS key filter before the table.
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
-                             bool has_salt, uint64_t max_windows, hipStream_t s);
+                             bool has_salt, uint64_t max_windows, bool filter, hipStream_t s);
 
 struct VerifyBufs {
   uint32_t* vlist;  // [c]

@@ -75,8 +75,14 @@ __global__ void k_keys(PhaseArgs a) {
       }
       a.k.slot[j] = (uint32_t)h;
       atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
-      const uint64_t fb = filter_bit(fp, a.filt_bits);
-      atomicOr(&a.filt[fb >> 5], 1u << (fb & 31));
+      if (a.filt_bits) {
+        const uint64_t f1 = filter_bit(fp, a.filt_bits);
+        atomicOr(&a.filt[f1 >> 5], 1u << (f1 & 31));
+      }
+      if (a.filt_bits && a.filt_two) {
+        const uint64_t f2 = filter_bit2(fp, a.filt_bits);
+        atomicOr(&a.filt[f2 >> 5], 1u << (f2 & 31));
+      }
     } else {
       // the one key of this text that ends at the text's end with a short block
       a.k.slot[j] = kOddKey;
@@ -137,33 +143,47 @@ __device__ __forceinline__ void probe(Slot* __restrict__ slots, uint64_t mask, u
 // consecutive prefix fingerprints.
 //
 // Before touching the table, a window's fingerprint is tested against a bit
-// filter of the phase's keys (one bit per key, set by k_keys) that every
+// filter of the phase's keys (one or two bits per key, set by k_keys) that every
 // workgroup first copies into LDS.  A clear bit proves that no key has this
-// fingerprint; only the remaining windows make the random table access, which
-// is what bounds the scan once the table outgrows the L1.
+// fingerprint.  The windows that pass are appended to a per-wave queue in LDS
+// (ballot + prefix popcount) and probed 64 at a time, so a wave pays the
+// latency of the random table access once per 64 candidates instead of once
+// per step in which any lane has one.
 constexpr int kProbeThreads = 1024;
+constexpr int kQueue = 128;  // entries per wave (< 64 pending + up to 64 new)
 
-template <bool ODD, bool SALT>
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool FILTER, bool ODD, bool SALT>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
                                                              const uint64_t* __restrict__ woff) {
-  extern __shared__ uint32_t s_filt[];
-  {
-    const uint32_t nq = (uint32_t)(1ull << (a.filt_bits - 7));  // uint4 words
+  extern __shared__ uint64_t s_lds[];
+  const uint32_t fbits = a.filt_bits;
+  uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);
+  if (FILTER) {
+    const uint32_t nq = (uint32_t)(1ull << (fbits - 7));  // uint4 words
     const uint4* src = reinterpret_cast<const uint4*>(a.filt);
     uint4* dst = reinterpret_cast<uint4*>(s_filt);
     for (uint32_t q = threadIdx.x; q < nq; q += blockDim.x) dst[q] = src[q];
     __syncthreads();
   }
+  const int lane = lane_id();
+  uint64_t* qf = s_lds + (1ull << (fbits - 6)) + (uint64_t)(threadIdx.x >> 6) * (2 * kQueue);
+  uint64_t* qi = qf + kQueue;
+  uint32_t qn = 0;  // wave-uniform queue length
+
   const uint64_t R = a.lv.R;
   const uint64_t W = woff[R];
-  const int lane = lane_id();
   const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t* __restrict__ P = a.P;
   const uint64_t* __restrict__ rs_ = a.lv.rs;
   const uint64_t* __restrict__ re_ = a.lv.re;
   const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
-  const uint32_t fbits = a.filt_bits;
   Slot* __restrict__ slots = a.tab.slots;
   const uint64_t mask = a.tab.mask;
 
@@ -180,8 +200,8 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
     uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
     for (int k = 0; k < kScanK; ++k) {
       const uint64_t w = w0 + (uint64_t)k * 64;
-      if (w >= W) break;
-      if (w >= wn) {
+      const bool live = w < W;  // every lane stays in the loop (the queue is wave-wide)
+      if (live && w >= wn) {
         do {
           ++r;
           wo = wn;
@@ -193,41 +213,91 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
         if (SALT) salt = a.tx.tsalt[t];
       }
       const uint64_t i = rs + (w - wo);
-      const uint64_t pi = P[i];
-      if (i + L <= re) {
-        uint64_t fp = sub61(P[i + L], mul61(pi, xL));
-        if (SALT) fp = add61(fp, salt);
-        fp &= fmask;
-        const uint64_t fb = filter_bit(fp, fbits);
-        if ((s_filt[fb >> 5] >> (fb & 31)) & 1) probe(slots, mask, fp, i);
+      uint64_t pi = 0, fp = 0;
+      bool cand = false;
+      if (live) {
+        pi = P[i];
+        if (i + L <= re) {
+          fp = sub61(P[i + L], mul61(pi, xL));
+          if (SALT) fp = add61(fp, salt);
+          fp &= fmask;
+          if (FILTER) {
+            const uint64_t b1 = filter_bit(fp, fbits);
+            const uint64_t b2 = a.filt_two ? filter_bit2(fp, fbits) : b1;
+            cand = ((s_filt[b1 >> 5] >> (b1 & 31)) & (s_filt[b2 >> 5] >> (b2 & 31)) & 1) != 0;
+          } else {
+            probe(slots, mask, fp, i);
+          }
+        }
       }
-      if (ODD) {
+      const uint64_t bal = FILTER ? __ballot(cand) : 0;
+      if (FILTER && bal) {
+        const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+        if (cand) {
+          qf[qn + my] = fp;
+          qi[qn + my] = i;
+        }
+        qn += (uint32_t)__popcll(bal);
+        if (qn >= 64) {
+          wave_sync();
+          const uint64_t f = qf[lane], ii = qi[lane];
+          const bool mv = (uint32_t)lane < qn - 64;
+          uint64_t f2 = 0, i2 = 0;
+          if (mv) {
+            f2 = qf[64 + lane];
+            i2 = qi[64 + lane];
+          }
+          wave_sync();
+          if (mv) {
+            qf[lane] = f2;
+            qi[lane] = i2;
+          }
+          qn -= 64;
+          probe(slots, mask, f, ii);
+          wave_sync();
+        }
+      }
+      if (ODD && live) {
         const uint64_t oL = a.odd.L[t];
         if (oL && i + oL <= re && i < a.odd.pos[t]) {
-          uint64_t fp = sub61(P[i + oL], mul61(pi, a.odd.xp[t]));
-          if (SALT) fp = add61(fp, salt);
-          if ((fp & fmask) == a.odd.fp[t] && i < a.odd.best[t])
+          uint64_t f = sub61(P[i + oL], mul61(pi, a.odd.xp[t]));
+          if (SALT) f = add61(f, salt);
+          if ((f & fmask) == a.odd.fp[t] && i < a.odd.best[t])
             atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
         }
       }
     }
   }
+  if (FILTER && qn) {
+    wave_sync();
+    if ((uint32_t)lane < qn) probe(slots, mask, qf[lane], qi[lane]);
+  }
 }
 
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
-                             bool has_salt, uint64_t max_windows, hipStream_t s) {
+                             bool has_salt, uint64_t max_windows, bool filter, hipStream_t s) {
   if (a.lv.R == 0) return hipSuccess;
   const uint64_t waves = (max_windows + kScanChunk - 1) / kScanChunk;
-  // two 1024-thread workgroups per CU at most (LDS: two filters of up to 64 KiB)
+  // two 1024-thread workgroups per CU (LDS: filter up to 32 KiB + queues 32 KiB)
   const unsigned grid = grid_for(waves * 64, kProbeThreads, 512);
-  const size_t lds = (size_t)1 << (a.filt_bits - 3);
-  if (has_odd) {
-    if (has_salt) k_probe_scan<true, true><<<grid, kProbeThreads, lds, s>>>(a, woff);
-    else k_probe_scan<true, false><<<grid, kProbeThreads, lds, s>>>(a, woff);
+  const size_t lds = filter ? ((size_t)1 << (a.filt_bits - 3)) +
+                                  (size_t)(kProbeThreads / 64) * 2 * kQueue * sizeof(uint64_t)
+                            : 0;
+#define BT_PROBE_LAUNCH(F, O, S) k_probe_scan<F, O, S><<<grid, kProbeThreads, lds, s>>>(a, woff)
+  if (filter) {
+    if (has_odd) {
+      if (has_salt) BT_PROBE_LAUNCH(true, true, true); else BT_PROBE_LAUNCH(true, true, false);
+    } else {
+      if (has_salt) BT_PROBE_LAUNCH(true, false, true); else BT_PROBE_LAUNCH(true, false, false);
+    }
   } else {
-    if (has_salt) k_probe_scan<false, true><<<grid, kProbeThreads, lds, s>>>(a, woff);
-    else k_probe_scan<false, false><<<grid, kProbeThreads, lds, s>>>(a, woff);
+    if (has_odd) {
+      if (has_salt) BT_PROBE_LAUNCH(false, true, true); else BT_PROBE_LAUNCH(false, true, false);
+    } else {
+      if (has_salt) BT_PROBE_LAUNCH(false, false, true); else BT_PROBE_LAUNCH(false, false, false);
+    }
   }
+#undef BT_PROBE_LAUNCH
   return hipGetLastError();
 }
 
@@ -273,35 +343,70 @@ __device__ __forceinline__ bool wave_bytes_differ(const uint8_t* __restrict__ T,
   return __any(diff);
 }
 
+// Items are (key, 4 KiB chunk) pairs.  A group of G lanes (G = 64 for keys of
+// 1 KiB or more, fewer for short keys so that several keys share a wave)
+// compares one item, 16 bytes per lane per step.
+template <int G>
 __global__ __launch_bounds__(256) void k_verify(PhaseArgs a, VerifyBufs v, uint64_t cpk) {
   const uint64_t cnt = v.counts[0];
   const uint64_t items = cnt * cpk;
-  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t it = gw; it < items; it += nw) {
-    const uint64_t idx = it / cpk;
-    const uint64_t chunk = it - idx * cpk;
-    const uint32_t j = v.vlist[idx];
-    const uint64_t best = v.vbest[idx];
-    const uint64_t pos = a.lv.st[j];
-    const uint64_t L = a.k.len[j];
-    if (best < a.tx.tstart[a.lv.text[j]]) {  // hit in another text: a collision
-      if (chunk == 0 && lane_id() == 0) v.vmis[idx] = 1;
-      continue;
+  const int lane = lane_id();
+  const int sub = lane % G;
+  const uint64_t ggrp = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const uint64_t ngrp = ((uint64_t)gridDim.x * blockDim.x) / G;
+  // every lane of a wave runs the same number of iterations (the group
+  // reduction below is a wave-wide ballot)
+  const uint64_t iters = (items + ngrp - 1) / ngrp;
+  for (uint64_t k = 0; k < iters; ++k) {
+    const uint64_t it = ggrp + k * ngrp;
+    bool diff = false;
+    bool mine = false;
+    uint64_t idx = 0;
+    if (it < items) {
+      idx = it / cpk;
+      const uint64_t chunk = it - idx * cpk;
+      const uint32_t j = v.vlist[idx];
+      const uint64_t best = v.vbest[idx];
+      const uint64_t pos = a.lv.st[j];
+      const uint64_t L = a.k.len[j];
+      if (best < a.tx.tstart[a.lv.text[j]]) {  // hit in another text: a collision
+        diff = true;
+        mine = true;
+      } else {
+        const uint64_t off = chunk * kVChunk;
+        if (off < L) {
+          mine = true;
+          const uint64_t end = L - off < kVChunk ? L : off + kVChunk;
+          for (uint64_t o = off + (uint64_t)sub * 16; o < end; o += (uint64_t)G * 16) {
+            if (o + 16 <= end) {
+              const uint4 x = load16(a.T + best + o);
+              const uint4 y = load16(a.T + pos + o);
+              diff |= (x.x != y.x) | (x.y != y.y) | (x.z != y.z) | (x.w != y.w);
+            } else {
+              for (uint64_t q = o; q < end; ++q) diff |= a.T[best + q] != a.T[pos + q];
+            }
+          }
+        }
+      }
     }
-    const uint64_t off = chunk * kVChunk;
-    if (off >= L) continue;
-    const uint64_t end = L - off < kVChunk ? L : off + kVChunk;
-    if (wave_bytes_differ(a.T, best, pos, off, end) && lane_id() == 0) v.vmis[idx] = 1;
+    const uint64_t bal = __ballot(diff);
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1) << (lane - sub));
+    if (mine && sub == 0 && (bal & gmask)) v.vmis[idx] = 1;
   }
 }
 
 hipError_t launch_verify(const PhaseArgs& a, const VerifyBufs& v, uint64_t max_len,
                          hipStream_t s) {
-  const uint64_t cpk = (max_len + kVChunk - 1) / kVChunk;
-  const uint64_t items = a.lv.c * (cpk ? cpk : 1);
-  const unsigned grid = grid_for(items * 64, 256, 256 * 8);
-  k_verify<<<grid, 256, 0, s>>>(a, v, cpk ? cpk : 1);
+  const uint64_t cpk = max_len ? (max_len + kVChunk - 1) / kVChunk : 1;
+  const uint64_t items = a.lv.c * cpk;
+  // lanes per item: about one 16-byte word per lane, at least 4 lanes
+  if (max_len <= 64) {
+    k_verify<4><<<grid_for(items * 4, 256, 2048), 256, 0, s>>>(a, v, cpk);
+  } else if (max_len <= 256) {
+    k_verify<16><<<grid_for(items * 16, 256, 2048), 256, 0, s>>>(a, v, cpk);
+  } else {
+    k_verify<64><<<grid_for(items * 64, 256, 2048), 256, 0, s>>>(a, v, cpk);
+  }
   return hipGetLastError();
 }
 
