@@ -141,6 +141,8 @@ def markov_versions(total_len, base_len, versions, edit_rate, run_max, seed,
                     prev = min(m, p + l)
             pieces.append(cur[prev:])
             cur = np.concatenate(pieces)
+    if not parts:
+        return np.zeros(0, np.uint8)
     seq = np.concatenate(parts)[:total_len]
     return alphabet[seq]
 

@@ -1,0 +1,107 @@
+"""Batched builds: every text's tree from one bt_build_batch call equals the
+oracle's tree of that text (and hence bt_build's), including empty texts,
+texts shorter than a leaf, ragged lengths and texts of very different sizes
+whose levels enter the shared level loop at different steps."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import to_device, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    import paper_2512_23314_amd as bt
+    c = bt.Context(0)
+    yield c
+    c.close()
+
+
+def _concat(texts, gap=0):
+    parts, offs, o = [], [], 0
+    for T in texts:
+        offs.append(o)
+        parts.append(np.asarray(T, np.uint8))
+        o += len(T)
+        if gap:
+            parts.append(np.full(gap, 7, np.uint8))
+            o += gap
+    offs.append(o - gap if gap else o)
+    # with gaps, text i is [offs[i], offs[i] + len_i); rebuild the offsets list
+    return np.concatenate(parts) if parts else np.zeros(0, np.uint8), offs
+
+
+def _texts(seed, count):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        kind = k % 6
+        n = int(rng.choice([0, 1, 5, 15, 16, 17, 100, 1000, 4096, 5000, 30000, 70000]))
+        if kind == 0:
+            out.append(synth.dna_copies(n, max(1, n // 8), 8, 0.01, 0.001, 4, int(rng.integers(1 << 30))))
+        elif kind == 1:
+            out.append(synth.random_text(n, 4, int(rng.integers(1 << 30))))
+        elif kind == 2:
+            out.append(synth.periodic_text(n, int(rng.integers(1, 40)), int(rng.integers(1 << 30))))
+        elif kind == 3:
+            out.append(np.full(n, 65, np.uint8))
+        elif kind == 4:
+            out.append(synth.markov_versions(n, max(1, n // 5), 5, 0.01, 8, int(rng.integers(1 << 30))))
+        else:
+            out.append(synth.cfg1_text(n) if n else np.zeros(0, np.uint8))
+    return out
+
+
+@pytest.mark.parametrize("tau,leaf,s_hint", [(2, 16, 1), (4, 16, 1), (3, 4, 1), (2, 8, 32)])
+def test_batch_matches_oracle(ctx, tau, leaf, s_hint):
+    texts = _texts(tau * 100 + leaf, 36)
+    concat, offs = _concat(texts)
+    trees = ctx.build_batch(to_device(concat), offs, tau=tau, leaf_len=leaf, s_hint=s_hint)
+    assert len(trees) == len(texts)
+    for T, tr in zip(texts, trees):
+        want = oracle.build_tree(T, tau, leaf, s_hint=s_hint).canonical
+        assert tr.serialize() == want, "text of length %d differs" % len(T)
+
+
+def test_batch_with_offset_and_weak_hash(ctx):
+    """Texts start at a non-zero offset; 12-bit fingerprints make fingerprints
+    of different texts collide, which must never leak an occurrence from one
+    text into another."""
+    import paper_2512_23314_amd as bt
+    base = synth.cfg1_text(1 << 12)
+    texts = [base[:3000], base[:3000].copy(), base[500:3500], synth.random_text(2000, 4, 1), base[:1]]
+    pad = np.full(13, 9, np.uint8)
+    concat = np.concatenate([pad] + texts)
+    offs = [13]
+    for T in texts:
+        offs.append(offs[-1] + len(T))
+    for flags in (0, bt.BT_DBG_WEAK_HASH):
+        trees = ctx.build_batch(to_device(concat), offs, tau=2, leaf_len=4, debug_flags=flags)
+        for T, tr in zip(texts, trees):
+            assert tr.serialize() == oracle.build_tree(T, 2, 4).canonical
+
+
+def test_batch_equals_single_builds(ctx):
+    texts = [synth.markov_versions(n, 4096, 20, 2e-3, 16, n) for n in (65536, 100001, 250000, 9000)]
+    concat, offs = _concat(texts)
+    d = to_device(concat)
+    trees = ctx.build_batch(d, offs, sigma=96, tau=4, leaf_len=16)
+    for T, tr in zip(texts, trees):
+        single = ctx.build(to_device(T), sigma=96, tau=4, leaf_len=16)
+        assert tr.serialize() == single.serialize()
+
+
+def test_batch_access(ctx):
+    torch = torch_cuda()
+    texts = _texts(5, 12)
+    concat, offs = _concat(texts)
+    trees = ctx.build_batch(to_device(concat), offs, tau=2, leaf_len=4)
+    for T, tr in zip(texts, trees):
+        if len(T) == 0:
+            continue
+        pos = torch.arange(len(T), device="cuda:0", dtype=torch.int64).to(torch.uint64)
+        assert np.array_equal(tr.access(pos).cpu().numpy(), np.asarray(T, np.uint8))
