@@ -53,6 +53,13 @@ extern "C" {
  * the byte-verification and retry paths run; the output must not change. */
 #define BT_DBG_WEAK_HASH 1u
 
+/* ---- build flags (bt_params.flags) ---- */
+/* Also build the counters that bt_rank and bt_select need: per block and per
+ * symbol, the occurrences before the block; per pointer, the occurrences
+ * between its target block's start and its source.  Texts must be shorter than
+ * 2^32 bytes.  bt_build always sets it. */
+#define BT_WITH_RANK_SELECT 1u
+
 typedef struct bt_ctx bt_ctx;   /* device, stream, scratch pool, statistics */
 typedef struct bt_tree bt_tree; /* a finished tree, resident in device memory */
 
@@ -71,6 +78,7 @@ typedef struct bt_tree bt_tree; /* a finished tree, resident in device memory */
  *   hash_seed      seeds the Karp-Rabin base x in [2^8, 2^61-1); the tree does
  *                  not depend on it.
  *   debug_flags    BT_DBG_* bits.
+ *   flags          BT_WITH_RANK_SELECT or 0.
  * Block lengths are b_l = b1 / tau^(l-1); the tree has h = k + 1 levels and
  * level h holds the leaves.  Every block has length b_l except the one that
  * ends the text, which may be shorter.
@@ -82,7 +90,7 @@ typedef struct {
   uint64_t s_hint;
   uint64_t hash_seed;
   uint32_t debug_flags;
-  uint32_t reserved;
+  uint32_t flags;
 } bt_params;
 
 /* ---- context ---- */
@@ -183,8 +191,8 @@ BT_API int bt_serialize(const bt_tree* tree, uint8_t* dst, uint64_t cap, uint64_
  * (rank is the paper's rank_c(i) with 1-based inclusive positions; select is
  * the paper's select minus one.)  Out-of-range i, k = 0 or k > count(c) give
  * UINT64_MAX; access of an out-of-range i gives 0 and the call returns
- * BT_E_INVAL after answering the rest.  Rank and select need the tree to have
- * been built with rank support (always, for sigma <= 256). */
+ * BT_E_INVAL after answering the rest.  bt_rank and bt_select return
+ * BT_E_INVAL when the tree was built without BT_WITH_RANK_SELECT. */
 BT_API int bt_access(bt_ctx* ctx, const bt_tree* tree, const uint64_t* d_pos, uint64_t m,
               uint8_t* d_out);
 BT_API int bt_rank(bt_ctx* ctx, const bt_tree* tree, const uint8_t* d_c, const uint64_t* d_pos,

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libbt.so")
 
 BT_OK, BT_E_INVAL, BT_E_NOMEM, BT_E_DEVICE, BT_E_INTERNAL = 0, -1, -2, -3, -4
 BT_DBG_WEAK_HASH = 1
+BT_WITH_RANK_SELECT = 1
 
 _lib = None
 
@@ -34,7 +35,7 @@ class bt_params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_uint32), ("leaf_len", ctypes.c_uint32),
                 ("root_block_len", ctypes.c_uint64), ("s_hint", ctypes.c_uint64),
                 ("hash_seed", ctypes.c_uint64), ("debug_flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32)]
 
 
 # name -> (restype, argtypes); the exported surface of include/bt.h
@@ -155,8 +156,10 @@ class Context:
 
     # ---- builds
     @staticmethod
-    def params(tau, leaf_len, s_hint=1, root_block_len=0, hash_seed=0x0B10C7EE, debug_flags=0):
-        return bt_params(tau, leaf_len, root_block_len, s_hint, hash_seed, debug_flags, 0)
+    def params(tau, leaf_len, s_hint=1, root_block_len=0, hash_seed=0x0B10C7EE, debug_flags=0,
+               rank_select=False):
+        return bt_params(tau, leaf_len, root_block_len, s_hint, hash_seed, debug_flags,
+                         BT_WITH_RANK_SELECT if rank_select else 0)
 
     def build(self, text, sigma=256, tau=2, leaf_len=16, **kw):
         """Build the tree of a uint8 CUDA tensor; returns a Tree."""

@@ -205,6 +205,9 @@ struct TreeLevel {
   const uint64_t* wrank = nullptr;  // marks before each word
   const uint64_t* pb = nullptr;     // u
   const uint64_t* po = nullptr;     // u
+  const uint32_t* cnt = nullptr;    // c * S (rank/select support)
+  const uint32_t* pcnt = nullptr;   // u * S
+  const uint64_t* st = nullptr;     // c
 };
 
 struct bt_tree {
@@ -217,6 +220,12 @@ struct bt_tree {
   uint64_t leaf_bytes = 0;
   QLevel* d_levels = nullptr;  // device copy of the level table for queries
   uint64_t dev_bytes = 0;
+  // rank/select support
+  bool has_rank = false;
+  const int16_t* sym = nullptr;   // 256 entries
+  uint32_t S = 0;
+  const uint64_t* total = nullptr;
+  uint64_t tstart = 0;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -417,7 +426,7 @@ uint64_t pow2_at_least(uint64_t v) {
 
 // Per-text, per-level bookkeeping collected on the host.
 struct TextLevelRec {
-  uint64_t b, c, u, word_off, ptr_off;
+  uint64_t b, c, u, word_off, ptr_off, first;
 };
 
 struct LevelBufs {
@@ -425,6 +434,9 @@ struct LevelBufs {
   uint64_t* wrank;
   uint64_t* pb;
   uint64_t* po;
+  uint32_t* cnt;
+  uint32_t* pcnt;
+  uint64_t* st;
 };
 
 int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& offs,
@@ -479,10 +491,31 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   upload(ctx, d_tx.p, h_tx.data(), 3 * (uint64_t)T);
   TextsDev tx{T, d_tx.p, d_tx.p + T, d_tx.p + 2 * T};
 
-  // ---- distinct byte values must not exceed sigma
+  // ---- distinct byte values must not exceed sigma; dense symbols for rank/select
   Buf<uint64_t> d_hist = alloc<uint64_t>(ctx, 256);
   HIPCHK(ctx, launch_fill_u64(d_hist.p, 0, 256, s));
   HIPCHK(ctx, launch_histogram(d_base + o0, N, d_hist.p, s));
+  std::vector<uint64_t> hist;
+  read_words(ctx, {{d_hist.p, 256}}, hist);
+  uint32_t S = 0;
+  std::vector<int16_t> h_sym(256, -1);
+  std::vector<uint8_t> h_byte_of;
+  for (int ch = 0; ch < 256; ++ch)
+    if (hist[ch]) {
+      h_sym[ch] = (int16_t)S++;
+      h_byte_of.push_back((uint8_t)ch);
+    }
+  if (S > sigma) {
+    ctx->err = "the text has " + std::to_string(S) + " distinct byte values, more than sigma";
+    return BT_E_INVAL;
+  }
+  const bool with_rank = (prm.flags & BT_WITH_RANK_SELECT) != 0;
+  if (with_rank)
+    for (uint32_t t = 0; t < T; ++t)
+      if (h_n[t] >= (1ull << 32)) {
+        ctx->err = "rank/select support needs texts shorter than 2^32 bytes";
+        return BT_E_INVAL;
+      }
 
   // ---- step a2: prefix fingerprints of the concatenation, once
   Buf<uint64_t> d_P = alloc<uint64_t>(ctx, N + 1);
@@ -498,10 +531,39 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   });
   const uint64_t* P = d_P.p - o0;  // P[i] belongs to text position i; never read below o0
 
-  // ---- outputs
-  std::vector<std::vector<TextLevelRec>> rec(T);
   auto store = std::make_shared<Storage>();
   store->pool = ctx->pool;
+
+  // ---- rank/select support: sampled count table and per-text counts
+  RankCtx rc{};
+  Buf<uint64_t> d_G, d_Rt;
+  uint64_t* d_Rtot = nullptr;
+  int16_t* d_sym = nullptr;
+  if (with_rank && S) {
+    Buf<int16_t> sym = alloc<int16_t>(ctx, 256);
+    upload(ctx, sym.p, h_sym.data(), 256);
+    Buf<uint8_t> byte_of = alloc<uint8_t>(ctx, S);
+    upload(ctx, byte_of.p, h_byte_of.data(), S);
+    const uint64_t K = (N + kRankQ - 1) / kRankQ;
+    const uint64_t nblk = (K + 1023) / 1024;
+    Buf<uint32_t> H = alloc<uint32_t>(ctx, std::max<uint64_t>(K, 1) * S);
+    Buf<uint64_t> B = alloc<uint64_t>(ctx, std::max<uint64_t>(nblk, 1) * S);
+    d_G = alloc<uint64_t>(ctx, (K + 1) * S);
+    HIPCHK(ctx, launch_fill_u64(d_G.p, 0, S, s));
+    HIPCHK(ctx, build_count_table(d_base, o0, N, sym.p, S, H.p, B.p, d_G.p, s));
+    rc = RankCtx{d_base, o0, d_G.p, S, byte_of.p};
+    d_Rt = alloc<uint64_t>(ctx, (uint64_t)T * S);
+    Buf<uint64_t> Rtot = alloc<uint64_t>(ctx, (uint64_t)T * S);
+    HIPCHK(ctx, launch_text_rank_counts(rc, tx, d_Rt.p, Rtot.p, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    d_Rtot = store->add(std::move(Rtot), (uint64_t)T * S);
+    d_sym = store->add(std::move(sym), 256);
+    store->add(std::move(byte_of), S);
+  }
+  const bool rank_on = with_rank && S;
+
+  // ---- outputs
+  std::vector<std::vector<TextLevelRec>> rec(T);
   std::vector<LevelBufs> lbufs;
   uint8_t* leaves = nullptr;
   std::vector<uint64_t> leaf_off(T, 0), leaf_bytes(T, 0);
@@ -576,6 +638,16 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       Buf<uint8_t> lb = alloc<uint8_t>(ctx, c * b);
       HIPCHK(ctx, launch_leaves(d_base, lv, tx, lb.p, s));
       leaves = store->add(std::move(lb), c * b);
+      LevelBufs LL{};
+      if (rank_on) {
+        Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
+        HIPCHK(ctx, launch_block_rank_counts(rc, st.p, text.p, c, d_Rt.p, cnt.p, s));
+        Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
+        if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st.p, c * 8, hipMemcpyDeviceToDevice, s));
+        LL.cnt = store->add(std::move(cnt), c * S);
+        LL.st = store->add(std::move(stc), c);
+      }
+      lbufs.push_back(LL);
       Buf<uint64_t> d_last = alloc<uint64_t>(ctx, T);
       HIPCHK(ctx, launch_last_block_len(lv, tx, d_tfirst.p, d_tcount.p, d_last.p, s));
       std::vector<uint64_t> last;
@@ -583,7 +655,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       for (uint32_t t = 0; t < T; ++t) {
         leaf_off[t] = h_tfirst[t] * b;
         leaf_bytes[t] = h_tcount[t] ? (h_tcount[t] - 1) * b + last[t] : 0;
-        rec[t].push_back({b, h_tcount[t], 0, 0, 0});
+        rec[t].push_back({b, h_tcount[t], 0, 0, 0, h_tfirst[t]});
       }
       break;
     }
@@ -712,10 +784,25 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       HIPCHK(ctx, hipMemcpyAsync(spb.p, pb.p, u * 8, hipMemcpyDeviceToDevice, s));
       HIPCHK(ctx, hipMemcpyAsync(spo.p, po.p, u * 8, hipMemcpyDeviceToDevice, s));
     }
-    lbufs.push_back({store->add(std::move(words), nwords), store->add(std::move(wrank), nwords + 1),
-                     store->add(std::move(spb), u), store->add(std::move(spo), u)});
+    LevelBufs LB{store->add(std::move(words), nwords), store->add(std::move(wrank), nwords + 1),
+                 store->add(std::move(spb), u), store->add(std::move(spo), u), nullptr, nullptr,
+                 nullptr};
+    if (rank_on) {
+      Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
+      Buf<uint32_t> pcnt = alloc<uint32_t>(ctx, u * S);
+      Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
+      HIPCHK(ctx, launch_block_rank_counts(rc, st.p, text.p, c, d_Rt.p, cnt.p, s));
+      HIPCHK(ctx, launch_pointer_rank_counts(rc, st.p, text.p, marked.p, c, uoff.p, d_tfirst.p,
+                                             pb.p, po.p, d_Rt.p, cnt.p, pcnt.p, s));
+      if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st.p, c * 8, hipMemcpyDeviceToDevice, s));
+      LB.cnt = store->add(std::move(cnt), c * S);
+      LB.pcnt = store->add(std::move(pcnt), u * S);
+      LB.st = store->add(std::move(stc), c);
+    }
+    lbufs.push_back(LB);
     for (uint32_t t = 0; t < T; ++t)
-      if (H - plan[t].h <= step) rec[t].push_back({b, h_tcount[t], h_tu[t], h_woff[t], h_poff[t]});
+      if (H - plan[t].h <= step)
+        rec[t].push_back({b, h_tcount[t], h_tu[t], h_woff[t], h_poff[t], h_tfirst[t]});
 
     // ---- next level's blocks
     uint64_t cn = 0;
@@ -738,16 +825,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   }
 
   std::vector<uint64_t> fin;
-  read_words(ctx, {{d_err.p, 1}, {d_hist.p, 256}}, fin);
+  read_words(ctx, {{d_err.p, 1}}, fin);
   if (fin[0]) {
     ctx->err = "device check failed: a pointer does not target a marked block or pair";
     return BT_E_INTERNAL;
-  }
-  uint32_t distinct = 0;
-  for (int ch = 0; ch < 256; ++ch) distinct += fin[1 + ch] != 0;
-  if (distinct > sigma) {
-    ctx->err = "the text has " + std::to_string(distinct) + " distinct byte values, more than sigma";
-    return BT_E_INVAL;
   }
 
   // ---- trees
@@ -772,12 +853,26 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       tl.wrank = L.wrank + r.word_off;
       tl.pb = L.pb + r.ptr_off;
       tl.po = L.po + r.ptr_off;
+      if (rank_on) {
+        tl.cnt = L.cnt + r.first * S;
+        tl.pcnt = L.pcnt + r.ptr_off * S;
+        tl.st = L.st + r.first;
+      }
       tr->lv.push_back(tl);
     }
     TreeLevel leafl;
     leafl.b = rec[t].back().b;
     leafl.c = rec[t].back().c;
+    if (rank_on) {
+      leafl.cnt = lbufs.back().cnt + rec[t].back().first * S;
+      leafl.st = lbufs.back().st + rec[t].back().first;
+    }
     tr->lv.push_back(leafl);
+    tr->has_rank = with_rank;
+    tr->sym = d_sym;
+    tr->S = S;
+    tr->total = d_Rtot ? d_Rtot + (uint64_t)t * S : nullptr;
+    tr->tstart = h_n[t] ? offs[t] : offs[t];
     tr->leaves = leaves + leaf_off[t];
     tr->leaf_bytes = leaf_bytes[t];
     tr->dev_bytes = store->bytes / T;
@@ -804,7 +899,7 @@ void ensure_qtree(bt_ctx* ctx, const bt_tree* ct) {
   std::vector<QLevel> h(t->h);
   for (uint32_t l = 0; l < t->h; ++l) {
     const TreeLevel& L = t->lv[l];
-    h[l] = QLevel{L.b, L.c, L.words, L.wrank, L.pb, L.po, nullptr, nullptr};
+    h[l] = QLevel{L.b, L.c, L.words, L.wrank, L.pb, L.po, L.cnt, L.pcnt, L.st};
   }
   Buf<QLevel> d = alloc<QLevel>(ctx, t->h);
   QLevel* staging = nullptr;
@@ -826,6 +921,10 @@ QTree qtree_of(const bt_tree* t) {
   q.n = t->n;
   q.leaves = t->leaves;
   q.leaf_len = t->leaf;
+  q.sym = t->sym;
+  q.S = t->S;
+  q.total = t->total;
+  q.tstart = t->tstart;
   return q;
 }
 
@@ -948,6 +1047,7 @@ int bt_build(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma, uin
   p.leaf_len = leaf_len;
   p.s_hint = 1;
   p.hash_seed = 0x0B10C7EEull;
+  p.flags = BT_WITH_RANK_SELECT;
   return bt_build_ex(ctx, d_text, n, sigma, &p, out);
 }
 
@@ -1080,16 +1180,43 @@ int bt_access(bt_ctx* ctx, const bt_tree* t, const uint64_t* d_pos, uint64_t m, 
 
 int bt_rank(bt_ctx* ctx, const bt_tree* t, const uint8_t* d_c, const uint64_t* d_pos, uint64_t m,
             uint64_t* d_out) {
-  (void)d_c; (void)d_pos; (void)m; (void)d_out; (void)t;
-  if (ctx) ctx->err = "bt_rank: not available in this build";
-  return BT_E_INVAL;
+  if (!ctx || !t || (m && (!d_c || !d_pos || !d_out))) return BT_E_INVAL;
+  if (!t->has_rank) {
+    ctx->err = "bt_rank: the tree was built without BT_WITH_RANK_SELECT";
+    return BT_E_INVAL;
+  }
+  return guarded(ctx, [&] {
+    HIPCHK(ctx, hipSetDevice(ctx->dev));
+    if (t->n == 0 || t->S == 0) {
+      // empty text: rank(c, 0) = 0, anything else is out of range
+      HIPCHK(ctx, launch_rank_empty(d_pos, m, d_out, ctx->stream));
+    } else {
+      ensure_qtree(ctx, t);
+      HIPCHK(ctx, launch_rank(qtree_of(t), d_c, d_pos, m, d_out, ctx->stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return BT_OK;
+  });
 }
 
 int bt_select(bt_ctx* ctx, const bt_tree* t, const uint8_t* d_c, const uint64_t* d_k, uint64_t m,
               uint64_t* d_out) {
-  (void)d_c; (void)d_k; (void)m; (void)d_out; (void)t;
-  if (ctx) ctx->err = "bt_select: not available in this build";
-  return BT_E_INVAL;
+  if (!ctx || !t || (m && (!d_c || !d_k || !d_out))) return BT_E_INVAL;
+  if (!t->has_rank) {
+    ctx->err = "bt_select: the tree was built without BT_WITH_RANK_SELECT";
+    return BT_E_INVAL;
+  }
+  return guarded(ctx, [&] {
+    HIPCHK(ctx, hipSetDevice(ctx->dev));
+    if (t->n == 0 || t->S == 0) {
+      HIPCHK(ctx, launch_fill_u64(d_out, ~0ull, m, ctx->stream));
+    } else {
+      ensure_qtree(ctx, t);
+      HIPCHK(ctx, launch_select(qtree_of(t), d_c, d_k, m, d_out, ctx->stream));
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return BT_OK;
+  });
 }
 
 int bt_tree_device_bytes(const bt_tree* t, uint64_t* bytes) {

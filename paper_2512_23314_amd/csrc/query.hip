@@ -90,6 +90,135 @@ hipError_t launch_access(QTree t, const uint64_t* pos, uint64_t m, uint8_t* out,
   return hipGetLastError();
 }
 
+// rank(c, i): the same walk as access; every pointer followed from block j
+// (unmarked number u, target t) adds cnt[j] - cnt[t] - pcnt[u], i.e. the count
+// before block j minus the count before the source position; at the leaf the
+// leaf's own count and the bytes before the offset are added.
+__global__ void k_rank(QTree q, const uint8_t* __restrict__ cs, const uint64_t* __restrict__ pos,
+                       uint64_t m, uint64_t* __restrict__ out) {
+  const uint32_t S = q.S;
+  GRID_STRIDE(k, m) {
+    const uint64_t i = pos[k];
+    const uint8_t ch = cs[k];
+    const int s = q.sym[ch];
+    if (i > q.n) {
+      out[k] = ~0ull;
+      continue;
+    }
+    if (s < 0) {
+      out[k] = 0;
+      continue;
+    }
+    if (i == q.n) {
+      out[k] = q.total[s];
+      continue;
+    }
+    int64_t acc = 0;
+    uint64_t leaf, o;
+    descend(q, i, leaf, o,
+            [&](uint32_t l, uint64_t j, uint64_t u, uint64_t t, uint64_t, uint64_t) {
+              const QLevel& L = q.lv[l];
+              acc += (int64_t)L.cnt[j * S + s] - (int64_t)L.cnt[t * S + s] -
+                     (int64_t)L.pcnt[u * S + s];
+            });
+    acc += q.lv[q.h - 1].cnt[leaf * S + s];
+    const uint8_t* lb = q.leaves + leaf * q.leaf_len;
+    for (uint64_t r = 0; r < o; ++r) acc += lb[r] == ch;
+    out[k] = (uint64_t)acc;
+  }
+}
+
+hipError_t launch_rank(QTree t, const uint8_t* cs, const uint64_t* pos, uint64_t m, uint64_t* out,
+                       hipStream_t s) {
+  if (!m) return hipSuccess;
+  k_rank<<<grid_for(m, 256), 256, 0, s>>>(t, cs, pos, m, out);
+  return hipGetLastError();
+}
+
+// select(c, k): keep the invariant cnt[j] < k <= cnt[j] + (occurrences in
+// block j).  Level 1: binary search over the blocks.  Marked block: the last
+// child whose count is below k.  Unmarked block j with pointer (t, off): the
+// wanted occurrence is the (k - cnt[j])-th inside the block, i.e. occurrence
+// k' = cnt[t] + pcnt[u] + (k - cnt[j]) of the source, which lies in block t or
+// t+1; the answer moves by (start of j) - (source position).  At the leaf,
+// scan its bytes.
+__global__ void k_select(QTree q, const uint8_t* __restrict__ cs, const uint64_t* __restrict__ ks,
+                         uint64_t m, uint64_t* __restrict__ out) {
+  const uint32_t S = q.S;
+  GRID_STRIDE(qi, m) {
+    const uint8_t ch = cs[qi];
+    uint64_t k = ks[qi];
+    const int s = q.sym[ch];
+    if (s < 0 || k == 0 || k > q.total[s]) {
+      out[qi] = ~0ull;
+      continue;
+    }
+    const QLevel* lv = q.lv;
+    uint64_t lo = 0, hi = lv[0].c;
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (lv[0].cnt[mid * S + s] < k) lo = mid; else hi = mid;
+    }
+    uint64_t j = lo;
+    uint32_t l = 0;
+    uint64_t shift = 0;
+    while (l + 1 < q.h) {
+      const QLevel& L = lv[l];
+      const uint64_t r1 = marks_before(L, j);
+      if (is_marked(L, j)) {
+        const QLevel& N = lv[l + 1];
+        const uint64_t j0 = r1 * q.tau;
+        uint64_t nch = N.c - j0;
+        if (nch > q.tau) nch = q.tau;
+        uint64_t x = 1;
+        while (x < nch && N.cnt[(j0 + x) * S + s] < k) ++x;
+        j = j0 + x - 1;
+        ++l;
+      } else {
+        const uint64_t u = j - r1;
+        const uint64_t t = L.pb[u];
+        const uint64_t src = L.st[t] + L.po[u];
+        const uint64_t k2 = (uint64_t)L.cnt[t * S + s] + L.pcnt[u * S + s] + (k - L.cnt[j * S + s]);
+        shift += L.st[j] - src;
+        uint64_t nt = t;
+        if (t + 1 < L.c && L.st[t + 1] == L.st[t] + L.b && L.cnt[(t + 1) * S + s] < k2) nt = t + 1;
+        j = nt;
+        k = k2;
+      }
+    }
+    const QLevel& LH = lv[q.h - 1];
+    uint64_t need = k - LH.cnt[j * S + s];
+    const uint8_t* lb = q.leaves + j * q.leaf_len;
+    uint64_t res = ~0ull;
+    const uint64_t rest = q.tstart + q.n - LH.st[j];
+    const uint64_t llen = rest < q.leaf_len ? rest : q.leaf_len;
+    for (uint64_t o = 0; o < llen; ++o) {
+      if (lb[o] == ch && --need == 0) {
+        res = LH.st[j] + o + shift - q.tstart;
+        break;
+      }
+    }
+    out[qi] = res;
+  }
+}
+
+hipError_t launch_select(QTree t, const uint8_t* cs, const uint64_t* ks, uint64_t m, uint64_t* out,
+                         hipStream_t s) {
+  if (!m) return hipSuccess;
+  k_select<<<grid_for(m, 256), 256, 0, s>>>(t, cs, ks, m, out);
+  return hipGetLastError();
+}
+
+__global__ void k_rank_empty(const uint64_t* pos, uint64_t m, uint64_t* out) {
+  GRID_STRIDE(k, m) out[k] = pos[k] == 0 ? 0 : ~0ull;
+}
+
+hipError_t launch_rank_empty(const uint64_t* pos, uint64_t m, uint64_t* out, hipStream_t s) {
+  if (!m) return hipSuccess;
+  k_rank_empty<<<grid_for(m, 256), 256, 0, s>>>(pos, m, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- auxiliary
 
 __global__ void k_histogram(const uint8_t* __restrict__ T, uint64_t n, uint64_t* hist) {

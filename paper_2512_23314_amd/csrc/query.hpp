@@ -17,10 +17,11 @@ struct QLevel {
   const uint64_t* wrank;   // marks before each word (within this tree)
   const uint64_t* pb;      // pointer block (level-local), one per unmarked block
   const uint64_t* po;      // pointer offset
-  // rank/select support (see query.hip)
-  const uint64_t* cnt;     // [c * S]: occurrences of each symbol before the block start
-  const uint64_t* pcnt;    // [u * S]: occurrences of each symbol in the target pair
-                           //           before the source position
+  // rank/select support (rank.hip); null when the tree was built without it
+  const uint32_t* cnt;     // [c * S]: occurrences of each symbol before the block
+  const uint32_t* pcnt;    // [u * S]: occurrences between the target block's start
+                           //          and the source position
+  const uint64_t* st;      // [c] block starts (positions in the build's buffer)
 };
 
 struct QTree {
@@ -30,10 +31,32 @@ struct QTree {
   uint64_t n;
   const uint8_t* leaves;   // leaf block j at j * leaf_len
   uint64_t leaf_len;
-  const int16_t* sym;      // byte -> dense symbol (-1 = absent)
+  const int16_t* sym;      // byte -> dense symbol (-1 = absent), 256 entries
   uint32_t S;              // dense alphabet size
-  const uint64_t* leafcnt; // [c_h * S] occurrences before each leaf block
+  const uint64_t* total;   // [S] occurrences in the whole text
+  uint64_t tstart;         // position of the text in the build's buffer
 };
+
+// Rank support construction.
+constexpr uint64_t kRankQ = 1024;  // sampling interval of the count table
+struct RankCtx {
+  const uint8_t* T;        // the build's buffer
+  uint64_t o0;             // first position covered by the table
+  const uint64_t* G;       // [(K + 1) * S] counts before each sampled position
+  uint32_t S;
+  const uint8_t* byte_of;  // [S] dense symbol -> byte
+};
+hipError_t build_count_table(const uint8_t* T, uint64_t o0, uint64_t N, const int16_t* sym,
+                             uint32_t S, uint32_t* H, uint64_t* B, uint64_t* G, hipStream_t s);
+hipError_t launch_text_rank_counts(const RankCtx& rc, const TextsDev& tx, uint64_t* Rt,
+                                   uint64_t* Rtot, hipStream_t s);
+hipError_t launch_block_rank_counts(const RankCtx& rc, const uint64_t* st, const uint32_t* text,
+                                    uint64_t c, const uint64_t* Rt, uint32_t* cnt, hipStream_t s);
+hipError_t launch_pointer_rank_counts(const RankCtx& rc, const uint64_t* st, const uint32_t* text,
+                                      const uint8_t* marked, uint64_t c, const uint64_t* uoff,
+                                      const uint64_t* tfirst, const uint64_t* pb,
+                                      const uint64_t* po, const uint64_t* Rt, const uint32_t* cnt,
+                                      uint32_t* pcnt, hipStream_t s);
 
 hipError_t launch_access(QTree t, const uint64_t* pos, uint64_t m, uint8_t* out, uint32_t* bad,
                          hipStream_t s);
@@ -41,6 +64,8 @@ hipError_t launch_rank(QTree t, const uint8_t* cs, const uint64_t* pos, uint64_t
                        hipStream_t s);
 hipError_t launch_select(QTree t, const uint8_t* cs, const uint64_t* ks, uint64_t m,
                          uint64_t* out, hipStream_t s);
+// rank on an empty text: 0 for position 0, UINT64_MAX otherwise
+hipError_t launch_rank_empty(const uint64_t* pos, uint64_t m, uint64_t* out, hipStream_t s);
 
 // auxiliary kernels used by the build
 hipError_t launch_histogram(const uint8_t* T, uint64_t n, uint64_t* hist, hipStream_t s);
