@@ -575,6 +575,12 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   uint64_t c = 0;
   Buf<uint64_t> st;
   Buf<uint32_t> text;
+  // scan entries of the current level (from the previous level's split; see
+  // "scan segments" in level.hip); E_ent = 0 means "one entry per run"
+  uint64_t E_ent = 0;
+  Buf<uint64_t> ent_a, ent_e, ent_child;
+  Buf<uint8_t> ent_f;
+  bool have_entries = false;
   std::vector<uint64_t> h_tcount(T, 0), h_tfirst(T + 1, 0);
   Buf<uint64_t> d_tcount = alloc<uint64_t>(ctx, T + 1), d_tfirst = alloc<uint64_t>(ctx, T + 1);
   Buf<uint64_t> scan_tmp;
@@ -633,6 +639,20 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint32_t> rtext = alloc<uint32_t>(ctx, R);
     HIPCHK(ctx, launch_run_table(st.p, text.p, c, b, tx, roff.p, run.p, rs.p, re.p, rtext.p, s));
     LevelDev lv{c, b, st.p, text.p, run.p, R, rs.p, re.p, rtext.p};
+    Buf<uint32_t> ent_run;
+    if (!leaf_step) {
+      if (!have_entries) {
+        E_ent = R;
+        ent_a = alloc<uint64_t>(ctx, R);
+        ent_e = alloc<uint64_t>(ctx, R);
+        ent_f = alloc<uint8_t>(ctx, R);
+        ent_run = alloc<uint32_t>(ctx, R);
+        HIPCHK(ctx, launch_entries_from_runs(lv, ent_a.p, ent_e.p, ent_f.p, ent_run.p, s));
+      } else {
+        ent_run = alloc<uint32_t>(ctx, E_ent);
+        HIPCHK(ctx, launch_entry_runs(ent_child.p, E_ent, run.p, ent_run.p, s));
+      }
+    }
 
     if (leaf_step) {
       Buf<uint8_t> lb = alloc<uint8_t>(ctx, c * b);
@@ -671,7 +691,11 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
                   klm = alloc<uint64_t>(ctx, c);
     Buf<uint32_t> kslot = alloc<uint32_t>(ctx, c);
     Buf<uint64_t> oddb = alloc<uint64_t>(ctx, 6 * (uint64_t)T);
-    Buf<uint64_t> woff = alloc<uint64_t>(ctx, R + 1);
+    Buf<uint64_t> woff = alloc<uint64_t>(ctx, E_ent + 1);
+    Buf<uint64_t> seg_ws = alloc<uint64_t>(ctx, E_ent), seg_re = alloc<uint64_t>(ctx, E_ent);
+    Buf<uint32_t> seg_text = alloc<uint32_t>(ctx, E_ent);
+    SegDev sg{E_ent, ent_a.p, ent_e.p, ent_f.p, ent_run.p, seg_ws.p, seg_re.p, seg_text.p};
+    Buf<uint8_t> facts = alloc<uint8_t>(ctx, c);
     Buf<uint32_t> vlist = alloc<uint32_t>(ctx, c), vmis = alloc<uint32_t>(ctx, c),
                   rlist = alloc<uint32_t>(ctx, c);
     Buf<uint64_t> vbest = alloc<uint64_t>(ctx, c), rlb = alloc<uint64_t>(ctx, c),
@@ -714,12 +738,17 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       HIPCHK(ctx, launch_fill_u64(vcnt.p, 0, 2, s));
       if (use_filter) HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
       HIPCHK(ctx, launch_keys(a, s));
-      HIPCHK(ctx, launch_window_counts(a, woff.p, s));
-      scan(woff.p, R);
+      HIPCHK(ctx, launch_segments(a, sg, woff.p, s));
+      scan(woff.p, E_ent);
       uint64_t* wst = wstats.p + 2 * step + (phase - 1);
-      HIPCHK(ctx, hipMemcpyAsync(wst, woff.p + R, 8, hipMemcpyDeviceToDevice, s));
+      HIPCHK(ctx, hipMemcpyAsync(wst, woff.p + E_ent, 8, hipMemcpyDeviceToDevice, s));
+      PhaseArgs as = a;  // the scan walks segments in place of runs
+      as.lv.R = E_ent;
+      as.lv.rs = seg_ws.p;
+      as.lv.re = seg_re.p;
+      as.lv.rtext = seg_text.p;
       timed(ctx, "probe_scan", 0, 0, wst, 16.0, [&] {
-        return launch_probe_scan(a, woff.p, has_odd, has_salt, c * b, use_filter, s);
+        return launch_probe_scan(as, woff.p, has_odd, has_salt, c * b, use_filter, s);
       });
       HIPCHK(ctx, launch_resolve(a, vb, s));
       timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });
@@ -728,8 +757,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     };
 
     // ---- phase 1: pairs (a3, a4) and marks (a5)
+    a.all_blocks = 0;
     run_phase(1, c - R);
     HIPCHK(ctx, launch_mark(a, marked.p, s));
+    HIPCHK(ctx, launch_pair_facts(a, facts.p, s));
 
     // ---- phase 2: unmarked blocks (a6) and pointers (a7)
     Buf<uint64_t> uoff = alloc<uint64_t>(ctx, c + 1);
@@ -737,7 +768,13 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     scan(uoff.p, c);
     std::vector<uint64_t> uu;
     read_words(ctx, {{uoff.p + c, 1}}, uu);
-    run_phase(2, uu[0]);
+    // When most blocks are unmarked the phase-2 scan costs the same with a key
+    // for every block; the leftmost occurrences of the marked blocks then tell
+    // the next level which windows are copies.  Not worth it before the last
+    // scanned level.
+    a.all_blocks = (4 * uu[0] >= c && step + 2 < H) ? 1 : 0;
+    run_phase(2, a.all_blocks ? c : uu[0]);
+    if (a.all_blocks) HIPCHK(ctx, launch_block_facts(a, facts.p, s));
     Buf<uint64_t> pb = alloc<uint64_t>(ctx, c), po = alloc<uint64_t>(ctx, c);
     HIPCHK(ctx, launch_pointers(a, marked.p, uoff.p, d_tfirst.p, pb.p, po.p,
                                 reinterpret_cast<uint32_t*>(d_err.p), s));
@@ -815,6 +852,22 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     upload(ctx, d_ids.p, ids.data(), ids.size());
     HIPCHK(ctx, launch_write_entering(d_ids.p, (uint32_t)ids.size(), tx, bn, ntfirst.p, nst.p,
                                       ntext.p, s));
+    {
+      const uint64_t nmarked = c - u;
+      const uint64_t En = nmarked + ids.size();
+      Buf<uint64_t> na = alloc<uint64_t>(ctx, En), ne = alloc<uint64_t>(ctx, En),
+                    nchild = alloc<uint64_t>(ctx, En);
+      Buf<uint8_t> nf = alloc<uint8_t>(ctx, En);
+      HIPCHK(ctx, launch_entries_next(lv, tx, marked.p, facts.p, uoff.p, cs.p, d_tfirst.p,
+                                      ntfirst.p, nmarked, d_ids.p, (uint32_t)ids.size(), na.p,
+                                      ne.p, nf.p, nchild.p, s));
+      E_ent = En;
+      ent_a = std::move(na);
+      ent_e = std::move(ne);
+      ent_f = std::move(nf);
+      ent_child = std::move(nchild);
+      have_entries = true;
+    }
     HIPCHK(ctx, hipMemcpyAsync(d_tcount.p, ntcount.p, T * 8, hipMemcpyDeviceToDevice, s));
     HIPCHK(ctx, hipMemcpyAsync(d_tfirst.p, ntfirst.p, (T + 1) * 8, hipMemcpyDeviceToDevice, s));
     h_tcount = h_ntcount;

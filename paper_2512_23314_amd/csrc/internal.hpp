@@ -90,6 +90,21 @@ struct PhaseArgs {
   uint32_t* filt;   // bit filter of the main-length keys' fingerprints
   uint32_t filt_bits;  // log2 of its size in bits (12..18); 0 = no filter
   uint32_t filt_two;   // 1: two bits per key, 0: one
+  uint32_t all_blocks; // phase 2: keys for every block, not only unmarked ones
+};
+
+// Scan entries and segments (level.hip, "scan segments").
+constexpr uint8_t kSkipInterior = 1;  // windows ending inside the entry are copies
+constexpr uint8_t kSkipCross = 2;     // every window starting in the entry is a copy
+struct SegDev {
+  uint64_t E;             // entries
+  const uint64_t* ea;     // [E] entry start
+  const uint64_t* ee;     // [E] entry end
+  const uint8_t* ef;      // [E] kSkip* flags
+  const uint32_t* erun;   // [E] run of the entry
+  uint64_t* ws;           // [E] first window start of the segment
+  uint64_t* sre;          // [E] run end
+  uint32_t* stext;        // [E] text
 };
 
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
@@ -103,8 +118,19 @@ hipError_t scan_excl_u64(uint64_t* a, uint64_t n, uint64_t* tmp, hipStream_t s);
 
 // Phase kernels (steps a3-a7).
 hipError_t launch_keys(const PhaseArgs& a, hipStream_t s);
-// Per-run window counts into woff[0..R) (then scanned by the caller).
-hipError_t launch_window_counts(const PhaseArgs& a, uint64_t* woff, hipStream_t s);
+hipError_t launch_entries_from_runs(const LevelDev& lv, uint64_t* ea, uint64_t* ee, uint8_t* ef,
+                                    uint32_t* erun, hipStream_t s);
+hipError_t launch_pair_facts(const PhaseArgs& a, uint8_t* pf, hipStream_t s);
+hipError_t launch_block_facts(const PhaseArgs& a, uint8_t* pf, hipStream_t s);
+hipError_t launch_entries_next(const LevelDev& lv, const TextsDev& tx, const uint8_t* marked,
+                               const uint8_t* pf, const uint64_t* uoff, const uint64_t* cs,
+                               const uint64_t* tfirst, const uint64_t* ntfirst, uint64_t nmarked,
+                               const uint32_t* ids, uint32_t E, uint64_t* ea, uint64_t* ee,
+                               uint8_t* ef, uint64_t* echild, hipStream_t s);
+hipError_t launch_entry_runs(const uint64_t* echild, uint64_t E, const uint32_t* run,
+                             uint32_t* erun, hipStream_t s);
+// Per-segment window counts into woff[0..E) (then scanned by the caller).
+hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff, hipStream_t s);
 // The sliding-window probe.  max_windows bounds the grid; filter selects the
 // variant that tests an LDS key filter before the table.
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,

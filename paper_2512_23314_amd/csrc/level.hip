@@ -53,7 +53,7 @@ __global__ void k_keys(PhaseArgs a) {
       valid = (j + 1 < lv.c) && lv.run[j + 1] == lv.run[j];
       if (valid) L = len + block_len(lv, a.tx, j + 1);
     } else {
-      valid = !a.marked[j];
+      valid = a.all_blocks || !a.marked[j];
       L = len;
     }
     if (!valid) {
@@ -100,21 +100,155 @@ hipError_t launch_keys(const PhaseArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- windows per run
+// ---------------------------------------------------------------- scan segments
+//
+// The probe scan walks "segments": ranges of window starts, each inside one run.
+// A window whose content also occurs earlier can never be the leftmost
+// occurrence of anything, so the previous level's results prune segments.  For
+// a marked parent block P (all windows of this level start inside some parent):
+//   - if the pair (P, P+1) has an earlier occurrence, every window starting in
+//     P lies inside a copy of it (windows are at most one parent long);
+//   - if the pair (P-1, P) has an earlier occurrence, or P itself does, every
+//     window that ends inside P is a copy.
+// Entries describe parents (or whole runs where there is no parent level) as
+// [a, e) plus these two facts; per phase they become segments.
 
-__global__ void k_window_counts(PhaseArgs a, uint64_t* woff) {
-  GRID_STRIDE(r, a.lv.R) {
-    const uint32_t t = a.lv.rtext[r];
-    const uint64_t len = a.lv.re[r] - a.lv.rs[r];
-    uint64_t Lmin = a.Lmain;
-    const uint64_t oL = a.odd.L[t];
-    if (oL && oL < Lmin) Lmin = oL;
-    woff[r] = (a.odd.nkeys[t] && len >= Lmin) ? len - Lmin + 1 : 0;
+// Entries from runs: the whole run, nothing skipped.
+__global__ void k_entries_from_runs(LevelDev lv, uint64_t* ea, uint64_t* ee, uint8_t* ef,
+                                    uint32_t* erun) {
+  GRID_STRIDE(r, lv.R) {
+    ea[r] = lv.rs[r];
+    ee[r] = lv.re[r];
+    ef[r] = 0;
+    erun[r] = (uint32_t)r;
   }
 }
 
-hipError_t launch_window_counts(const PhaseArgs& a, uint64_t* woff, hipStream_t s) {
-  k_window_counts<<<grid_for(a.lv.R, 256), 256, 0, s>>>(a, woff);
+hipError_t launch_entries_from_runs(const LevelDev& lv, uint64_t* ea, uint64_t* ee, uint8_t* ef,
+                                    uint32_t* erun, hipStream_t s) {
+  if (!lv.R) return hipSuccess;
+  k_entries_from_runs<<<grid_for(lv.R, 256), 256, 0, s>>>(lv, ea, ee, ef, erun);
+  return hipGetLastError();
+}
+
+// Pair facts after phase 1: bit 0 of pf[j] = the pair (j, j+1) occurs earlier.
+__global__ void k_pair_facts(PhaseArgs a, uint8_t* pf) {
+  GRID_STRIDE(j, a.lv.c) {
+    pf[j] = (a.k.slot[j] != kNoKey && a.k.lm[j] < a.lv.st[j]) ? 1 : 0;
+  }
+}
+
+hipError_t launch_pair_facts(const PhaseArgs& a, uint8_t* pf, hipStream_t s) {
+  k_pair_facts<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, pf);
+  return hipGetLastError();
+}
+
+// Block facts after a phase 2 over all blocks: bit 1 = block j occurs earlier.
+__global__ void k_block_facts(PhaseArgs a, uint8_t* pf) {
+  GRID_STRIDE(j, a.lv.c) {
+    if (a.k.slot[j] != kNoKey && a.k.lm[j] < a.lv.st[j]) pf[j] |= 2;
+  }
+}
+
+hipError_t launch_block_facts(const PhaseArgs& a, uint8_t* pf, hipStream_t s) {
+  k_block_facts<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, pf);
+  return hipGetLastError();
+}
+
+// Entries of the next level: one per marked block P of this level (in order;
+// its children start at next index ntfirst[t] + cs[P] - cs[tfirst[t]]), then
+// one per entering text (whole text, nothing skipped).
+__global__ void k_entries_from_parents(LevelDev lv, TextsDev tx, const uint8_t* marked,
+                                       const uint8_t* pf, const uint64_t* uoff, const uint64_t* cs,
+                                       const uint64_t* tfirst, const uint64_t* ntfirst,
+                                       uint64_t* ea, uint64_t* ee, uint8_t* ef, uint64_t* echild) {
+  GRID_STRIDE(P, lv.c) {
+    if (!marked[P]) continue;
+    const uint64_t k = P - uoff[P];
+    const uint32_t t = lv.text[P];
+    const uint64_t st = lv.st[P], te = tx.tend[t];
+    ea[k] = st;
+    ee[k] = st + (te - st < lv.b ? te - st : lv.b);
+    uint8_t f = 0;
+    if (pf[P] & 1) f |= kSkipCross;
+    if ((pf[P] & 2) || (P > 0 && (pf[P - 1] & 1))) f |= kSkipInterior;
+    ef[k] = f;
+    echild[k] = ntfirst[t] + (cs[P] - cs[tfirst[t]]);
+  }
+}
+
+__global__ void k_entries_entering(const uint32_t* ids, uint32_t E, TextsDev tx, uint64_t base,
+                                   const uint64_t* ntfirst, uint64_t* ea, uint64_t* ee,
+                                   uint8_t* ef, uint64_t* echild) {
+  GRID_STRIDE(k, E) {
+    const uint32_t t = ids[k];
+    ea[base + k] = tx.tstart[t];
+    ee[base + k] = tx.tend[t];
+    ef[base + k] = 0;
+    echild[base + k] = ntfirst[t];
+  }
+}
+
+hipError_t launch_entries_next(const LevelDev& lv, const TextsDev& tx, const uint8_t* marked,
+                               const uint8_t* pf, const uint64_t* uoff, const uint64_t* cs,
+                               const uint64_t* tfirst, const uint64_t* ntfirst, uint64_t nmarked,
+                               const uint32_t* ids, uint32_t E, uint64_t* ea, uint64_t* ee,
+                               uint8_t* ef, uint64_t* echild, hipStream_t s) {
+  if (lv.c)
+    k_entries_from_parents<<<grid_for(lv.c, 256), 256, 0, s>>>(lv, tx, marked, pf, uoff, cs, tfirst,
+                                                               ntfirst, ea, ee, ef, echild);
+  if (E)
+    k_entries_entering<<<grid_for(E, 256), 256, 0, s>>>(ids, E, tx, nmarked, ntfirst, ea, ee, ef,
+                                                          echild);
+  return hipGetLastError();
+}
+
+// Run of each entry, from the block its children start with.
+__global__ void k_entry_runs(const uint64_t* echild, uint64_t E, const uint32_t* run,
+                             uint32_t* erun) {
+  GRID_STRIDE(k, E) erun[k] = run[echild[k]];
+}
+
+hipError_t launch_entry_runs(const uint64_t* echild, uint64_t E, const uint32_t* run,
+                             uint32_t* erun, hipStream_t s) {
+  if (!E) return hipSuccess;
+  k_entry_runs<<<grid_for(E, 256), 256, 0, s>>>(echild, E, run, erun);
+  return hipGetLastError();
+}
+
+// Per phase: segment k = window starts [ws[k], ws[k] + cnt - 1] (cnt into woff[k]),
+// bounded by the run end sre[k]; stext[k] = the run's text.
+__global__ void k_segments(PhaseArgs a, SegDev sg, uint64_t* woff) {
+  GRID_STRIDE(k, sg.E) {
+    const uint32_t r = sg.erun[k];
+    const uint32_t t = a.lv.rtext[r];
+    const uint64_t re = a.lv.re[r];
+    const uint64_t L = a.Lmain;
+    uint64_t Lmin = L;
+    const uint64_t oL = a.odd.L[t];
+    if (oL && oL < Lmin) Lmin = oL;
+    const uint8_t f = sg.ef[k];
+    uint64_t lo = sg.ea[k];
+    if (f & kSkipInterior) {
+      const uint64_t x = sg.ee[k] + 1 > L ? sg.ee[k] + 1 - L : 0;  // first start crossing e
+      if (x > lo) lo = x;
+    }
+    uint64_t cnt = 0;
+    if (a.odd.nkeys[t] && !(f & kSkipCross) && re >= Lmin) {
+      uint64_t hi = sg.ee[k] - 1;
+      if (re - Lmin < hi) hi = re - Lmin;
+      if (hi >= lo && sg.ee[k] > lo) cnt = hi - lo + 1;
+    }
+    sg.ws[k] = lo;
+    sg.sre[k] = re;
+    sg.stext[k] = t;
+    woff[k] = cnt;
+  }
+}
+
+hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff, hipStream_t s) {
+  if (!sg.E) return hipSuccess;
+  k_segments<<<grid_for(sg.E, 256), 256, 0, s>>>(a, sg, woff);
   return hipGetLastError();
 }
 
