@@ -245,23 +245,27 @@ class Tree:
         return b.value
 
     # ---- queries (device tensors in, device tensors out)
-    def access(self, pos, out=None):
+    # ctx: the context whose stream runs the query (default: the building one)
+    def access(self, pos, out=None, ctx=None):
         torch = _torch()
+        ctx = ctx or self.ctx
         if out is None:
             out = torch.empty(pos.numel(), dtype=torch.uint8, device=pos.device)
-        self.ctx._check(lib().bt_access(self.ctx.h, self.h, _ptr(pos), pos.numel(), _ptr(out)))
+        ctx._check(lib().bt_access(ctx.h, self.h, _ptr(pos), pos.numel(), _ptr(out)))
         return out
 
-    def rank(self, cs, pos, out=None):
+    def rank(self, cs, pos, out=None, ctx=None):
         torch = _torch()
+        ctx = ctx or self.ctx
         if out is None:
             out = torch.empty(pos.numel(), dtype=torch.uint64, device=pos.device)
-        self.ctx._check(lib().bt_rank(self.ctx.h, self.h, _ptr(cs), _ptr(pos), pos.numel(), _ptr(out)))
+        ctx._check(lib().bt_rank(ctx.h, self.h, _ptr(cs), _ptr(pos), pos.numel(), _ptr(out)))
         return out
 
-    def select(self, cs, ks, out=None):
+    def select(self, cs, ks, out=None, ctx=None):
         torch = _torch()
+        ctx = ctx or self.ctx
         if out is None:
             out = torch.empty(ks.numel(), dtype=torch.uint64, device=ks.device)
-        self.ctx._check(lib().bt_select(self.ctx.h, self.h, _ptr(cs), _ptr(ks), ks.numel(), _ptr(out)))
+        ctx._check(lib().bt_select(ctx.h, self.h, _ptr(cs), _ptr(ks), ks.numel(), _ptr(out)))
         return out

@@ -928,8 +928,28 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     tr->tstart = h_n[t] ? offs[t] : offs[t];
     tr->leaves = leaves + leaf_off[t];
     tr->leaf_bytes = leaf_bytes[t];
-    tr->dev_bytes = store->bytes / T;
     outs[t] = tr;
+  }
+  // query level tables of every tree, in one upload
+  {
+    std::vector<QLevel> ql;
+    std::vector<uint64_t> at(T);
+    for (uint32_t t = 0; t < T; ++t) {
+      at[t] = ql.size();
+      for (const TreeLevel& L : outs[t]->lv)
+        ql.push_back(QLevel{L.b, L.c, L.words, L.wrank, L.pb, L.po, L.cnt, L.pcnt, L.st});
+    }
+    Buf<QLevel> d = alloc<QLevel>(ctx, ql.size());
+    const uint64_t words = (ql.size() * sizeof(QLevel) + 7) / 8;
+    uint64_t* stg = small_host(ctx, words);
+    std::memcpy(stg, ql.data(), ql.size() * sizeof(QLevel));
+    HIPCHK(ctx, hipMemcpyAsync(d.p, stg, ql.size() * sizeof(QLevel), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    QLevel* base = store->add(std::move(d), ql.size());
+    for (uint32_t t = 0; t < T; ++t) {
+      outs[t]->d_levels = base + at[t];
+      outs[t]->dev_bytes = store->bytes / T;
+    }
   }
   return BT_OK;
 }
@@ -943,27 +963,6 @@ int guarded(bt_ctx* ctx, const std::function<int()>& f) {
     ctx->err = "host allocation failed";
     return BT_E_NOMEM;
   }
-}
-
-// Upload the level table of a tree for the query kernels (once).
-void ensure_qtree(bt_ctx* ctx, const bt_tree* ct) {
-  bt_tree* t = const_cast<bt_tree*>(ct);
-  if (t->d_levels) return;
-  std::vector<QLevel> h(t->h);
-  for (uint32_t l = 0; l < t->h; ++l) {
-    const TreeLevel& L = t->lv[l];
-    h[l] = QLevel{L.b, L.c, L.words, L.wrank, L.pb, L.po, L.cnt, L.pcnt, L.st};
-  }
-  Buf<QLevel> d = alloc<QLevel>(ctx, t->h);
-  QLevel* staging = nullptr;
-  HIPCHK(ctx, hipHostMalloc((void**)&staging, sizeof(QLevel) * t->h, hipHostMallocDefault));
-  std::memcpy(staging, h.data(), sizeof(QLevel) * t->h);
-  hipError_t e = hipMemcpyAsync(d.p, staging, sizeof(QLevel) * t->h, hipMemcpyHostToDevice,
-                                ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  (void)hipHostFree(staging);
-  HIPCHK(ctx, e);
-  t->d_levels = t->store->add(std::move(d), t->h);
 }
 
 QTree qtree_of(const bt_tree* t) {
@@ -1211,7 +1210,6 @@ int bt_access(bt_ctx* ctx, const bt_tree* t, const uint64_t* d_pos, uint64_t m, 
   if (!ctx || !t || (m && (!d_pos || !d_out))) return BT_E_INVAL;
   return guarded(ctx, [&] {
     HIPCHK(ctx, hipSetDevice(ctx->dev));
-    ensure_qtree(ctx, t);
     Buf<uint64_t> bad = alloc<uint64_t>(ctx, 1);
     HIPCHK(ctx, launch_fill_u64(bad.p, 0, 1, ctx->stream));
     if (t->n == 0) {
@@ -1244,8 +1242,7 @@ int bt_rank(bt_ctx* ctx, const bt_tree* t, const uint8_t* d_c, const uint64_t* d
       // empty text: rank(c, 0) = 0, anything else is out of range
       HIPCHK(ctx, launch_rank_empty(d_pos, m, d_out, ctx->stream));
     } else {
-      ensure_qtree(ctx, t);
-      HIPCHK(ctx, launch_rank(qtree_of(t), d_c, d_pos, m, d_out, ctx->stream));
+        HIPCHK(ctx, launch_rank(qtree_of(t), d_c, d_pos, m, d_out, ctx->stream));
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return BT_OK;
@@ -1264,8 +1261,7 @@ int bt_select(bt_ctx* ctx, const bt_tree* t, const uint8_t* d_c, const uint64_t*
     if (t->n == 0 || t->S == 0) {
       HIPCHK(ctx, launch_fill_u64(d_out, ~0ull, m, ctx->stream));
     } else {
-      ensure_qtree(ctx, t);
-      HIPCHK(ctx, launch_select(qtree_of(t), d_c, d_k, m, d_out, ctx->stream));
+        HIPCHK(ctx, launch_select(qtree_of(t), d_c, d_k, m, d_out, ctx->stream));
     }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return BT_OK;
