@@ -34,6 +34,12 @@ WORKLOADS = {
                         "same text, about 2^19 root blocks (b1 = 256)"),
     "dna1m": ("cfg1", 4, 2, 16, 1, "1 MiB DNA: 16 mutated copies of a 64 KiB base"),
     "dna1m_s": ("cfg1", 4, 2, 16, 10000, "1 MiB DNA, s about 10^4 (b1 = 64)"),
+    "batch4096": ("cfg4", 4, 4, 16, 1,
+                  "4096 DNA texts, lognormal lengths (median 256 KiB, 4 KiB-64 MiB, ~3.9 GiB): "
+                  "one batched build vs a loop of single builds"),
+    "serve": ("cfg5", 4, 4, 16, 1,
+              "serving: Poisson build requests (lognormal sizes, median 256 KiB, 1 KiB-256 MiB, "
+              "DNA texts) at 0.8x measured capacity, interleaved 1M-query batches"),
 }
 
 
@@ -58,6 +64,170 @@ def traffic_record(kernel):
     if h != rec.get("source_sha256"):
         return None
     return rec
+
+
+def bench_batch(args, sigma, tau, leaf, desc):
+    """Batched build of 4096 texts vs a loop of single builds over the same
+    device buffer."""
+    import numpy as np
+    import torch
+    import paper_2512_23314_amd as bt
+    import synth
+    t0 = time.time()
+    texts = synth.batch_texts()
+    offs = np.zeros(len(texts) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(t) for t in texts])
+    concat = np.concatenate(texts)
+    del texts
+    n = int(offs[-1])
+    log("generated %d texts, %d bytes in %.1f s" % (len(offs) - 1, n, time.time() - t0))
+    d = torch.from_numpy(concat).to("cuda:0")
+    del concat
+    ctx = bt.Context(0)
+
+    def batched():
+        trees = ctx.build_batch(d, offs, sigma=sigma, tau=tau, leaf_len=leaf)
+        for tr in trees:
+            tr.free()
+
+    def plain():
+        for k in range(len(offs) - 1):
+            a, b = int(offs[k]), int(offs[k + 1])
+            ctx.build(d[a:b], sigma=sigma, tau=tau, leaf_len=leaf).free()
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / args.steps
+    ctx.profile(False)
+    ps = ctx.kernel_stats("probe_scan")
+    plain()  # warm the plain path's allocations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    log("batched %.1f ms (%.0f MB/s), plain loop %.1f ms (%.0f MB/s)" % (
+        dt_b * 1e3, n / 1e6 / dt_b, dt_p * 1e3, n / 1e6 / dt_p))
+    achieved = ps["bytes"] / ps["ms"] / 1e6 if ps["ms"] > 0 else 0.0
+    out = {
+        "metric": "block-tree build MB/s and KR-scan GB/s (% HBM peak) on 1 MI355X vs CPU oracle",
+        "value": round(n / 1e6 / dt_b, 2), "unit": "MB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt_b * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batch4096", "description": desc, "n": n, "texts": len(offs) - 1,
+                   "sigma": sigma, "tau": tau, "leaf_len": leaf},
+        "batched_vs_plain": {"batched_mb_s": round(n / 1e6 / dt_b, 2),
+                             "plain_loop_mb_s": round(n / 1e6 / dt_p, 2),
+                             "speedup": round(dt_p / dt_b, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "probe_scan"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_serve(args, sigma, tau, leaf, desc, seconds=10.0):
+    """Open-loop serving: Poisson build arrivals at 0.8x the capacity measured by a
+    closed-loop burst, 1M-query batches (a third each of access, rank, select)
+    against random resident trees."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2512_23314_amd.serve import Server
+    rng = np.random.default_rng(synth.CFG_SEEDS[5])
+    sizes = synth.serving_sizes(384)
+    t0 = time.time()
+    pool = [synth.dna_copies(int(s), max(1, int(s) // 16), 16, 1e-3, 1e-4, 8, int(rng.integers(1 << 30)))
+            for s in sizes]
+    log("generated %d request texts (%.0f MiB) in %.1f s" % (
+        len(pool), sum(len(p) for p in pool) / 2**20, time.time() - t0))
+    dpool = [torch.from_numpy(p).to("cuda:0") for p in pool]
+    torch.cuda.synchronize()
+    mean = float(np.mean([len(p) for p in pool]))
+
+    def run(srv, arrivals, query_every):
+        """arrivals: list of (time, pool index).  Returns wall seconds."""
+        futs, rids, seen = [], [], []
+        qfuts = []
+        t_start = time.perf_counter()
+        next_q = query_every
+        for ta, k in arrivals:
+            now = time.perf_counter() - t_start
+            if ta > now:
+                time.sleep(ta - now)
+            futs.append(srv.submit_build(dpool[k]))
+            now = time.perf_counter() - t_start
+            if query_every and now >= next_q:
+                if rids:
+                    rid = rids[int(rng.integers(len(rids)))]
+                    n = srv.tree(rid).n
+                    m = 1 << 20
+                    third = m // 3
+                    pos = torch.randint(0, max(n, 1), (m,), device="cuda:0").to(torch.uint64)
+                    cs = torch.from_numpy(np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, m)]).to("cuda:0")
+                    ks = torch.randint(1, max(2, n // 8), (m,), device="cuda:0").to(torch.uint64)
+                    qfuts.append(srv.submit_queries(rid, "access", pos[:third]))
+                    qfuts.append(srv.submit_queries(rid, "rank", cs[third:2 * third], pos[third:2 * third]))
+                    qfuts.append(srv.submit_queries(rid, "select", cs[2 * third:], ks[2 * third:]))
+                next_q += query_every
+            # keep the resident set bounded (oldest finished trees first)
+            for f in futs[len(seen):]:
+                if not f.done():
+                    break
+                seen.append(int(f.result()))
+                rids.append(seen[-1])
+            while len(rids) > 128:
+                srv.release(rids.pop(0))
+        for f in futs:
+            f.result()
+        for q in qfuts:
+            q.result()
+        return time.perf_counter() - t_start
+
+    # capacity: closed-loop burst
+    srv = Server(budget=96 << 30, slots=3, max_batch=256, tau=tau, leaf_len=leaf, sigma=sigma)
+    burst = [(0.0, k) for k in range(len(pool))]
+    dt = run(srv, burst, 0)
+    cap = sum(len(p) for p in pool) / dt
+    srv.close()
+    lam = 0.8 * cap / mean
+    log("capacity %.0f MB/s (burst of %d requests in %.2f s); Poisson rate %.1f req/s" % (
+        cap / 1e6, len(pool), dt, lam))
+    t, arrivals = 0.0, []
+    while t < seconds:
+        t += float(rng.exponential(1.0 / lam))
+        arrivals.append((t, int(rng.integers(len(pool)))))
+    srv = Server(budget=96 << 30, slots=3, max_batch=256, tau=tau, leaf_len=leaf, sigma=sigma)
+    wall = run(srv, arrivals, 0.1)
+    st = srv.stats()
+    srv.close()
+    served = st["built_bytes"] / wall
+    log("served %s" % st)
+    out = {
+        "metric": "block-tree build MB/s and KR-scan GB/s (% HBM peak) on 1 MI355X vs CPU oracle",
+        "value": round(served / 1e6, 2), "unit": "MB/s", "n_gpus": 1, "steps": len(arrivals),
+        "warmup": len(pool), "ms_per_step": round(wall / max(len(arrivals), 1) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "serve", "description": desc, "requests": len(arrivals),
+                   "rate_per_s": round(lam, 2), "seconds": round(wall, 2), "tau": tau,
+                   "leaf_len": leaf, "sigma": sigma},
+        "serving": {"build_p50_ms": st["build_p50_ms"], "build_p99_ms": st["build_p99_ms"],
+                    "query_batch_p50_ms": st["query_p50_ms"], "query_batch_p99_ms": st["query_p99_ms"],
+                    "query_batches": st["query_batches"], "build_batches": st["batches"],
+                    "capacity_mb_s": round(cap / 1e6, 2)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(T, sigma, tau, leaf, s_hint, sample_bytes):
@@ -103,6 +273,10 @@ def main():
     import paper_2512_23314_amd as bt
 
     gen, sigma, tau, leaf, s_hint, desc = WORKLOADS[args.workload]
+    if gen == "cfg4":
+        return bench_batch(args, sigma, tau, leaf, desc)
+    if gen == "cfg5":
+        return bench_serve(args, sigma, tau, leaf, desc)
     t0 = time.time()
     T = make_text(gen)
     log("generated %s (%d bytes) in %.1f s" % (args.workload, T.size, time.time() - t0))

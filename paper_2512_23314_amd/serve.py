@@ -74,6 +74,8 @@ class Server:
         self.inflight = 0
         self.max_used = 0
         self.qqueue = collections.deque()
+        self.pins = collections.Counter()   # queued or running queries per tree
+        self.doomed = set()                 # released while pinned
         self.workers = [threading.Thread(target=self._build_worker, daemon=True) for _ in range(slots)]
         self.qworker = threading.Thread(target=self._query_worker, daemon=True)
         for w in self.workers:
@@ -103,6 +105,9 @@ class Server:
         the result tensor."""
         fut = Future()
         with self.lock:
+            if rid not in self.trees or rid in self.doomed:
+                raise KeyError("no resident tree %d" % rid)
+            self.pins[rid] += 1  # the tree stays resident until its queries ran
             self.qqueue.append((rid, kind, a, b, fut, time.perf_counter()))
             self.lock.notify_all()
         return fut
@@ -111,11 +116,19 @@ class Server:
         return self.trees[rid][0]
 
     def release(self, rid):
+        """Free a resident tree (deferred until its queued queries have run)."""
         with self.lock:
-            tree, nbytes = self.trees.pop(rid)
-            tree.free()
-            self.used -= nbytes
-            self.lock.notify_all()
+            if self.pins[rid]:
+                self.doomed.add(rid)
+                return
+            self._free(rid)
+
+    def _free(self, rid):
+        tree, nbytes = self.trees.pop(rid)
+        tree.free()
+        self.used -= nbytes
+        self.doomed.discard(rid)
+        self.lock.notify_all()
 
     def close(self):
         with self.lock:
@@ -210,6 +223,7 @@ class Server:
                     break
                 rid, kind, a, b, fut, t0 = self.qqueue.popleft()
                 tree = self.trees.get(rid, (None, 0))[0]
+            out, err = None, None
             try:
                 if tree is None:
                     raise KeyError("no resident tree %d" % rid)
@@ -220,11 +234,20 @@ class Server:
                         out = tree.rank(a, b, ctx=ctx)
                     else:
                         out = tree.select(a, b, ctx=ctx)
-                with self.lock:
-                    self.query_lat.append(time.perf_counter() - t0)
-                fut.set_result(out)
             except Exception as e:
-                fut.set_exception(e)
+                err = e
+            with self.lock:
+                if err is None:
+                    self.query_lat.append(time.perf_counter() - t0)
+                self.pins[rid] -= 1
+                if self.pins[rid] <= 0:
+                    del self.pins[rid]
+                    if rid in self.doomed:
+                        self._free(rid)
+            if err is None:
+                fut.set_result(out)
+            else:
+                fut.set_exception(err)
         ctx.close()
 
     def stats(self):

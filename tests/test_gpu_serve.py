@@ -74,9 +74,15 @@ def test_admission_respects_budget():
     futs = [srv.submit_build(T) for T in texts]
     rids = [f.result(timeout=120) for f in futs]
     st = srv.stats()
+    # a tree with a queued query is released only after the query ran
+    import torch
+    pos = torch.zeros(4, dtype=torch.int64, device="cuda:0").to(torch.uint64)
+    qf = [srv.submit_queries(rid, "access", pos) for rid in rids if srv.tree(rid).n]
     # resident trees stay charged; release them and check the accounting empties
     for rid in rids:
         srv.release(rid)
+    for f in qf:
+        f.result(timeout=60)
     assert srv.used == 0
     srv.close()
     assert st["max_admitted_bytes"] <= srv.budget
