@@ -687,6 +687,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
 
     const uint64_t cap = std::max<uint64_t>(1024, pow2_at_least(2 * c));
     Buf<Slot> tab = alloc<Slot>(ctx, cap);
+    Buf<uint64_t> tags = alloc<uint64_t>(ctx, cap / 8);
     Buf<uint64_t> kfp = alloc<uint64_t>(ctx, c), klen = alloc<uint64_t>(ctx, c),
                   klm = alloc<uint64_t>(ctx, c);
     Buf<uint32_t> kslot = alloc<uint32_t>(ctx, c);
@@ -701,9 +702,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint64_t> vbest = alloc<uint64_t>(ctx, c), rlb = alloc<uint64_t>(ctx, c),
                   vcnt = alloc<uint64_t>(ctx, 2);
     Buf<uint8_t> marked = alloc<uint8_t>(ctx, c);
-    // LDS key filter of up to 2^18 bits, sized per phase from the key count
-    Buf<uint32_t> filt = alloc<uint32_t>(ctx, (1ull << 18) / 32);
-    bool use_filter = true;
+    // LDS key filter of up to 2^19 bits, sized per phase from the key count
+    Buf<uint32_t> filt = alloc<uint32_t>(ctx, (1ull << 19) / 32);
+    int scan_mode = 1;
     uint32_t fbits = 12;
     VerifyBufs vb{vlist.p, vbest.p, vmis.p, rlist.p, rlb.p, vcnt.p};
 
@@ -715,7 +716,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.k = KeysDev{kfp.p, klen.p, kslot.p, klm.p};
     a.odd = OddDev{oddb.p, oddb.p + T, oddb.p + 2 * T, oddb.p + 3 * T, oddb.p + 4 * T,
                    oddb.p + 5 * T};
-    a.tab = TableDev{tab.p, cap - 1};
+    a.tab = TableDev{tab.p, cap - 1, reinterpret_cast<uint8_t*>(tags.p)};
     a.x = x;
     a.fpmask = fpmask;
     a.marked = marked.p;
@@ -726,17 +727,28 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       a.phase = phase;
       a.Lmain = phase == 1 ? 2 * b : b;
       a.xLmain = host_pow61(x, a.Lmain);
-      // about 32 filter bits per key; two bits per key while there are at least
-      // 8 bits per key, one while there is at least one, else no filter
+      // Up to 2^17 keys: about 32 filter bits per key (at most 2^18) with
+      // candidate queues (mode 1); two bits per key while there are at least 8
+      // bits per key.  Beyond that a 2^19-bit one-bit filter without queues
+      // (mode 2, 64 KiB of LDS, two workgroups per CU).  Measured on 256 MiB
+      // texts, mode 2 beats direct probing (mode 0) even at 1.4M keys, where
+      // most windows pass the filter, and a 2^20-bit filter loses (one
+      // workgroup per CU).
       fbits = 12;
       while (fbits < 18 && (1ull << fbits) < 32 * nkeys) ++fbits;
-      use_filter = nkeys <= (1ull << fbits);
-      a.filt_bits = use_filter ? fbits : 0;
+      if (nkeys <= (1ull << 17)) {
+        scan_mode = 1;
+      } else {
+        scan_mode = 2;
+        fbits = 19;
+      }
+      a.filt_bits = scan_mode ? fbits : 0;
       a.filt_two = 8 * nkeys <= (1ull << fbits);
       HIPCHK(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(tab.p), ~0ull, 2 * cap, s));
+      HIPCHK(ctx, launch_fill_u64(tags.p, 0, cap / 8, s));
       HIPCHK(ctx, launch_fill_u64(oddb.p, 0, 6 * (uint64_t)T, s));
       HIPCHK(ctx, launch_fill_u64(vcnt.p, 0, 2, s));
-      if (use_filter) HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
+      if (scan_mode) HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
       HIPCHK(ctx, launch_keys(a, s));
       HIPCHK(ctx, launch_segments(a, sg, woff.p, s));
       scan(woff.p, E_ent);
@@ -748,7 +760,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       as.lv.re = seg_re.p;
       as.lv.rtext = seg_text.p;
       timed(ctx, "probe_scan", 0, 0, wst, 16.0, [&] {
-        return launch_probe_scan(as, woff.p, has_odd, has_salt, c * b, use_filter, s);
+        return launch_probe_scan(as, woff.p, has_odd, has_salt, c * b, scan_mode, s);
       });
       HIPCHK(ctx, launch_resolve(a, vb, s));
       timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });

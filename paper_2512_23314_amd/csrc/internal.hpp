@@ -68,9 +68,13 @@ struct Slot {
   uint64_t best;  // smallest position with this fingerprint seen so far
 };
 
+// Slots plus one tag byte per slot (0 = empty, else tag_of(fp) of the slot's
+// key): lookups scan the small tag array eight slots per load and touch a slot
+// only where its tag matches.
 struct TableDev {
   Slot* slots;
-  uint64_t mask;  // capacity - 1
+  uint64_t mask;  // capacity - 1 (capacity a power of two, at least 1024)
+  uint8_t* tag;   // capacity bytes, 8-byte aligned
 };
 
 struct PhaseArgs {
@@ -88,7 +92,7 @@ struct PhaseArgs {
   const uint8_t* marked;  // phase 2: skip marked blocks
   int phase;        // 1 or 2
   uint32_t* filt;   // bit filter of the main-length keys' fingerprints
-  uint32_t filt_bits;  // log2 of its size in bits (12..18); 0 = no filter
+  uint32_t filt_bits;  // log2 of its size in bits (12..19); 0 = no filter
   uint32_t filt_two;   // 1: two bits per key, 0: one
   uint32_t all_blocks; // phase 2: keys for every block, not only unmarked ones
 };
@@ -131,10 +135,10 @@ hipError_t launch_entry_runs(const uint64_t* echild, uint64_t E, const uint32_t*
                              uint32_t* erun, hipStream_t s);
 // Per-segment window counts into woff[0..E) (then scanned by the caller).
 hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff, hipStream_t s);
-// The sliding-window probe.  max_windows bounds the grid; filter selects the
-// variant that tests an LDS key filter before the table.
+// The sliding-window probe.  max_windows bounds the grid; mode 0: no filter,
+// 1: LDS key filter and per-wave candidate queues, 2: LDS key filter, inline probe.
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
-                             bool has_salt, uint64_t max_windows, bool filter, hipStream_t s);
+                             bool has_salt, uint64_t max_windows, int mode, hipStream_t s);
 
 struct VerifyBufs {
   uint32_t* vlist;  // [c]

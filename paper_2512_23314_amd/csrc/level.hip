@@ -74,6 +74,7 @@ __global__ void k_keys(PhaseArgs a) {
         h = (h + 1) & a.tab.mask;
       }
       a.k.slot[j] = (uint32_t)h;
+      a.tab.tag[h] = (uint8_t)tag_of(fp);  // every key of the slot writes the same byte
       atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
       if (a.filt_bits) {
         const uint64_t f1 = filter_bit(fp, a.filt_bits);
@@ -257,17 +258,35 @@ hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff,
 constexpr int kScanK = 16;                      // windows per lane per chunk
 constexpr uint64_t kScanChunk = 64ull * kScanK;  // windows per wave per chunk
 
-__device__ __forceinline__ void probe(Slot* __restrict__ slots, uint64_t mask, uint64_t fp,
-                                      uint64_t i) {
-  uint64_t h = slot_of(fp, mask);
+// Linear probing over the tag array, one aligned group of eight tags per load:
+// the slots from the home slot up to the first empty one are exactly those a
+// key with this fingerprint could occupy; only those whose tag matches are read.
+__device__ __forceinline__ void probe(Slot* __restrict__ slots, const uint8_t* __restrict__ tags,
+                                      uint64_t mask, uint64_t fp, uint64_t i) {
+  constexpr uint64_t kLo7 = 0x7F7F7F7F7F7F7F7Full;
+  const uint64_t h = slot_of(fp, mask);
+  const uint64_t tb = 0x0101010101010101ull * tag_of(fp);
+  uint64_t g = h >> 3;
+  uint64_t valid = ~0ull << (8 * (h & 7));  // bytes at or after the home slot
   while (true) {
-    const Slot s = slots[h];
-    if (s.fp == fp) {
-      if (i < s.best) atomicMin((unsigned long long*)&slots[h].best, (unsigned long long)i);
-      return;
+    const uint64_t w = *reinterpret_cast<const uint64_t*>(tags + 8 * g);
+    // bit 8k+7 set exactly where byte k is zero (empty) / equals the tag
+    const uint64_t emp = ~(((w & kLo7) + kLo7) | w | kLo7) & valid;
+    const uint64_t x = w ^ tb;
+    uint64_t mat = ~(((x & kLo7) + kLo7) | x | kLo7) & valid;
+    if (emp) mat &= (emp & (0 - emp)) - 1;  // matches before the first empty slot
+    while (mat) {
+      const uint64_t j = 8 * g + (__builtin_ctzll(mat) >> 3);
+      const Slot s = slots[j];
+      if (s.fp == fp) {
+        if (i < s.best) atomicMin((unsigned long long*)&slots[j].best, (unsigned long long)i);
+        return;
+      }
+      mat &= mat - 1;
     }
-    if (s.fp == kEmpty) return;
-    h = (h + 1) & mask;
+    if (emp) return;
+    g = (g + 1) & (mask >> 3);
+    valid = ~0ull;
   }
 }
 
@@ -292,9 +311,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool FILTER, bool ODD, bool SALT>
+// MODE 0: no filter, every window probes the table.  MODE 1: filter, candidates
+// queued and probed 64 at a time.  MODE 2: filter, candidates probe at once (for
+// large filters, whose LDS leaves no room for the queues).
+template <int MODE, bool ODD, bool SALT>
 __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
                                                              const uint64_t* __restrict__ woff) {
+  constexpr bool FILTER = MODE != 0;
   extern __shared__ uint64_t s_lds[];
   const uint32_t fbits = a.filt_bits;
   uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);
@@ -319,6 +342,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
   const uint64_t* __restrict__ re_ = a.lv.re;
   const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
   Slot* __restrict__ slots = a.tab.slots;
+  const uint8_t* __restrict__ tags = a.tab.tag;
   const uint64_t mask = a.tab.mask;
 
   for (uint64_t ch = gw; ch * kScanChunk < W; ch += nw) {
@@ -359,13 +383,14 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
             const uint64_t b1 = filter_bit(fp, fbits);
             const uint64_t b2 = a.filt_two ? filter_bit2(fp, fbits) : b1;
             cand = ((s_filt[b1 >> 5] >> (b1 & 31)) & (s_filt[b2 >> 5] >> (b2 & 31)) & 1) != 0;
+            if (MODE == 2 && cand) probe(slots, tags, mask, fp, i);
           } else {
-            probe(slots, mask, fp, i);
+            probe(slots, tags, mask, fp, i);
           }
         }
       }
-      const uint64_t bal = FILTER ? __ballot(cand) : 0;
-      if (FILTER && bal) {
+      const uint64_t bal = MODE == 1 ? __ballot(cand) : 0;
+      if (MODE == 1 && bal) {
         const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
         if (cand) {
           qf[qn + my] = fp;
@@ -387,7 +412,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
             qi[lane] = i2;
           }
           qn -= 64;
-          probe(slots, mask, f, ii);
+          probe(slots, tags, mask, f, ii);
           wave_sync();
         }
       }
@@ -402,35 +427,39 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
       }
     }
   }
-  if (FILTER && qn) {
+  if (MODE == 1 && qn) {
     wave_sync();
-    if ((uint32_t)lane < qn) probe(slots, mask, qf[lane], qi[lane]);
+    if ((uint32_t)lane < qn) probe(slots, tags, mask, qf[lane], qi[lane]);
   }
 }
 
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
-                             bool has_salt, uint64_t max_windows, bool filter, hipStream_t s) {
+                             bool has_salt, uint64_t max_windows, int mode, hipStream_t s) {
   if (a.lv.R == 0) return hipSuccess;
   const uint64_t waves = (max_windows + kScanChunk - 1) / kScanChunk;
-  // two 1024-thread workgroups per CU (LDS: filter up to 32 KiB + queues 32 KiB)
+  // two 1024-thread workgroups per CU: LDS of at most 64 KiB each (mode 1: filter
+  // up to 32 KiB + queues 32 KiB; mode 2: filter up to 64 KiB)
   const unsigned grid = grid_for(waves * 64, kProbeThreads, 512);
-  const size_t lds = filter ? ((size_t)1 << (a.filt_bits - 3)) +
-                                  (size_t)(kProbeThreads / 64) * 2 * kQueue * sizeof(uint64_t)
-                            : 0;
-#define BT_PROBE_LAUNCH(F, O, S) k_probe_scan<F, O, S><<<grid, kProbeThreads, lds, s>>>(a, woff)
-  if (filter) {
-    if (has_odd) {
-      if (has_salt) BT_PROBE_LAUNCH(true, true, true); else BT_PROBE_LAUNCH(true, true, false);
-    } else {
-      if (has_salt) BT_PROBE_LAUNCH(true, false, true); else BT_PROBE_LAUNCH(true, false, false);
-    }
-  } else {
-    if (has_odd) {
-      if (has_salt) BT_PROBE_LAUNCH(false, true, true); else BT_PROBE_LAUNCH(false, true, false);
-    } else {
-      if (has_salt) BT_PROBE_LAUNCH(false, false, true); else BT_PROBE_LAUNCH(false, false, false);
-    }
+  size_t lds = 0;
+  if (mode == 1)
+    lds = ((size_t)1 << (a.filt_bits - 3)) + (size_t)(kProbeThreads / 64) * 2 * kQueue * 8;
+  else if (mode == 2)
+    lds = (size_t)1 << (a.filt_bits - 3);
+#define BT_PROBE_LAUNCH(M, O, S) k_probe_scan<M, O, S><<<grid, kProbeThreads, lds, s>>>(a, woff)
+#define BT_PROBE_MODE(M)                                                  \
+  if (has_odd) {                                                          \
+    if (has_salt) BT_PROBE_LAUNCH(M, true, true); else BT_PROBE_LAUNCH(M, true, false);   \
+  } else {                                                                \
+    if (has_salt) BT_PROBE_LAUNCH(M, false, true); else BT_PROBE_LAUNCH(M, false, false); \
   }
+  if (mode == 1) {
+    BT_PROBE_MODE(1)
+  } else if (mode == 2) {
+    BT_PROBE_MODE(2)
+  } else {
+    BT_PROBE_MODE(0)
+  }
+#undef BT_PROBE_MODE
 #undef BT_PROBE_LAUNCH
   return hipGetLastError();
 }
