@@ -66,6 +66,127 @@ def traffic_record(kernel):
     return rec
 
 
+# ---------------------------------------------------------------- profile summaries
+# These turn rocprofv3 output (CSV) into the short text summaries kept under
+# profiles/; they read files only and never touch a GPU.
+
+def _find_csv(d, suffix):
+    for root, _, files in os.walk(d):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError("no *%s under %s" % (suffix, d))
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short_name(name):
+    """'void bt::k_probe_scan<2, false, false>(bt::PhaseArgs, ...)' -> 'k_probe_scan<2, false, false>'"""
+    s = name[5:] if name.startswith("void ") else name
+    depth, cut = 0, len(s)
+    for i, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    s = s[:cut]
+    return s[4:] if s.startswith("bt::") else s
+
+
+def _bench_line(path):
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{") and '"metric"' in line:
+                return json.loads(line)
+    raise ValueError("no bench JSON line in %s" % path)
+
+
+def summarize_stats(stats_dir, bench_json, cmd, out, top=20):
+    rows = _csv_rows(_find_csv(stats_dir, "kernel_stats.csv"))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    b = _bench_line(bench_json)
+    probe = [r for r in rows if "k_probe_scan<" in r["Name"]]
+    calls = sum(int(r["Calls"]) for r in probe)
+    pns = sum(float(r["TotalDurationNs"]) for r in probe)
+    rf = b["roofline"]
+    lines = ["# Kernel time, %s build" % b["config"]["workload"], "",
+             "Command (repository root, one MI355X):", "", "    " + cmd, "",
+             "Bench line of the same run: %.2f %s, %.3f ms per step, probe_scan average "
+             "launch %.4f ms (HIP events on the library stream), %d launches per step." % (
+                 b["value"], b["unit"], b["ms_per_step"], rf["avg_launch_ms"], rf["launches_per_step"]),
+             "",
+             "rocprofv3: k_probe_scan (all instantiations) %d calls, average %.4f ms "
+             "(ratio to the HIP-event average %.3f); warmup and timed steps launch the same "
+             "kernels, so the averages compare." % (calls, pns / max(calls, 1) / 1e6,
+                                                     pns / max(calls, 1) / 1e6 / rf["avg_launch_ms"]),
+             "", "| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        lines.append("| %s | %s | %.3f | %.1f | %.1f |" % (
+            _short_name(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e3, 100.0 * float(r["TotalDurationNs"]) / total))
+    lines.append("| (all kernels) | %d | %.3f | | 100 |" % (sum(int(r["Calls"]) for r in rows), total / 1e6))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out)
+
+
+def _counter_per_launch(d, needle):
+    rows = [r for r in _csv_rows(_find_csv(d, "counter_collection.csv")) if needle in r["Kernel_Name"]]
+    if not rows:
+        raise ValueError("no %s dispatches in %s" % (needle, d))
+    return sum(float(r["Counter_Value"]) for r in rows) / len(rows), len(rows)
+
+
+def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, bench_json, cmds,
+                      out_md, out_json, kernel="probe_scan", source="level.hip"):
+    copy_bytes = copy_mib << 20
+    cf, _ = _counter_per_launch(cfetch_dir, "copyBuffer")
+    cw, _ = _counter_per_launch(cwrite_dir, "copyBuffer")
+    # a copy of B bytes reads B and writes B: scale each counter (KiB) to that
+    ff, fw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    kf, n = _counter_per_launch(fetch_dir, "k_%s<" % kernel)
+    kw, _ = _counter_per_launch(write_dir, "k_%s<" % kernel)
+    fetch, write = kf * 1024.0 * ff, kw * 1024.0 * fw
+    b = _bench_line(bench_json)
+    algo = b["roofline"].get("bytes_per_launch")
+    src = os.path.join(ROOT, "paper_2512_23314_amd", "csrc", source)
+    rec = {"kernel": kernel, "source": source,
+           "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "workload": b["config"]["workload"], "launches": n,
+           "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+           "bytes_per_launch": round(fetch + write), "algorithmic_bytes_per_launch": algo,
+           "fetch_scale": ff, "write_scale": fw}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    lines = ["# HBM traffic of %s, %s build" % (kernel, b["config"]["workload"]), "",
+             "Commands (repository root, one MI355X, each its own run):", ""]
+    lines += ["    " + c for c in cmds]
+    lines += ["",
+              "Calibration: a device copy of %d MiB reads FETCH_SIZE %.1f KiB and WRITE_SIZE "
+              "%.1f KiB per dispatch, so the scale factors are %.4f (fetch) and %.4f (write)." % (
+                  copy_mib, cf, cw, ff, fw), "",
+              "| per launch (average of %d) | bytes |" % n, "|---|---:|",
+              "| FETCH_SIZE, scaled | %.4g |" % fetch, "| WRITE_SIZE, scaled | %.4g |" % write,
+              "| traffic (fetch + write) | %.4g |" % (fetch + write)]
+    if algo:
+        lines += ["| algorithmic (16 B per window) | %.4g |" % algo,
+                  "| traffic / algorithmic | %.3f |" % ((fetch + write) / algo)]
+    lines += ["", "Source hash (%s): %s" % (source, rec["source_sha256"])]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out_md, out_json)
+
+
 def bench_batch(args, sigma, tau, leaf, desc):
     """Batched build of 4096 texts vs a loop of single builds over the same
     device buffer."""
@@ -252,7 +373,23 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
                          "known-size reference for the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="write a markdown summary of a rocprofv3 --stats run (no GPU)")
+    ap.add_argument("--summarize-traffic", nargs=4,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the probe_scan traffic record from four --pmc runs (no GPU)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--bench-json", help="stdout of the profiled bench run")
+    ap.add_argument("--profile-cmd", action="append", default=[],
+                    help="the command(s) that produced the profile, quoted in the summary")
+    ap.add_argument("--out", nargs="+", help="output file(s) of a summary")
     args = ap.parse_args()
+    if args.summarize_stats:
+        return summarize_stats(args.summarize_stats, args.bench_json, " ".join(args.profile_cmd),
+                               args.out[0])
+    if args.summarize_traffic:
+        return summarize_traffic(*args.summarize_traffic, args.copy_mib, args.bench_json,
+                                 args.profile_cmd, args.out[0], args.out[1])
     if args.calibrate_copy:
         import torch
         nb = args.calibrate_copy << 20
@@ -321,6 +458,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "probe_scan", "launches_per_step": ps["launches"] // max(args.steps, 1),
+                "bytes_per_launch": round(ps["bytes"] / max(ps["launches"], 1)),
                 "avg_launch_ms": round(ps["ms"] / max(ps["launches"], 1), 5)}
     cpu = None
     if not args.no_cpu_baseline:
