@@ -286,6 +286,35 @@ uint64_t base_from_seed(uint64_t seed) {
   return 256 + r % (kP61Host - 1 - 256);
 }
 
+// Odd base of the 32-bit pre-filter hash (an even base would make the hash of
+// a long window depend on its last 32 bytes only).
+uint32_t base32_from_seed(uint64_t seed) {
+  uint64_t s = seed ^ 0x32B17ull;
+  splitmix64(s);
+  uint32_t x = (uint32_t)(splitmix64(s) >> 17) | 1u;
+  return x == 1u ? 0x9E3779B1u : x;
+}
+
+uint32_t host_pow32(uint32_t x, uint64_t e) {
+  uint32_t r = 1;
+  while (e) {
+    if (e & 1) r *= x;
+    x *= x;
+    e >>= 1;
+  }
+  return r;
+}
+
+void fill_pow32(PfPow32* pw, uint32_t x) {
+  pw->x1[0] = 1;
+  for (int k = 1; k <= 16; ++k) pw->x1[k] = pw->x1[k - 1] * x;
+  pw->x16[0] = 1;
+  for (int k = 1; k <= 256; ++k) pw->x16[k] = pw->x16[k - 1] * pw->x1[16];
+  const uint32_t xt = host_pow32(x, kPfTile);
+  pw->xt[0] = 1;
+  for (int k = 1; k <= 64; ++k) pw->xt[k] = pw->xt[k - 1] * xt;
+}
+
 void fill_pow(PfPow* pw, uint64_t x) {
   pw->x1[0] = 1;
   for (int k = 1; k <= 16; ++k) pw->x1[k] = host_mul61(pw->x1[k - 1], x);
@@ -531,6 +560,22 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   });
   const uint64_t* P = d_P.p - o0;  // P[i] belongs to text position i; never read below o0
 
+  // 32-bit pre-filter hashes of the concatenation (same indexing as P)
+  const uint32_t x32 = base32_from_seed(prm.hash_seed);
+  Buf<uint32_t> d_H = alloc<uint32_t>(ctx, N + 1);
+  Buf<PfPow32> d_pw32 = alloc<PfPow32>(ctx, 1);
+  {
+    PfPow32 hp;
+    fill_pow32(&hp, x32);
+    upload(ctx, reinterpret_cast<uint32_t*>(d_pw32.p), reinterpret_cast<const uint32_t*>(&hp),
+           sizeof(PfPow32) / 4);
+  }
+  timed(ctx, "prefix_h32", (double)N + 4.0 * (double)(N + 1), (double)N, nullptr, 0, [&] {
+    return launch_prefix_h32(d_base + o0, N, d_H.p, d_pw32.p, d_status.p,
+                             reinterpret_cast<uint32_t*>(d_ctr.p), s);
+  });
+  const uint32_t* H32 = d_H.p - o0;
+
   auto store = std::make_shared<Storage>();
   store->pool = ctx->pool;
 
@@ -711,6 +756,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     PhaseArgs a{};
     a.T = d_base;
     a.P = P;
+    a.P32 = H32;
     a.tx = tx;
     a.lv = lv;
     a.k = KeysDev{kfp.p, klen.p, kslot.p, klm.p};
@@ -727,23 +773,27 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       a.phase = phase;
       a.Lmain = phase == 1 ? 2 * b : b;
       a.xLmain = host_pow61(x, a.Lmain);
-      // Up to 2^17 keys: about 32 filter bits per key (at most 2^18) with
-      // candidate queues (mode 1); two bits per key while there are at least 8
-      // bits per key.  Beyond that a 2^19-bit one-bit filter without queues
-      // (mode 2, 64 KiB of LDS, two workgroups per CU).  Measured on 256 MiB
-      // texts, mode 2 beats direct probing (mode 0) even at 1.4M keys, where
-      // most windows pass the filter, and a 2^20-bit filter loses (one
-      // workgroup per CU).
+      // About 32 filter bits per key, at most 2^19 (64 KiB of LDS), two bits
+      // per key while there are at least 8 bits per key.  Up to 2^18 keys the
+      // scan queues its candidates (mode 1) and tests the 32-bit pre-filter
+      // hash, unless the level has a short final key (whose per-window check
+      // reads the 61-bit prefix anyway; then up to 2^17 keys).  Beyond that
+      // most windows pass any filter that fits in LDS: a 2^19-bit filter
+      // without queues (mode 2) on 61-bit fingerprints.  Queue entries pack a
+      // position below 2^40 and a text below 2^24; past that, mode 2.
       fbits = 12;
-      while (fbits < 18 && (1ull << fbits) < 32 * nkeys) ++fbits;
-      if (nkeys <= (1ull << 17)) {
+      while (fbits < 19 && (1ull << fbits) < 32 * nkeys) ++fbits;
+      const bool can_queue = T <= (1u << 24) && offs[T] < (1ull << 40);
+      if (can_queue && nkeys <= (has_odd ? (1ull << 17) : (1ull << 18))) {
         scan_mode = 1;
       } else {
         scan_mode = 2;
-        fbits = 19;
+        fbits = std::max<uint32_t>(fbits, 19);
       }
-      a.filt_bits = scan_mode ? fbits : 0;
+      a.filt_bits = fbits;
       a.filt_two = 8 * nkeys <= (1ull << fbits);
+      a.pre32 = scan_mode == 1 && !has_odd;
+      a.x32L = host_pow32(x32, a.Lmain);
       HIPCHK(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(tab.p), ~0ull, 2 * cap, s));
       HIPCHK(ctx, launch_fill_u64(tags.p, 0, cap / 8, s));
       HIPCHK(ctx, launch_fill_u64(oddb.p, 0, 6 * (uint64_t)T, s));
@@ -759,7 +809,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       as.lv.rs = seg_ws.p;
       as.lv.re = seg_re.p;
       as.lv.rtext = seg_text.p;
-      timed(ctx, "probe_scan", 0, 0, wst, 16.0, [&] {
+      // algorithmic bytes per window: the two prefix values it reads (8-byte
+      // 61-bit prefixes, or 4-byte 32-bit hashes when pre-filtering)
+      timed(ctx, "probe_scan", 0, 0, wst, a.pre32 ? 8.0 : 16.0, [&] {
         return launch_probe_scan(as, woff.p, has_odd, has_salt, c * b, scan_mode, s);
       });
       HIPCHK(ctx, launch_resolve(a, vb, s));

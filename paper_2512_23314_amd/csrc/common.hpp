@@ -74,6 +74,15 @@ __device__ __forceinline__ uint64_t filter_bit2(uint64_t fp, uint32_t bits) {
   return ((fp >> 17) ^ (fp >> 41) ^ (fp * 0x9E3779B1ull >> 20)) & ((1ull << bits) - 1);
 }
 
+// The two bits of a 32-bit window hash (mod 2^32 polynomial hash, whose high
+// bits depend on every byte) in a filter of 2^bits bits.
+__device__ __forceinline__ uint32_t filter_bit32(uint32_t h, uint32_t bits) {
+  return h >> (32 - bits);
+}
+__device__ __forceinline__ uint32_t filter_bit32b(uint32_t h, uint32_t bits) {
+  return (h * 0x9E3779B1u) >> (32 - bits);
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

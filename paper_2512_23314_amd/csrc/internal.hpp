@@ -19,9 +19,21 @@ struct PfPow {
   uint64_t xt[65];    // x^(tile k),   k = 0..64
 };
 
+// Powers of the base of the 32-bit prefix hash (arithmetic mod 2^32):
+// x1[k] = x^k, x16[k] = x^(16k), xt[k] = x^(kPfTile * k).
+struct PfPow32 {
+  uint32_t x1[17];
+  uint32_t x16[257];
+  uint32_t xt[65];
+};
+
 // status: ceil(n / tile) words, zeroed by the wrapper; ctr: one word.
 hipError_t launch_prefix_fp(const uint8_t* T, uint64_t n, uint64_t* P, const PfPow* pw,
                             uint64_t* status, uint32_t* ctr, hipStream_t s);
+// 32-bit prefix hashes H[0] = 0, H[i+1] = H[i] * x32 + T[i] (mod 2^32), the
+// cheap pre-filter of the probe scan (n + 1 outputs; status: tiles + 1 words).
+hipError_t launch_prefix_h32(const uint8_t* T, uint64_t n, uint32_t* H, const PfPow32* pw,
+                             uint64_t* status, uint32_t* ctr, hipStream_t s);
 
 // ---- level data (device arrays; positions are offsets into the text base) ----
 struct TextsDev {
@@ -95,6 +107,12 @@ struct PhaseArgs {
   uint32_t filt_bits;  // log2 of its size in bits (12..19); 0 = no filter
   uint32_t filt_two;   // 1: two bits per key, 0: one
   uint32_t all_blocks; // phase 2: keys for every block, not only unmarked ones
+  // 32-bit pre-filter hash: when pre32 is set the filter holds bits of the
+  // keys' 32-bit window hashes, and the scan computes a window's fingerprint
+  // only where its 32-bit hash passes the filter.
+  const uint32_t* P32;  // prefix hashes mod 2^32 (same indexing as P)
+  uint32_t x32L;        // x32^Lmain mod 2^32
+  uint32_t pre32;
 };
 
 // Scan entries and segments (level.hip, "scan segments").

@@ -77,12 +77,17 @@ __global__ void k_keys(PhaseArgs a) {
       a.tab.tag[h] = (uint8_t)tag_of(fp);  // every key of the slot writes the same byte
       atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
       if (a.filt_bits) {
-        const uint64_t f1 = filter_bit(fp, a.filt_bits);
+        uint64_t f1, f2;
+        if (a.pre32) {
+          const uint32_t h = a.P32[st + L] - a.P32[st] * a.x32L + (uint32_t)a.tx.tsalt[t];
+          f1 = filter_bit32(h, a.filt_bits);
+          f2 = filter_bit32b(h, a.filt_bits);
+        } else {
+          f1 = filter_bit(fp, a.filt_bits);
+          f2 = filter_bit2(fp, a.filt_bits);
+        }
         atomicOr(&a.filt[f1 >> 5], 1u << (f1 & 31));
-      }
-      if (a.filt_bits && a.filt_two) {
-        const uint64_t f2 = filter_bit2(fp, a.filt_bits);
-        atomicOr(&a.filt[f2 >> 5], 1u << (f2 & 31));
+        if (a.filt_two) atomicOr(&a.filt[f2 >> 5], 1u << (f2 & 31));
       }
     } else {
       // the one key of this text that ends at the text's end with a short block
@@ -295,13 +300,11 @@ __device__ __forceinline__ void probe(Slot* __restrict__ slots, const uint8_t* _
 // in step k lane l handles window chunk + 64k + l, so consecutive lanes read
 // consecutive prefix fingerprints.
 //
-// Before touching the table, a window's fingerprint is tested against a bit
-// filter of the phase's keys (one or two bits per key, set by k_keys) that every
+// Before touching the table, a window's hash is tested against a bit filter of
+// the phase's keys (one or two bits per key, set by k_keys) that every
 // workgroup first copies into LDS.  A clear bit proves that no key has this
-// fingerprint.  The windows that pass are appended to a per-wave queue in LDS
-// (ballot + prefix popcount) and probed 64 at a time, so a wave pays the
-// latency of the random table access once per 64 candidates instead of once
-// per step in which any lane has one.
+// hash.  The windows that pass are appended to a per-wave queue in LDS (ballot
+// + prefix popcount) and probed 64 at a time.
 constexpr int kProbeThreads = 1024;
 constexpr int kQueue = 128;  // entries per wave (< 64 pending + up to 64 new)
 
@@ -311,15 +314,41 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// MODE 0: no filter, every window probes the table.  MODE 1: filter, candidates
-// queued and probed 64 at a time.  MODE 2: filter, candidates probe at once (for
-// large filters, whose LDS leaves no room for the queues).
-template <int MODE, bool ODD, bool SALT>
-__global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
-                                                             const uint64_t* __restrict__ woff) {
+__device__ __forceinline__ bool filter_has(const uint32_t* s_filt, uint64_t b1, uint64_t b2) {
+  return ((s_filt[b1 >> 5] >> (b1 & 31)) & (s_filt[b2 >> 5] >> (b2 & 31)) & 1) != 0;
+}
+
+// Queue entries pack a window start (below 2^40) and its text (below 2^24).
+constexpr int kQPosBits = 40;
+constexpr uint64_t kQPosMask = (1ull << kQPosBits) - 1;
+
+// MODE 0: no filter, every window probes the table.  MODE 1: filter, and the
+// windows that pass go to a per-wave LDS queue; 64 queued windows at a time
+// then form their fingerprints and probe together, so a wave waits for one
+// round of loads per 64 candidates rather than per step.  MODE 2: filter,
+// candidates probe at once (no queue; texts beyond the queue's packing).
+//
+// PRE (MODE 1 only): the filter holds bits of the keys' 32-bit hashes
+// (H[i+L] - H[i] x32^L mod 2^32), and the scan reads only H for every window;
+// the 61-bit fingerprint is formed for queued windows alone.  Equal strings
+// have equal hashes of both kinds, so every occurrence of a key still reaches
+// the table; a window that agrees with a key in both hashes without being an
+// occurrence is a collision, caught by the same verification as before.
+//
+// A chunk in which every lane's 16 windows lie inside that lane's current
+// segment (the usual case on long runs) takes a straight-line path that issues
+// eight windows' loads before using any of them.
+//
+// Two 1024-thread workgroups per CU need 8 waves per SIMD: the register budget
+// (SGPRs included) is held to that.
+template <int MODE, bool ODD, bool SALT, bool PRE>
+__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   constexpr bool FILTER = MODE != 0;
+  static_assert(!PRE || MODE == 1, "the 32-bit hash feeds the queued filter only");
   extern __shared__ uint64_t s_lds[];
   const uint32_t fbits = a.filt_bits;
+  const bool two = a.filt_two != 0;
   uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);
   if (FILTER) {
     const uint32_t nq = (uint32_t)(1ull << (fbits - 7));  // uint4 words
@@ -329,8 +358,7 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
     __syncthreads();
   }
   const int lane = lane_id();
-  uint64_t* qf = s_lds + (1ull << (fbits - 6)) + (uint64_t)(threadIdx.x >> 6) * (2 * kQueue);
-  uint64_t* qi = qf + kQueue;
+  uint64_t* q = s_lds + (FILTER ? (1ull << (fbits - 6)) : 0) + (uint64_t)(threadIdx.x >> 6) * kQueue;
   uint32_t qn = 0;  // wave-uniform queue length
 
   const uint64_t R = a.lv.R;
@@ -338,12 +366,53 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
   const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t* __restrict__ P = a.P;
+  const uint32_t* __restrict__ H = a.P32;
   const uint64_t* __restrict__ rs_ = a.lv.rs;
   const uint64_t* __restrict__ re_ = a.lv.re;
   const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
+  const uint32_t x32L = a.x32L;
   Slot* __restrict__ slots = a.tab.slots;
   const uint8_t* __restrict__ tags = a.tab.tag;
   const uint64_t mask = a.tab.mask;
+
+  const auto fp61 = [&](uint64_t i, uint64_t salt) {
+    uint64_t f = sub61(P[i + L], mul61(P[i], xL));
+    if (SALT) f = add61(f, salt);
+    return f & fmask;
+  };
+  const auto pass32 = [&](uint32_t h) {
+    const uint32_t b1 = filter_bit32(h, fbits);
+    return filter_has(s_filt, b1, two ? filter_bit32b(h, fbits) : b1);
+  };
+  const auto pass61 = [&](uint64_t f) {
+    const uint64_t b1 = filter_bit(f, fbits);
+    return filter_has(s_filt, b1, two ? filter_bit2(f, fbits) : b1);
+  };
+  // the entry this lane holds: form its fingerprint and probe
+  const auto probe_entry = [&](uint64_t e) {
+    const uint64_t i = e & kQPosMask;
+    const uint64_t salt = SALT ? a.tx.tsalt[e >> kQPosBits] : 0;
+    probe(slots, tags, mask, fp61(i, salt), i);
+  };
+  // whole wave: append the lanes' candidates; probe 64 once 64 are waiting
+  const auto push = [&](bool cand, uint64_t i, uint32_t t) {
+    const uint64_t bal = __ballot(cand);
+    if (!bal) return;
+    const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+    if (cand) q[qn + my] = ((uint64_t)t << kQPosBits) | i;
+    qn += (uint32_t)__popcll(bal);
+    if (qn >= 64) {
+      wave_sync();
+      const uint64_t e = q[lane];
+      const bool mv = (uint32_t)lane < qn - 64;
+      const uint64_t e2 = mv ? q[64 + lane] : 0;
+      wave_sync();
+      if (mv) q[lane] = e2;
+      qn -= 64;
+      probe_entry(e);
+      wave_sync();
+    }
+  };
 
   for (uint64_t ch = gw; ch * kScanChunk < W; ch += nw) {
     const uint64_t w0 = ch * kScanChunk + lane;
@@ -356,6 +425,41 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
     uint64_t wo = woff[r], wn = woff[r + 1], rs = rs_[r], re = re_[r];
     uint32_t t = (ODD || SALT) ? a.lv.rtext[r] : 0;
     uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
+
+    if (!ODD) {
+      const uint64_t wl = w0 + 64ull * (kScanK - 1);
+      const bool lane_ok = wl < wn && rs + (wl - wo) + L <= re;
+      if (__ballot(lane_ok) == ~0ull) {
+        const uint64_t i0 = rs + (w0 - wo);
+#pragma unroll
+        for (int k0 = 0; k0 < kScanK; k0 += 8) {
+          if (PRE) {
+            const uint32_t s32 = SALT ? (uint32_t)salt : 0u;
+            uint32_t hv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint64_t i = i0 + 64ull * (k0 + k);
+              hv[k] = H[i + L] - H[i] * x32L + s32;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) push(pass32(hv[k]), i0 + 64ull * (k0 + k), t);
+          } else {
+            uint64_t fv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) fv[k] = fp61(i0 + 64ull * (k0 + k), salt);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint64_t i = i0 + 64ull * (k0 + k);
+              const bool cand = FILTER ? pass61(fv[k]) : true;
+              if (MODE == 1) push(cand, i, t);
+              else if (cand) probe(slots, tags, mask, fv[k], i);
+            }
+          }
+        }
+        continue;
+      }
+    }
+
     for (int k = 0; k < kScanK; ++k) {
       const uint64_t w = w0 + (uint64_t)k * 64;
       const bool live = w < W;  // every lane stays in the loop (the queue is wave-wide)
@@ -371,57 +475,23 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
         if (SALT) salt = a.tx.tsalt[t];
       }
       const uint64_t i = rs + (w - wo);
-      uint64_t pi = 0, fp = 0;
       bool cand = false;
-      if (live) {
-        pi = P[i];
-        if (i + L <= re) {
-          fp = sub61(P[i + L], mul61(pi, xL));
-          if (SALT) fp = add61(fp, salt);
-          fp &= fmask;
-          if (FILTER) {
-            const uint64_t b1 = filter_bit(fp, fbits);
-            const uint64_t b2 = a.filt_two ? filter_bit2(fp, fbits) : b1;
-            cand = ((s_filt[b1 >> 5] >> (b1 & 31)) & (s_filt[b2 >> 5] >> (b2 & 31)) & 1) != 0;
-            if (MODE == 2 && cand) probe(slots, tags, mask, fp, i);
-          } else {
-            probe(slots, tags, mask, fp, i);
-          }
+      if (live && i + L <= re) {
+        if (PRE) {
+          cand = pass32(H[i + L] - H[i] * x32L + (SALT ? (uint32_t)salt : 0u));
+        } else {
+          const uint64_t f = fp61(i, salt);
+          cand = FILTER ? pass61(f) : true;
+          if (MODE != 1 && cand) probe(slots, tags, mask, f, i);
         }
       }
-      const uint64_t bal = MODE == 1 ? __ballot(cand) : 0;
-      if (MODE == 1 && bal) {
-        const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
-        if (cand) {
-          qf[qn + my] = fp;
-          qi[qn + my] = i;
-        }
-        qn += (uint32_t)__popcll(bal);
-        if (qn >= 64) {
-          wave_sync();
-          const uint64_t f = qf[lane], ii = qi[lane];
-          const bool mv = (uint32_t)lane < qn - 64;
-          uint64_t f2 = 0, i2 = 0;
-          if (mv) {
-            f2 = qf[64 + lane];
-            i2 = qi[64 + lane];
-          }
-          wave_sync();
-          if (mv) {
-            qf[lane] = f2;
-            qi[lane] = i2;
-          }
-          qn -= 64;
-          probe(slots, tags, mask, f, ii);
-          wave_sync();
-        }
-      }
+      if (MODE == 1) push(cand, i, t);
       if (ODD && live) {
         const uint64_t oL = a.odd.L[t];
         if (oL && i + oL <= re && i < a.odd.pos[t]) {
-          uint64_t f = sub61(P[i + oL], mul61(pi, a.odd.xp[t]));
-          if (SALT) f = add61(f, salt);
-          if ((f & fmask) == a.odd.fp[t] && i < a.odd.best[t])
+          uint64_t g = sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+          if (SALT) g = add61(g, salt);
+          if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
             atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
         }
       }
@@ -429,37 +499,60 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_scan(PhaseArgs a,
   }
   if (MODE == 1 && qn) {
     wave_sync();
-    if ((uint32_t)lane < qn) probe(slots, tags, mask, qf[lane], qi[lane]);
+    if ((uint32_t)lane < qn) probe_entry(q[lane]);
   }
+}
+
+// Dynamic LDS beyond 64 KiB has to be allowed per kernel.
+static hipError_t allow_lds(const void* fn, size_t bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
                              bool has_salt, uint64_t max_windows, int mode, hipStream_t s) {
   if (a.lv.R == 0) return hipSuccess;
   const uint64_t waves = (max_windows + kScanChunk - 1) / kScanChunk;
-  // two 1024-thread workgroups per CU: LDS of at most 64 KiB each (mode 1: filter
-  // up to 32 KiB + queues 32 KiB; mode 2: filter up to 64 KiB)
+  // two 1024-thread workgroups per CU: LDS of at most 80 KiB each (mode 1:
+  // filter up to 64 KiB + queues 16 KiB; mode 2: filter up to 64 KiB)
   const unsigned grid = grid_for(waves * 64, kProbeThreads, 512);
   size_t lds = 0;
   if (mode == 1)
-    lds = ((size_t)1 << (a.filt_bits - 3)) + (size_t)(kProbeThreads / 64) * 2 * kQueue * 8;
+    lds = ((size_t)1 << (a.filt_bits - 3)) + (size_t)(kProbeThreads / 64) * kQueue * 8;
   else if (mode == 2)
     lds = (size_t)1 << (a.filt_bits - 3);
-#define BT_PROBE_LAUNCH(M, O, S) k_probe_scan<M, O, S><<<grid, kProbeThreads, lds, s>>>(a, woff)
-#define BT_PROBE_MODE(M)                                                  \
-  if (has_odd) {                                                          \
-    if (has_salt) BT_PROBE_LAUNCH(M, true, true); else BT_PROBE_LAUNCH(M, true, false);   \
-  } else {                                                                \
-    if (has_salt) BT_PROBE_LAUNCH(M, false, true); else BT_PROBE_LAUNCH(M, false, false); \
-  }
+  // the keys filled the filter from the hash kind that pre32 names
+  if (a.pre32 && (mode != 1 || has_odd)) return hipErrorInvalidValue;
+  const bool pre = a.pre32 != 0;
+#define BT_PROBE_LAUNCH(M, O, S, Q)                                                      \
+  do {                                                                                   \
+    if (lds > 65536) {                                                                   \
+      const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_probe_scan<M, O, S, Q>), lds); \
+      if (e != hipSuccess) return e;                                                     \
+    }                                                                                    \
+    k_probe_scan<M, O, S, Q><<<grid, kProbeThreads, lds, s>>>(a, woff);                  \
+  } while (0)
+#define BT_PROBE_SALT(M, O, Q) \
+  if (has_salt) BT_PROBE_LAUNCH(M, O, true, Q); else BT_PROBE_LAUNCH(M, O, false, Q);
   if (mode == 1) {
-    BT_PROBE_MODE(1)
+    if (has_odd) {
+      BT_PROBE_SALT(1, true, false)
+    } else if (pre) {
+      BT_PROBE_SALT(1, false, true)
+    } else {
+      return hipErrorInvalidValue;  // queued scans without a short key pre-filter
+    }
   } else if (mode == 2) {
-    BT_PROBE_MODE(2)
+    if (has_odd) {
+      BT_PROBE_SALT(2, true, false)
+    } else {
+      BT_PROBE_SALT(2, false, false)
+    }
+  } else if (has_odd) {
+    BT_PROBE_SALT(0, true, false)
   } else {
-    BT_PROBE_MODE(0)
+    BT_PROBE_SALT(0, false, false)
   }
-#undef BT_PROBE_MODE
+#undef BT_PROBE_SALT
 #undef BT_PROBE_LAUNCH
   return hipGetLastError();
 }
