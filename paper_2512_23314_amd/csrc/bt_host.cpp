@@ -768,6 +768,12 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.marked = marked.p;
     a.filt = filt.p;
 
+    // Phase-2 segments come from this level's blocks and pair facts.
+    Buf<uint64_t> bwc = alloc<uint64_t>(ctx, c + 1), bhd = alloc<uint64_t>(ctx, c + 1);
+    Buf<uint64_t> bws = alloc<uint64_t>(ctx, c), bre = alloc<uint64_t>(ctx, c);
+    Buf<uint64_t> bwoff = alloc<uint64_t>(ctx, c + 1);
+    Buf<uint32_t> btext = alloc<uint32_t>(ctx, c);
+
     // nkeys: keys of the phase (pairs of consecutive blocks, or unmarked blocks)
     auto run_phase = [&](int phase, uint64_t nkeys) {
       a.phase = phase;
@@ -800,19 +806,32 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       HIPCHK(ctx, launch_fill_u64(vcnt.p, 0, 2, s));
       if (scan_mode) HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
       HIPCHK(ctx, launch_keys(a, s));
-      HIPCHK(ctx, launch_segments(a, sg, woff.p, s));
-      scan(woff.p, E_ent);
-      uint64_t* wst = wstats.p + 2 * step + (phase - 1);
-      HIPCHK(ctx, hipMemcpyAsync(wst, woff.p + E_ent, 8, hipMemcpyDeviceToDevice, s));
       PhaseArgs as = a;  // the scan walks segments in place of runs
-      as.lv.R = E_ent;
-      as.lv.rs = seg_ws.p;
-      as.lv.re = seg_re.p;
-      as.lv.rtext = seg_text.p;
+      uint64_t* swoff = woff.p;
+      uint64_t* wst = wstats.p + 2 * step + (phase - 1);
+      if (phase == 1) {
+        HIPCHK(ctx, launch_segments(a, sg, woff.p, s));
+        scan(woff.p, E_ent);
+        as.lv.R = E_ent;
+        as.lv.rs = seg_ws.p;
+        as.lv.re = seg_re.p;
+        as.lv.rtext = seg_text.p;
+      } else {
+        HIPCHK(ctx, launch_block_seg_counts(a, facts.p, bwc.p, bhd.p, s));
+        scan(bwc.p, c);
+        scan(bhd.p, c);
+        HIPCHK(ctx, launch_block_segments(a, bwc.p, bhd.p, bws.p, bre.p, btext.p, bwoff.p, s));
+        swoff = bwoff.p;
+        as.lv.R = c;
+        as.lv.rs = bws.p;
+        as.lv.re = bre.p;
+        as.lv.rtext = btext.p;
+      }
+      HIPCHK(ctx, hipMemcpyAsync(wst, swoff + as.lv.R, 8, hipMemcpyDeviceToDevice, s));
       // algorithmic bytes per window: the two prefix values it reads (8-byte
       // 61-bit prefixes, or 4-byte 32-bit hashes when pre-filtering)
       timed(ctx, "probe_scan", 0, 0, wst, a.pre32 ? 8.0 : 16.0, [&] {
-        return launch_probe_scan(as, woff.p, has_odd, has_salt, c * b, scan_mode, s);
+        return launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
       });
       HIPCHK(ctx, launch_resolve(a, vb, s));
       timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });

@@ -9,18 +9,20 @@ namespace bt {
 
 // ---- prefix fingerprints (step a2) ----
 constexpr int kPfThreads = 256;
-constexpr int kPfBytes = 16;                       // bytes per thread
-constexpr uint64_t kPfTile = kPfThreads * kPfBytes;  // bytes per tile
+constexpr int kPfBytes = 16;                            // bytes per thread per row
+constexpr uint64_t kPfRow = kPfThreads * kPfBytes;      // bytes per row (4 KiB)
+constexpr int kPfRows = 4;                              // rows per tile
+constexpr uint64_t kPfTile = kPfRow * kPfRows;          // bytes per tile (16 KiB)
 
-// Powers of the base used by the prefix scan, computed on the host.
+// Powers of the base used by the prefix scan, computed on the host
+// (x^(16 * 256) = x^row is x16[256]).
 struct PfPow {
   uint64_t x1[17];    // x^k,          k = 0..16
   uint64_t x16[257];  // x^(16 k),     k = 0..256
   uint64_t xt[65];    // x^(tile k),   k = 0..64
 };
 
-// Powers of the base of the 32-bit prefix hash (arithmetic mod 2^32):
-// x1[k] = x^k, x16[k] = x^(16k), xt[k] = x^(kPfTile * k).
+// The same powers for the 32-bit prefix hash (arithmetic mod 2^32).
 struct PfPow32 {
   uint32_t x1[17];
   uint32_t x16[257];
@@ -153,6 +155,12 @@ hipError_t launch_entry_runs(const uint64_t* echild, uint64_t E, const uint32_t*
                              uint32_t* erun, hipStream_t s);
 // Per-segment window counts into woff[0..E) (then scanned by the caller).
 hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff, hipStream_t s);
+// Phase-2 segments from this level's pair facts (bit 0 of pf); see level.hip.
+hipError_t launch_block_seg_counts(const PhaseArgs& a, const uint8_t* pf, uint64_t* wc,
+                                   uint64_t* head, hipStream_t s);
+hipError_t launch_block_segments(const PhaseArgs& a, const uint64_t* wcs, const uint64_t* hs,
+                                 uint64_t* ws, uint64_t* sre, uint32_t* stext, uint64_t* woff,
+                                 hipStream_t s);
 // The sliding-window probe.  max_windows bounds the grid; mode 0: no filter,
 // 1: LDS key filter and per-wave candidate queues, 2: LDS key filter, inline probe.
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,

@@ -258,6 +258,71 @@ hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff,
   return hipGetLastError();
 }
 
+// Phase-2 segments from this level's phase-1 results.  A window of length b
+// that starts in block Q lies inside the pair (Q, Q+1), so if that pair occurs
+// earlier, so does the window: Q contributes no window starts.  Consecutive
+// blocks of a run that keep their starts form one segment (their starts are
+// consecutive positions).
+//   k_block_seg_counts: wc[Q] = starts of Q, head[Q] = 1 where a segment begins;
+//   (exclusive scans of both, totals at index c)
+//   k_block_segments: segment k < S (S = head total) from its first block;
+//   entries S..c repeat the window total, so a scan over c segments works.
+__global__ void k_block_seg_counts(PhaseArgs a, const uint8_t* pf, uint64_t* wc, uint64_t* head) {
+  const LevelDev lv = a.lv;
+  GRID_STRIDE(Q, lv.c) {
+    const uint32_t t = lv.text[Q];
+    const uint64_t re = lv.re[lv.run[Q]];
+    const uint64_t st = lv.st[Q];
+    uint64_t Lmin = a.Lmain;
+    const uint64_t oL = a.odd.L[t];
+    if (oL && oL < Lmin) Lmin = oL;
+    uint64_t cnt = 0;
+    if (a.odd.nkeys[t] && !(pf[Q] & 1) && re >= Lmin) {
+      uint64_t hi = st + block_len(lv, a.tx, Q) - 1;
+      if (re - Lmin < hi) hi = re - Lmin;
+      if (hi >= st) cnt = hi - st + 1;
+    }
+    wc[Q] = cnt;
+    bool h = cnt != 0;
+    if (h && Q > 0 && lv.run[Q - 1] == lv.run[Q] && !(pf[Q - 1] & 1)) {
+      // the previous block keeps its starts: they run up to st - 1 (a block
+      // whose starts stop short of its end is the run's last with any)
+      h = false;
+    }
+    head[Q] = h ? 1 : 0;
+  }
+}
+
+__global__ void k_block_segments(PhaseArgs a, const uint64_t* wcs, const uint64_t* hs,
+                                 uint64_t* ws, uint64_t* sre, uint32_t* stext, uint64_t* woff) {
+  const LevelDev lv = a.lv;
+  const uint64_t S = hs[lv.c], W = wcs[lv.c];
+  GRID_STRIDE(k, lv.c + 1) {
+    if (k < lv.c && hs[k + 1] != hs[k]) {
+      const uint64_t g = hs[k];
+      woff[g] = wcs[k];
+      ws[g] = lv.st[k];
+      sre[g] = lv.re[lv.run[k]];
+      stext[g] = lv.text[k];
+    }
+    if (k >= S) woff[k] = W;
+  }
+}
+
+hipError_t launch_block_seg_counts(const PhaseArgs& a, const uint8_t* pf, uint64_t* wc,
+                                   uint64_t* head, hipStream_t s) {
+  if (!a.lv.c) return hipSuccess;
+  k_block_seg_counts<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, pf, wc, head);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_segments(const PhaseArgs& a, const uint64_t* wcs, const uint64_t* hs,
+                                 uint64_t* ws, uint64_t* sre, uint32_t* stext, uint64_t* woff,
+                                 hipStream_t s) {
+  k_block_segments<<<grid_for(a.lv.c + 1, 256), 256, 0, s>>>(a, wcs, hs, ws, sre, stext, woff);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- probe scan (a4, a6)
 
 constexpr int kScanK = 16;                      // windows per lane per chunk
@@ -559,25 +624,57 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
 
 // ---------------------------------------------------------------- resolve / verify / retry
 
-__global__ void k_resolve(PhaseArgs a, VerifyBufs v) {
-  GRID_STRIDE(j, a.lv.c) {
-    const uint32_t s = a.k.slot[j];
-    if (s == kNoKey) continue;
-    const uint64_t pos = a.lv.st[j];
-    const uint64_t best = (s == kOddKey) ? a.odd.best[a.lv.text[j]] : a.tab.slots[s].best;
-    if (best == pos) {
-      a.k.lm[j] = pos;
-    } else {
-      const uint64_t idx = atomicAdd((unsigned long long*)&v.counts[0], 1ull);
+// Keys whose slot minimum is their own position are their own leftmost
+// occurrence; the rest are appended to the verification list.  Returning
+// atomics on one address serialize (about 10 ns apart), so a 1024-thread
+// workgroup claims its whole share of the list with a single update.
+constexpr int kResolveThreads = 1024;
+
+__global__ __launch_bounds__(kResolveThreads) void k_resolve(PhaseArgs a, VerifyBufs v) {
+  __shared__ uint32_t s_w[kResolveThreads / 64];
+  __shared__ unsigned long long s_base;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const uint64_t c = a.lv.c;
+  for (uint64_t j0 = (uint64_t)blockIdx.x * kResolveThreads; j0 < c;
+       j0 += (uint64_t)gridDim.x * kResolveThreads) {
+    const uint64_t j = j0 + threadIdx.x;
+    bool need = false;
+    uint64_t best = 0;
+    if (j < c) {
+      const uint32_t s = a.k.slot[j];
+      if (s != kNoKey) {
+        const uint64_t pos = a.lv.st[j];
+        best = (s == kOddKey) ? a.odd.best[a.lv.text[j]] : a.tab.slots[s].best;
+        if (best == pos) a.k.lm[j] = pos;
+        else need = true;
+      }
+    }
+    const uint64_t bal = __ballot(need);
+    if (lane == 0) s_w[wv] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int q = 0; q < kResolveThreads / 64; ++q) {
+        const uint32_t n = s_w[q];
+        s_w[q] = tot;
+        tot += n;
+      }
+      s_base = tot ? atomicAdd((unsigned long long*)&v.counts[0], (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    if (need) {
+      const uint64_t idx = s_base + s_w[wv] + __popcll(bal & ((1ull << lane) - 1));
       v.vlist[idx] = (uint32_t)j;
       v.vbest[idx] = best;
       v.vmis[idx] = 0;
     }
+    __syncthreads();  // s_w and s_base are reused
   }
 }
 
 hipError_t launch_resolve(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s) {
-  k_resolve<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, v);
+  k_resolve<<<grid_for(a.lv.c, kResolveThreads, 2048), kResolveThreads, 0, s>>>(a, v);
   return hipGetLastError();
 }
 

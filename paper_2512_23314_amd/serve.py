@@ -25,7 +25,8 @@ from . import Context, BtError
 
 def build_footprint(n, tau=4, leaf_len=16, sigma=256, rank_select=False):
     """Upper bound on the device bytes a build of an n-byte text needs while it
-    runs: the text (n) and its prefix fingerprints (8(n+1)); about 320 bytes per
+    runs: the text (n), its prefix fingerprints (8(n+1)) and 32-bit prefix
+    hashes (4(n+1)); about 320 bytes per
     block of the largest scanned level (block, run, key, table at load 1/2 or
     less, verification, pointer and split arrays; that level has at most
     n / (tau * leaf_len) + 2 blocks); the leaf bytes; with rank/select support,
@@ -33,7 +34,7 @@ def build_footprint(n, tau=4, leaf_len=16, sigma=256, rank_select=False):
     2n / leaf_len + 2 of each) and the sampled count table; 16 MiB for small
     buffers."""
     blocks = n // max(tau * leaf_len, 1) + 2
-    foot = 9 * n + 8 + 320 * blocks + 2 * n + (16 << 20)
+    foot = 13 * n + 12 + 320 * blocks + 2 * n + (16 << 20)
     if rank_select:
         foot += 8 * sigma * (2 * n // max(leaf_len, 1) + 2) + 16 * sigma * (n // 1024 + 2)
     return foot

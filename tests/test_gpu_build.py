@@ -28,7 +28,10 @@ def _build(ctx, T, tau, leaf, sigma=256, **kw):
 
 # ---- step a2: prefix fingerprints
 
-@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4095, 4096, 4097, 65536 * 3 + 7, (1 << 20) + 13])
+# sizes around a thread's 16 bytes, a 4 KiB row, a 16 KiB tile, and enough tiles
+# for the look-back to cross more than one window of 64 tiles
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4095, 4096, 4097, 12289, 16383, 16384, 16385,
+                               65536 * 3 + 7, (1 << 20) + 13, (5 << 20) + 1])
 def test_prefix_fingerprints(ctx, n):
     rng = np.random.default_rng(n + 1)
     T = rng.integers(0, 256, n).astype(np.uint8)
