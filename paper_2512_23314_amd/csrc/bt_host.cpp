@@ -749,6 +749,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint8_t> marked = alloc<uint8_t>(ctx, c);
     // LDS key filter of up to 2^19 bits, sized per phase from the key count
     Buf<uint32_t> filt = alloc<uint32_t>(ctx, (1ull << 19) / 32);
+    // second key filter (global memory, at most 2^24 bits = 2 MiB: stays in L2)
+    Buf<uint32_t> filt2 = alloc<uint32_t>(ctx, (1ull << 24) / 32);
     int scan_mode = 1;
     uint32_t fbits = 12;
     VerifyBufs vb{vlist.p, vbest.p, vmis.p, rlist.p, rlb.p, vcnt.p};
@@ -767,6 +769,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.fpmask = fpmask;
     a.marked = marked.p;
     a.filt = filt.p;
+    a.filt2 = filt2.p;
 
     // Phase-2 segments come from this level's blocks and pair facts.
     Buf<uint64_t> bwc = alloc<uint64_t>(ctx, c + 1), bhd = alloc<uint64_t>(ctx, c + 1);
@@ -779,26 +782,37 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       a.phase = phase;
       a.Lmain = phase == 1 ? 2 * b : b;
       a.xLmain = host_pow61(x, a.Lmain);
-      // About 32 filter bits per key, at most 2^19 (64 KiB of LDS), two bits
-      // per key while there are at least 8 bits per key.  Up to 2^18 keys the
-      // scan queues its candidates (mode 1) and tests the 32-bit pre-filter
-      // hash, unless the level has a short final key (whose per-window check
-      // reads the 61-bit prefix anyway; then up to 2^17 keys).  Beyond that
-      // most windows pass any filter that fits in LDS: a 2^19-bit filter
-      // without queues (mode 2) on 61-bit fingerprints.  Queue entries pack a
-      // position below 2^40 and a text below 2^24; past that, mode 2.
+      // LDS filter: about 32 bits per key, at most 2^19 (64 KiB), two bits per
+      // key while there are at least 8 bits per key.  Up to 2^18 keys (2^17
+      // on levels with a short final key, whose per-window check reads the
+      // 61-bit prefix anyway) the scan queues its candidates (mode 1) and,
+      // without a short key, tests the 32-bit pre-filter hash; from 2^14 keys
+      // on, where the LDS filter starts to pass a sizeable share of the
+      // windows, those also test a blocked second filter in global memory of
+      // about 16 bits per key (at most 2^24 bits, L2-resident).  Beyond that
+      // most windows pass any filter that fits in LDS, and the table's tag
+      // bytes are the cheapest second test: a 2^19-bit filter on 61-bit
+      // fingerprints without queues (mode 2).  Queue entries pack a position
+      // below 2^40 and a text below 2^24; past that, mode 2.
       fbits = 12;
       while (fbits < 19 && (1ull << fbits) < 32 * nkeys) ++fbits;
+      uint32_t f2words = 0;
       const bool can_queue = T <= (1u << 24) && offs[T] < (1ull << 40);
       if (can_queue && nkeys <= (has_odd ? (1ull << 17) : (1ull << 18))) {
         scan_mode = 1;
+        if (!has_odd && nkeys >= (1ull << 14)) {
+          f2words = 11;
+          while (f2words < 19 && (32ull << f2words) < 16 * nkeys) ++f2words;
+        }
       } else {
         scan_mode = 2;
-        fbits = std::max<uint32_t>(fbits, 19);
+        fbits = 19;
       }
       a.filt_bits = fbits;
       a.filt_two = 8 * nkeys <= (1ull << fbits);
       a.pre32 = scan_mode == 1 && !has_odd;
+      a.filt2_words = f2words;
+      if (f2words) HIPCHK(ctx, launch_fill_u32(filt2.p, 0, 1ull << f2words, s));
       a.x32L = host_pow32(x32, a.Lmain);
       HIPCHK(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(tab.p), ~0ull, 2 * cap, s));
       HIPCHK(ctx, launch_fill_u64(tags.p, 0, cap / 8, s));

@@ -83,6 +83,18 @@ __device__ __forceinline__ uint32_t filter_bit32b(uint32_t h, uint32_t bits) {
   return (h * 0x9E3779B1u) >> (32 - bits);
 }
 
+// Second (global, L2-resident) filter of a 32-bit window hash: blocked, both
+// bits in one 32-bit word, so that a test is one load.  The word and the two
+// bit positions come from multiplicative hashes with their own odd constants,
+// unrelated to the bits the LDS filter takes.  words_log2 = log2(words).
+__device__ __forceinline__ uint32_t filter2_word(uint32_t h, uint32_t words_log2) {
+  return (h * 0x6F4F2A35u) >> (32 - words_log2);
+}
+__device__ __forceinline__ uint32_t filter2_mask(uint32_t h) {
+  const uint32_t m = h * 0xD35A2D97u;
+  return (1u << (m >> 27)) | (1u << ((m >> 22) & 31));
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -115,6 +115,12 @@ struct PhaseArgs {
   const uint32_t* P32;  // prefix hashes mod 2^32 (same indexing as P)
   uint32_t x32L;        // x32^Lmain mod 2^32
   uint32_t pre32;
+  // With pre32: a second, blocked bit filter of the keys' 32-bit hashes in
+  // global memory (2^filt2_words 32-bit words, two bits of one word per key;
+  // 0 = none), tested by the windows that pass the LDS filter before they are
+  // queued.
+  uint32_t* filt2;
+  uint32_t filt2_words;
 };
 
 // Scan entries and segments (level.hip, "scan segments").

@@ -82,6 +82,8 @@ __global__ void k_keys(PhaseArgs a) {
           const uint32_t h = a.P32[st + L] - a.P32[st] * a.x32L + (uint32_t)a.tx.tsalt[t];
           f1 = filter_bit32(h, a.filt_bits);
           f2 = filter_bit32b(h, a.filt_bits);
+          if (a.filt2_words)
+            atomicOr(&a.filt2[filter2_word(h, a.filt2_words)], filter2_mask(h));
         } else {
           f1 = filter_bit(fp, a.filt_bits);
           f2 = filter_bit2(fp, a.filt_bits);
@@ -449,6 +451,12 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     const uint32_t b1 = filter_bit32(h, fbits);
     return filter_has(s_filt, b1, two ? filter_bit32b(h, fbits) : b1);
   };
+  const uint32_t* __restrict__ filt2 = a.filt2;
+  const uint32_t f2words = a.filt2_words;
+  const auto pass2 = [&](uint32_t h) {
+    const uint32_t m = filter2_mask(h);
+    return (filt2[filter2_word(h, f2words)] & m) == m;
+  };
   const auto pass61 = [&](uint64_t f) {
     const uint64_t b1 = filter_bit(f, fbits);
     return filter_has(s_filt, b1, two ? filter_bit2(f, fbits) : b1);
@@ -506,8 +514,22 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
               const uint64_t i = i0 + 64ull * (k0 + k);
               hv[k] = H[i + L] - H[i] * x32L + s32;
             }
+            bool ok[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) push(pass32(hv[k]), i0 + 64ull * (k0 + k), t);
+            for (int k = 0; k < 8; ++k) ok[k] = pass32(hv[k]);
+            if (f2words) {
+              // second filter: the eight steps' loads are issued together
+              uint32_t wv[8];
+#pragma unroll
+              for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? filt2[filter2_word(hv[k], f2words)] : ~0u;
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const uint32_t m = filter2_mask(hv[k]);
+                ok[k] = ok[k] && (wv[k] & m) == m;
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) push(ok[k], i0 + 64ull * (k0 + k), t);
           } else {
             uint64_t fv[8];
 #pragma unroll
@@ -543,7 +565,8 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
       bool cand = false;
       if (live && i + L <= re) {
         if (PRE) {
-          cand = pass32(H[i + L] - H[i] * x32L + (SALT ? (uint32_t)salt : 0u));
+          const uint32_t h = H[i + L] - H[i] * x32L + (SALT ? (uint32_t)salt : 0u);
+          cand = pass32(h) && (!f2words || pass2(h));
         } else {
           const uint64_t f = fp61(i, salt);
           cand = FILTER ? pass61(f) : true;
