@@ -180,6 +180,10 @@ struct bt_ctx {
   uint64_t* h_small = nullptr;  // pinned host words for count read-back
   size_t h_small_words = 0;
   PfPow* h_pw = nullptr;        // pinned staging for the power table
+  // pinned staging of host-to-device uploads: a bump region that is reused
+  // only after the stream has been synchronized (every earlier upload is done)
+  uint64_t* h_stage = nullptr;
+  size_t h_stage_words = 0, h_stage_used = 0;
 };
 
 // Device-resident storage shared by the trees of one build.
@@ -390,6 +394,26 @@ uint64_t* small_host(bt_ctx* ctx, size_t words) {
   return ctx->h_small;
 }
 
+// Pinned staging for an upload of `words` u64 (see bt_ctx::h_stage).
+uint64_t* stage_host(bt_ctx* ctx, size_t words) {
+  if (ctx->h_stage_used + words > ctx->h_stage_words) {
+    // queued uploads may still read the region: let them finish first
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->h_stage_used = 0;
+    if (words > ctx->h_stage_words) {
+      if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+      ctx->h_stage = nullptr;
+      ctx->h_stage_words = 0;
+      const size_t w = std::max<size_t>({words, 2 * ctx->h_stage_words, 1 << 16});
+      HIPCHK(ctx, hipHostMalloc((void**)&ctx->h_stage, w * 8, hipHostMallocDefault));
+      ctx->h_stage_words = w;
+    }
+  }
+  uint64_t* p = ctx->h_stage + ctx->h_stage_used;
+  ctx->h_stage_used += words;
+  return p;
+}
+
 // Read `words` u64 from device (stream-ordered, then synchronise).
 void read_words(bt_ctx* ctx, std::vector<std::pair<const uint64_t*, uint64_t>> src,
                 std::vector<uint64_t>& out) {
@@ -403,6 +427,7 @@ void read_words(bt_ctx* ctx, std::vector<std::pair<const uint64_t*, uint64_t>> s
     o += s.second;
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->h_stage_used = 0;  // every queued upload has completed
   collect_events(ctx);
   out.assign(h, h + tot);
 }
@@ -410,12 +435,12 @@ void read_words(bt_ctx* ctx, std::vector<std::pair<const uint64_t*, uint64_t>> s
 template <typename T>
 void upload(bt_ctx* ctx, T* d, const T* h, uint64_t n) {
   if (!n) return;
-  // stage through pinned memory so the copy is stream-ordered and async-safe
+  // stage through pinned memory: the copy is stream-ordered, and the host
+  // does not wait for it
   const uint64_t words = (n * sizeof(T) + 7) / 8;
-  uint64_t* st = small_host(ctx, words);
+  uint64_t* st = stage_host(ctx, words);
   std::memcpy(st, h, n * sizeof(T));
   HIPCHK(ctx, hipMemcpyAsync(d, st, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
 }
 
 struct Plan {
@@ -1111,6 +1136,7 @@ void bt_ctx_destroy(bt_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->h_pw) (void)hipHostFree(ctx->h_pw);
   ctx->pool->trim();
   delete ctx;

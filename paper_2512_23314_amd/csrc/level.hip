@@ -268,7 +268,8 @@ hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff,
 //   k_block_seg_counts: wc[Q] = starts of Q, head[Q] = 1 where a segment begins;
 //   (exclusive scans of both, totals at index c)
 //   k_block_segments: segment k < S (S = head total) from its first block;
-//   entries S..c repeat the window total, so a scan over c segments works.
+//   entries S..c repeat the window total (and name text 0), so a scan over c
+//   segments works.
 __global__ void k_block_seg_counts(PhaseArgs a, const uint8_t* pf, uint64_t* wc, uint64_t* head) {
   const LevelDev lv = a.lv;
   GRID_STRIDE(Q, lv.c) {
@@ -307,7 +308,15 @@ __global__ void k_block_segments(PhaseArgs a, const uint64_t* wcs, const uint64_
       sre[g] = lv.re[lv.run[k]];
       stext[g] = lv.text[k];
     }
-    if (k >= S) woff[k] = W;
+    if (k >= S) {
+      // padding: no windows, and a valid text for lanes that land here
+      woff[k] = W;
+      if (k < lv.c) {
+        ws[k] = 0;
+        sre[k] = 0;
+        stext[k] = 0;
+      }
+    }
   }
 }
 
@@ -496,7 +505,8 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     }
     uint64_t r = lo;
     uint64_t wo = woff[r], wn = woff[r + 1], rs = rs_[r], re = re_[r];
-    uint32_t t = (ODD || SALT) ? a.lv.rtext[r] : 0;
+    // lanes past the last window hold no segment: they read no text entry
+    uint32_t t = ((ODD || SALT) && w0 < W) ? a.lv.rtext[r] : 0;
     uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
 
     if (!ODD) {

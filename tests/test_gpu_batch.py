@@ -105,3 +105,19 @@ def test_batch_access(ctx):
             continue
         pos = torch.arange(len(T), device="cuda:0", dtype=torch.int64).to(torch.uint64)
         assert np.array_equal(tr.access(pos).cpu().numpy(), np.asarray(T, np.uint8))
+
+
+def test_batch_on_reused_pool_memory(ctx):
+    """Batched builds on a context whose cached device memory holds data from
+    earlier builds (nonzero), so a kernel that read an entry it never wrote
+    would see garbage rather than zeros."""
+    torch_cuda()
+    big = synth.markov_versions(400000, 8192, 40, 2e-3, 32, 5)
+    ctx.build(to_device(big), sigma=256, tau=4, leaf_len=16).free()
+    for seed in range(3):
+        texts = _texts(900 + seed, 24)
+        concat, offs = _concat(texts)
+        trees = ctx.build_batch(to_device(concat), offs, tau=4, leaf_len=16)
+        for T, tr in zip(texts, trees):
+            assert tr.serialize() == oracle.build_tree(T, 4, 16).canonical
+            tr.free()
