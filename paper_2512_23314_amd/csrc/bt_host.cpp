@@ -359,19 +359,26 @@ void timed(bt_ctx* ctx, const char* name, double bytes, double units, const uint
   ctx->pending.push_back({name, a, b, bytes, units, d_units, bytes_per_unit});
 }
 
-void collect_events(bt_ctx* ctx) {
+// Folds finished timed launches into the statistics.  A launch whose unit
+// count lives on the device (d_units) waits until the caller passes a host
+// copy of the region holding it ([dbase, dbase + len) -> hbase); the build reads
+// that region once at its end instead of one blocking copy per launch.
+void collect_events(bt_ctx* ctx, const uint64_t* dbase = nullptr, const uint64_t* hbase = nullptr,
+                    uint64_t len = 0) {
+  std::vector<PendingEv> keep;
   for (auto& p : ctx->pending) {
+    double units = p.units, bytes = p.bytes;
+    if (p.d_units) {
+      if (!(dbase && p.d_units >= dbase && p.d_units < dbase + len)) {
+        keep.push_back(p);
+        continue;
+      }
+      units = (double)hbase[p.d_units - dbase];
+      bytes = units * p.bytes_per_unit;
+    }
     float ms = 0;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       KStat& s = ctx->stats[p.name];
-      double units = p.units, bytes = p.bytes;
-      if (p.d_units) {
-        uint64_t v = 0;
-        if (hipMemcpy(&v, p.d_units, 8, hipMemcpyDeviceToHost) == hipSuccess) {
-          units = (double)v;
-          bytes = units * p.bytes_per_unit;
-        }
-      }
       s.launches++;
       s.ms += ms;
       s.bytes += bytes;
@@ -380,7 +387,7 @@ void collect_events(bt_ctx* ctx) {
     ctx->ev_free.push_back(p.a);
     ctx->ev_free.push_back(p.b);
   }
-  ctx->pending.clear();
+  ctx->pending.swap(keep);
 }
 
 uint64_t* small_host(bt_ctx* ctx, size_t words) {
@@ -761,7 +768,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint64_t> kfp = alloc<uint64_t>(ctx, c), klen = alloc<uint64_t>(ctx, c),
                   klm = alloc<uint64_t>(ctx, c);
     Buf<uint32_t> kslot = alloc<uint32_t>(ctx, c);
-    Buf<uint64_t> oddb = alloc<uint64_t>(ctx, 6 * (uint64_t)T);
+    Buf<uint64_t> oddb = alloc<uint64_t>(ctx, 7 * (uint64_t)T);
     Buf<uint64_t> woff = alloc<uint64_t>(ctx, E_ent + 1);
     Buf<uint64_t> seg_ws = alloc<uint64_t>(ctx, E_ent), seg_re = alloc<uint64_t>(ctx, E_ent);
     Buf<uint32_t> seg_text = alloc<uint32_t>(ctx, E_ent);
@@ -787,8 +794,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.tx = tx;
     a.lv = lv;
     a.k = KeysDev{kfp.p, klen.p, kslot.p, klm.p};
-    a.odd = OddDev{oddb.p, oddb.p + T, oddb.p + 2 * T, oddb.p + 3 * T, oddb.p + 4 * T,
-                   oddb.p + 5 * T};
+    a.odd = OddDev{oddb.p,         oddb.p + T,     oddb.p + 2 * T, oddb.p + 3 * T,
+                   oddb.p + 4 * T, oddb.p + 5 * T, oddb.p + 6 * T};
+    a.x32 = x32;
     a.tab = TableDev{tab.p, cap - 1, reinterpret_cast<uint8_t*>(tags.p)};
     a.x = x;
     a.fpmask = fpmask;
@@ -808,24 +816,23 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       a.Lmain = phase == 1 ? 2 * b : b;
       a.xLmain = host_pow61(x, a.Lmain);
       // LDS filter: about 32 bits per key, at most 2^19 (64 KiB), two bits per
-      // key while there are at least 8 bits per key.  Up to 2^18 keys (2^17
-      // on levels with a short final key, whose per-window check reads the
-      // 61-bit prefix anyway) the scan queues its candidates (mode 1) and,
-      // without a short key, tests the 32-bit pre-filter hash; from 2^14 keys
-      // on, where the LDS filter starts to pass a sizeable share of the
-      // windows, those also test a blocked second filter in global memory of
-      // about 16 bits per key (at most 2^24 bits, L2-resident).  Beyond that
-      // most windows pass any filter that fits in LDS, and the table's tag
-      // bytes are the cheapest second test: a 2^19-bit filter on 61-bit
-      // fingerprints without queues (mode 2).  Queue entries pack a position
-      // below 2^40 and a text below 2^24; past that, mode 2.
+      // key while there are at least 8 bits per key.  Up to 2^18 keys the scan
+      // tests the 32-bit pre-filter hash and queues its candidates (mode 1);
+      // from 2^14 keys on, where the LDS filter starts to pass a sizeable
+      // share of the windows, those also test a blocked second filter in
+      // global memory of about 16 bits per key (at most 2^24 bits,
+      // L2-resident).  Beyond that most windows pass any filter that fits in
+      // LDS, and the table's tag bytes are the cheapest second test: a
+      // 2^19-bit filter on 61-bit fingerprints without queues (mode 2).  Queue
+      // entries pack a position below 2^40 and a text below 2^24; past that,
+      // mode 2.
       fbits = 12;
       while (fbits < 19 && (1ull << fbits) < 32 * nkeys) ++fbits;
       uint32_t f2words = 0;
       const bool can_queue = T <= (1u << 24) && offs[T] < (1ull << 40);
-      if (can_queue && nkeys <= (has_odd ? (1ull << 17) : (1ull << 18))) {
+      if (can_queue && nkeys <= (1ull << 18)) {
         scan_mode = 1;
-        if (!has_odd && nkeys >= (1ull << 14)) {
+        if (nkeys >= (1ull << 14)) {
           f2words = 11;
           while (f2words < 19 && (32ull << f2words) < 16 * nkeys) ++f2words;
         }
@@ -835,15 +842,19 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       }
       a.filt_bits = fbits;
       a.filt_two = 8 * nkeys <= (1ull << fbits);
-      a.pre32 = scan_mode == 1 && !has_odd;
+      a.pre32 = scan_mode == 1;
       a.filt2_words = f2words;
-      if (f2words) HIPCHK(ctx, launch_fill_u32(filt2.p, 0, 1ull << f2words, s));
       a.x32L = host_pow32(x32, a.Lmain);
-      HIPCHK(ctx, launch_fill_u64(reinterpret_cast<uint64_t*>(tab.p), ~0ull, 2 * cap, s));
-      HIPCHK(ctx, launch_fill_u64(tags.p, 0, cap / 8, s));
-      HIPCHK(ctx, launch_fill_u64(oddb.p, 0, 6 * (uint64_t)T, s));
-      HIPCHK(ctx, launch_fill_u64(vcnt.p, 0, 2, s));
-      if (scan_mode) HIPCHK(ctx, launch_fill_u32(filt.p, 0, (1ull << fbits) / 32, s));
+      {
+        FillList f;
+        f.add(tab.p, 4 * cap, ~0u);  // empty slots: fp = best = ~0
+        f.add(tags.p, cap / 4, 0);
+        f.add(oddb.p, 14 * (uint64_t)T, 0);
+        f.add(vcnt.p, 4, 0);
+        f.add(filt.p, (1ull << fbits) / 32, 0);
+        if (f2words) f.add(filt2.p, 1ull << f2words, 0);
+        HIPCHK(ctx, launch_fill_many(f, s));
+      }
       HIPCHK(ctx, launch_keys(a, s));
       PhaseArgs as = a;  // the scan walks segments in place of runs
       uint64_t* swoff = woff.p;
@@ -866,7 +877,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         as.lv.re = bre.p;
         as.lv.rtext = btext.p;
       }
-      HIPCHK(ctx, hipMemcpyAsync(wst, swoff + as.lv.R, 8, hipMemcpyDeviceToDevice, s));
+      if (ctx->profile)  // window count of the launch, for the kernel statistics
+        HIPCHK(ctx, hipMemcpyAsync(wst, swoff + as.lv.R, 8, hipMemcpyDeviceToDevice, s));
       // algorithmic bytes per window: the two prefix values it reads (8-byte
       // 61-bit prefixes, or 4-byte 32-bit hashes when pre-filtering)
       timed(ctx, "probe_scan", 0, 0, wst, a.pre32 ? 8.0 : 16.0, [&] {
@@ -881,12 +893,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     // ---- phase 1: pairs (a3, a4) and marks (a5)
     a.all_blocks = 0;
     run_phase(1, c - R);
-    HIPCHK(ctx, launch_mark(a, marked.p, s));
-    HIPCHK(ctx, launch_pair_facts(a, facts.p, s));
+    Buf<uint64_t> uoff = alloc<uint64_t>(ctx, c + 1);
+    HIPCHK(ctx, launch_mark_facts(a, marked.p, facts.p, uoff.p, s));
 
     // ---- phase 2: unmarked blocks (a6) and pointers (a7)
-    Buf<uint64_t> uoff = alloc<uint64_t>(ctx, c + 1);
-    HIPCHK(ctx, launch_unmarked_counts(marked.p, c, uoff.p, s));
     scan(uoff.p, c);
     std::vector<uint64_t> uu;
     read_words(ctx, {{uoff.p + c, 1}}, uu);
@@ -897,8 +907,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.all_blocks = (4 * uu[0] >= c && step + 2 < H) ? 1 : 0;
     run_phase(2, a.all_blocks ? c : uu[0]);
     if (a.all_blocks) HIPCHK(ctx, launch_block_facts(a, facts.p, s));
-    Buf<uint64_t> pb = alloc<uint64_t>(ctx, c), po = alloc<uint64_t>(ctx, c);
-    HIPCHK(ctx, launch_pointers(a, marked.p, uoff.p, d_tfirst.p, pb.p, po.p,
+    // pointers of the unmarked blocks, compacted by unmarked rank: tree storage
+    Buf<uint64_t> spb = alloc<uint64_t>(ctx, uu[0]), spo = alloc<uint64_t>(ctx, uu[0]);
+    HIPCHK(ctx, launch_pointers(a, marked.p, uoff.p, d_tfirst.p, spb.p, spo.p,
                                 reinterpret_cast<uint32_t*>(d_err.p), s));
 
     // ---- split (a8): per-text counts of the next level
@@ -938,11 +949,6 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     HIPCHK(ctx, launch_word_pop(words.p, nwords, wtmp.p, s));
     scan(wtmp.p, nwords);
     HIPCHK(ctx, launch_word_rank(wtmp.p, T, d_woff.p, nwords, wrank.p, s));
-    Buf<uint64_t> spb = alloc<uint64_t>(ctx, u), spo = alloc<uint64_t>(ctx, u);
-    if (u) {
-      HIPCHK(ctx, hipMemcpyAsync(spb.p, pb.p, u * 8, hipMemcpyDeviceToDevice, s));
-      HIPCHK(ctx, hipMemcpyAsync(spo.p, po.p, u * 8, hipMemcpyDeviceToDevice, s));
-    }
     LevelBufs LB{store->add(std::move(words), nwords), store->add(std::move(wrank), nwords + 1),
                  store->add(std::move(spb), u), store->add(std::move(spo), u), nullptr, nullptr,
                  nullptr};
@@ -951,8 +957,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       Buf<uint32_t> pcnt = alloc<uint32_t>(ctx, u * S);
       Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
       HIPCHK(ctx, launch_block_rank_counts(rc, st.p, text.p, c, d_Rt.p, cnt.p, s));
+      // the pointer arrays now belong to the storage (spb/spo were released)
       HIPCHK(ctx, launch_pointer_rank_counts(rc, st.p, text.p, marked.p, c, uoff.p, d_tfirst.p,
-                                             pb.p, po.p, d_Rt.p, cnt.p, pcnt.p, s));
+                                             LB.pb, LB.po, d_Rt.p, cnt.p, pcnt.p, s));
       if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st.p, c * 8, hipMemcpyDeviceToDevice, s));
       LB.cnt = store->add(std::move(cnt), c * S);
       LB.pcnt = store->add(std::move(pcnt), u * S);
@@ -990,8 +997,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       ent_child = std::move(nchild);
       have_entries = true;
     }
-    HIPCHK(ctx, hipMemcpyAsync(d_tcount.p, ntcount.p, T * 8, hipMemcpyDeviceToDevice, s));
-    HIPCHK(ctx, hipMemcpyAsync(d_tfirst.p, ntfirst.p, (T + 1) * 8, hipMemcpyDeviceToDevice, s));
+    std::swap(d_tcount, ntcount);
+    std::swap(d_tfirst, ntfirst);
     h_tcount = h_ntcount;
     for (uint32_t t = 0; t < T; ++t) h_tfirst[t + 1] = h_tfirst[t] + h_tcount[t];
     st = std::move(nst);
@@ -1000,7 +1007,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   }
 
   std::vector<uint64_t> fin;
-  read_words(ctx, {{d_err.p, 1}}, fin);
+  read_words(ctx, {{d_err.p, 1}, {wstats.p, ctx->profile ? 2 * (uint64_t)H + 2 : 0}}, fin);
+  if (ctx->profile) collect_events(ctx, wstats.p, fin.data() + 1, 2 * (uint64_t)H + 2);
   if (fin[0]) {
     ctx->err = "device check failed: a pointer does not target a marked block or pair";
     return BT_E_INTERNAL;

@@ -75,6 +75,7 @@ struct OddDev {
   uint64_t* best;   // [T] atomicMin target, initialised to the key's position
   uint64_t* pos;    // [T]
   uint64_t* nkeys;  // [T] keys of this text in this phase (main + odd)
+  uint64_t* h32;    // [T] the key's 32-bit hash (low half) and x32^L (high half)
 };
 
 struct Slot {
@@ -114,6 +115,7 @@ struct PhaseArgs {
   // only where its 32-bit hash passes the filter.
   const uint32_t* P32;  // prefix hashes mod 2^32 (same indexing as P)
   uint32_t x32L;        // x32^Lmain mod 2^32
+  uint32_t x32;         // the 32-bit hash's base
   uint32_t pre32;
   // With pre32: a second, blocked bit filter of the keys' 32-bit hashes in
   // global memory (2^filt2_words 32-bit words, two bits of one word per key;
@@ -140,6 +142,22 @@ struct SegDev {
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s);
+// Up to kFillJobs fills of 32-bit words in one launch (jobs with no words are
+// skipped by their blocks).
+constexpr int kFillJobs = 8;
+struct FillList {
+  uint32_t* p[kFillJobs];
+  uint64_t words[kFillJobs];
+  uint32_t value[kFillJobs];
+  int n = 0;
+  void add(void* ptr, uint64_t nwords, uint32_t v) {
+    p[n] = static_cast<uint32_t*>(ptr);
+    words[n] = nwords;
+    value[n] = v;
+    ++n;
+  }
+};
+hipError_t launch_fill_many(const FillList& f, hipStream_t s);
 
 // Exclusive scan of a[0..n) in place; a[n] receives the total.  tmp must hold
 // scan_tmp_words(n) words.
@@ -188,6 +206,9 @@ hipError_t launch_retry(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s);
 
 // Step a5: marks from the phase-1 results (plus the isolated-block rule).
 hipError_t launch_mark(const PhaseArgs& a, uint8_t* marked, hipStream_t s);
+// marks, pair facts (bit 0) and the unmarked indicator in one pass
+hipError_t launch_mark_facts(const PhaseArgs& a, uint8_t* marked, uint8_t* pf, uint64_t* ucnt,
+                             hipStream_t s);
 // Unmarked-prefix counts: cnt[j] = !marked[j].
 hipError_t launch_unmarked_counts(const uint8_t* marked, uint64_t c, uint64_t* cnt,
                                   hipStream_t s);

@@ -99,6 +99,13 @@ __global__ void k_keys(PhaseArgs a) {
       a.odd.fp[t] = fp;
       a.odd.pos[t] = st;
       a.odd.best[t] = st;
+      uint32_t x32p = 1, base = a.x32;  // x32^L
+      for (uint64_t e = L; e; e >>= 1) {
+        if (e & 1) x32p *= base;
+        base *= base;
+      }
+      const uint32_t h = a.P32[st + L] - a.P32[st] * x32p + (uint32_t)a.tx.tsalt[t];
+      a.odd.h32[t] = (uint64_t)h | ((uint64_t)x32p << 32);
     }
   }
 }
@@ -508,6 +515,19 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     // lanes past the last window hold no segment: they read no text entry
     uint32_t t = ((ODD || SALT) && w0 < W) ? a.lv.rtext[r] : 0;
     uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
+    // the text's short final key, if any (kept in registers while t holds)
+    uint64_t oL = 0, opos = 0;
+    uint32_t oh = 0, ox = 0;
+    const auto load_odd = [&]() {
+      oL = a.odd.L[t];
+      if (oL) {
+        opos = a.odd.pos[t];
+        const uint64_t hx = a.odd.h32[t];
+        oh = (uint32_t)hx;
+        ox = (uint32_t)(hx >> 32);
+      }
+    };
+    if (ODD && w0 < W) load_odd();
 
     if (!ODD) {
       const uint64_t wl = w0 + 64ull * (kScanK - 1);
@@ -570,6 +590,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         re = re_[r];
         if (ODD || SALT) t = a.lv.rtext[r];
         if (SALT) salt = a.tx.tsalt[t];
+        if (ODD) load_odd();
       }
       const uint64_t i = rs + (w - wo);
       bool cand = false;
@@ -584,9 +605,11 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         }
       }
       if (MODE == 1) push(cand, i, t);
-      if (ODD && live) {
-        const uint64_t oL = a.odd.L[t];
-        if (oL && i + oL <= re && i < a.odd.pos[t]) {
+      // the short key: its 32-bit hash first (equal strings always agree),
+      // the 61-bit fingerprint only where that matches
+      if (ODD && live && oL && i + oL <= re && i < opos) {
+        const uint32_t ho = H[i + oL] - H[i] * ox + (SALT ? (uint32_t)salt : 0u);
+        if (ho == oh) {
           uint64_t g = sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
           if (SALT) g = add61(g, salt);
           if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
@@ -619,7 +642,7 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
   else if (mode == 2)
     lds = (size_t)1 << (a.filt_bits - 3);
   // the keys filled the filter from the hash kind that pre32 names
-  if (a.pre32 && (mode != 1 || has_odd)) return hipErrorInvalidValue;
+  if (a.pre32 && mode != 1) return hipErrorInvalidValue;
   const bool pre = a.pre32 != 0;
 #define BT_PROBE_LAUNCH(M, O, S, Q)                                                      \
   do {                                                                                   \
@@ -632,12 +655,11 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
 #define BT_PROBE_SALT(M, O, Q) \
   if (has_salt) BT_PROBE_LAUNCH(M, O, true, Q); else BT_PROBE_LAUNCH(M, O, false, Q);
   if (mode == 1) {
+    if (!pre) return hipErrorInvalidValue;  // queued scans always pre-filter
     if (has_odd) {
-      BT_PROBE_SALT(1, true, false)
-    } else if (pre) {
-      BT_PROBE_SALT(1, false, true)
+      BT_PROBE_SALT(1, true, true)
     } else {
-      return hipErrorInvalidValue;  // queued scans without a short key pre-filter
+      BT_PROBE_SALT(1, false, true)
     }
   } else if (mode == 2) {
     if (has_odd) {
@@ -790,6 +812,8 @@ hipError_t launch_verify(const PhaseArgs& a, const VerifyBufs& v, uint64_t max_l
     k_verify<4><<<grid_for(items * 4, 256, 2048), 256, 0, s>>>(a, v, cpk);
   } else if (max_len <= 256) {
     k_verify<16><<<grid_for(items * 16, 256, 2048), 256, 0, s>>>(a, v, cpk);
+  } else if (max_len <= 512) {
+    k_verify<32><<<grid_for(items * 32, 256, 2048), 256, 0, s>>>(a, v, cpk);
   } else {
     k_verify<64><<<grid_for(items * 64, 256, 2048), 256, 0, s>>>(a, v, cpk);
   }
@@ -883,6 +907,32 @@ __global__ void k_mark(PhaseArgs a, uint8_t* marked) {
 
 hipError_t launch_mark(const PhaseArgs& a, uint8_t* marked, hipStream_t s) {
   k_mark<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, marked);
+  return hipGetLastError();
+}
+
+// After phase 1, in one pass: the marks (as k_mark), the pair facts (as
+// k_pair_facts) and the unmarked indicator that the pointer ranks scan from.
+__global__ void k_mark_facts(PhaseArgs a, uint8_t* marked, uint8_t* pf, uint64_t* ucnt) {
+  const LevelDev lv = a.lv;
+  GRID_STRIDE(j, lv.c) {
+    const bool own = a.k.slot[j] != kNoKey;
+    const uint64_t lmj = own ? a.k.lm[j] : 0;
+    bool m = own && lmj == lv.st[j];
+    if (j > 0 && a.k.slot[j - 1] != kNoKey && a.k.lm[j - 1] == lv.st[j - 1]) m = true;
+    const uint32_t r = lv.run[j];
+    const bool left = j > 0 && lv.run[j - 1] == r;
+    const bool right = j + 1 < lv.c && lv.run[j + 1] == r;
+    if (!left && !right) m = true;  // a block with no consecutive neighbour
+    marked[j] = m ? 1 : 0;
+    pf[j] = (own && lmj < lv.st[j]) ? 1 : 0;
+    ucnt[j] = m ? 0 : 1;
+  }
+}
+
+hipError_t launch_mark_facts(const PhaseArgs& a, uint8_t* marked, uint8_t* pf, uint64_t* ucnt,
+                             hipStream_t s) {
+  if (!a.lv.c) return hipSuccess;
+  k_mark_facts<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, marked, pf, ucnt);
   return hipGetLastError();
 }
 

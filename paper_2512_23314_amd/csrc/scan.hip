@@ -39,6 +39,32 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Several fills in one launch: job y = blockIdx.y fills words[y] 32-bit words
+// at p[y] with value[y], 16 bytes per store where the buffer allows.
+__global__ void k_fill_many(FillList f) {
+  const int y = blockIdx.y;
+  uint32_t* p = f.p[y];
+  const uint64_t n = f.words[y];
+  const uint32_t v = f.value[y];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t head = ((reinterpret_cast<uintptr_t>(p) & 15) == 0) ? 0 : n;  // unaligned: scalar only
+  const uint64_t nq = (n - head) / 4;
+  uint4* q = reinterpret_cast<uint4*>(p);
+  const uint4 vv = make_uint4(v, v, v, v);
+  for (uint64_t i = tid; i < nq; i += stride) q[i] = vv;
+  for (uint64_t i = 4 * nq + tid; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_many(const FillList& f, hipStream_t s) {
+  uint64_t most = 0;
+  for (int k = 0; k < f.n; ++k) most = f.words[k] > most ? f.words[k] : most;
+  if (!f.n || !most) return hipSuccess;
+  const dim3 grid(grid_for((most + 3) / 4, 256, 4096), (unsigned)f.n);
+  k_fill_many<<<grid, 256, 0, s>>>(f);
+  return hipGetLastError();
+}
+
 // Exclusive scan of one block's values (256 threads); returns the block total.
 __device__ uint64_t block_excl_scan(uint64_t v, uint64_t* s_w) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
