@@ -52,6 +52,10 @@ extern "C" {
 /* Truncate every fingerprint to 12 bits.  Forces fingerprint collisions so that
  * the byte-verification and retry paths run; the output must not change. */
 #define BT_DBG_WEAK_HASH 1u
+/* Scan with 61-bit fingerprints and without candidate queues, the path that is
+ * otherwise taken only past the queues' packing limits (more than 2^24 texts
+ * in a batch, or positions beyond 2^40); the output must not change. */
+#define BT_DBG_NO_QUEUE 2u
 
 /* ---- build flags (bt_params.flags) ---- */
 /* Also build the counters that bt_rank and bt_select need: per block and per

@@ -816,21 +816,21 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       a.Lmain = phase == 1 ? 2 * b : b;
       a.xLmain = host_pow61(x, a.Lmain);
       // LDS filter: about 32 bits per key, at most 2^19 (64 KiB), two bits per
-      // key while there are at least 8 bits per key.  Up to 2^18 keys the scan
-      // tests the 32-bit pre-filter hash and queues its candidates (mode 1);
-      // from 2^14 keys on, where the LDS filter starts to pass a sizeable
-      // share of the windows, those also test a blocked second filter in
-      // global memory of about 16 bits per key (at most 2^24 bits,
-      // L2-resident).  Beyond that most windows pass any filter that fits in
-      // LDS, and the table's tag bytes are the cheapest second test: a
-      // 2^19-bit filter on 61-bit fingerprints without queues (mode 2).  Queue
-      // entries pack a position below 2^40 and a text below 2^24; past that,
-      // mode 2.
+      // key while there are at least 8 bits per key.  The scan tests the
+      // 32-bit pre-filter hash and queues its candidates (mode 1); from 2^14
+      // keys on, where the LDS filter starts to pass a sizeable share of the
+      // windows, those also test a blocked second filter in global memory of
+      // about 16 bits per key (at most 2^24 bits, L2-resident; beyond 2^20
+      // keys it is what rejects most windows).  Queue entries pack a position
+      // below 2^40 and a text below 2^24; past that, a 2^19-bit filter on
+      // 61-bit fingerprints without queues (mode 2), where the table's tag
+      // bytes are the second test.
       fbits = 12;
       while (fbits < 19 && (1ull << fbits) < 32 * nkeys) ++fbits;
       uint32_t f2words = 0;
-      const bool can_queue = T <= (1u << 24) && offs[T] < (1ull << 40);
-      if (can_queue && nkeys <= (1ull << 18)) {
+      const bool can_queue = T <= (1u << 24) && offs[T] < (1ull << 40) &&
+                             !(prm.debug_flags & BT_DBG_NO_QUEUE);
+      if (can_queue) {
         scan_mode = 1;
         if (nkeys >= (1ull << 14)) {
           f2words = 11;

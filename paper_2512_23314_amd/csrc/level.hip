@@ -405,7 +405,8 @@ __device__ __forceinline__ bool filter_has(const uint32_t* s_filt, uint64_t b1, 
 constexpr int kQPosBits = 40;
 constexpr uint64_t kQPosMask = (1ull << kQPosBits) - 1;
 
-// MODE 0: no filter, every window probes the table.  MODE 1: filter, and the
+// MODE 0 (kept in the template, not launched): no filter, every window probes
+// the table.  MODE 1: filter, and the
 // windows that pass go to a per-wave LDS queue; 64 queued windows at a time
 // then form their fingerprints and probe together, so a wave waits for one
 // round of loads per 64 candidates rather than per step.  MODE 2: filter,
@@ -667,10 +668,8 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
     } else {
       BT_PROBE_SALT(2, false, false)
     }
-  } else if (has_odd) {
-    BT_PROBE_SALT(0, true, false)
   } else {
-    BT_PROBE_SALT(0, false, false)
+    return hipErrorInvalidValue;  // every scan filters (mode 1 or 2)
   }
 #undef BT_PROBE_SALT
 #undef BT_PROBE_LAUNCH

@@ -79,7 +79,7 @@ def test_batch_with_offset_and_weak_hash(ctx):
     offs = [13]
     for T in texts:
         offs.append(offs[-1] + len(T))
-    for flags in (0, bt.BT_DBG_WEAK_HASH):
+    for flags in (0, bt.BT_DBG_WEAK_HASH, bt.BT_DBG_NO_QUEUE, bt.BT_DBG_NO_QUEUE | bt.BT_DBG_WEAK_HASH):
         trees = ctx.build_batch(to_device(concat), offs, tau=2, leaf_len=4, debug_flags=flags)
         for T, tr in zip(texts, trees):
             assert tr.serialize() == oracle.build_tree(T, 2, 4).canonical
@@ -121,3 +121,14 @@ def test_batch_on_reused_pool_memory(ctx):
         for T, tr in zip(texts, trees):
             assert tr.serialize() == oracle.build_tree(T, 4, 16).canonical
             tr.free()
+
+
+def test_batch_unqueued_scan(ctx):
+    """The unqueued 61-bit scan on a batch with short final keys and salts."""
+    import paper_2512_23314_amd as bt
+    texts = _texts(77, 30)
+    concat, offs = _concat(texts)
+    trees = ctx.build_batch(to_device(concat), offs, tau=3, leaf_len=4,
+                            debug_flags=bt.BT_DBG_NO_QUEUE)
+    for T, tr in zip(texts, trees):
+        assert tr.serialize() == oracle.build_tree(T, 3, 4).canonical

@@ -94,6 +94,10 @@ def test_hash_independence_and_weak_hash(ctx):
         for seed in (1, 0xDEADBEEF):
             assert _build(ctx, T, 2, 4, hash_seed=seed).serialize() == ref
         assert _build(ctx, T, 2, 4, debug_flags=bt.BT_DBG_WEAK_HASH).serialize() == ref
+        # the unqueued 61-bit scan (taken only past the queue's packing limits)
+        assert _build(ctx, T, 2, 4, debug_flags=bt.BT_DBG_NO_QUEUE).serialize() == ref
+        assert _build(ctx, T, 2, 4,
+                      debug_flags=bt.BT_DBG_NO_QUEUE | bt.BT_DBG_WEAK_HASH).serialize() == ref
 
 
 @pytest.mark.parametrize("n,tau,leaf", [(0, 2, 16), (1, 2, 16), (15, 2, 16), (16, 2, 16),
