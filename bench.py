@@ -8,9 +8,10 @@ HBM.  Prints one JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 The roofline object covers the probe-scan kernel (the sliding-window
-fingerprint probe, the dominant kernel): its algorithmic bytes (16 per window:
-the two prefix fingerprints each window reads) over its HIP-event time on the
-library's stream.  The cpu_baseline object times the CPU oracle on a bounded
+fingerprint probe, the dominant kernel): its algorithmic bytes (the two prefix
+values each window reads: 8 bytes of 32-bit pre-filter hashes, or 16 bytes of
+61-bit prefix fingerprints where the scan does not pre-filter) over its
+HIP-event time on the library's stream.  The cpu_baseline object times the CPU oracle on a bounded
 prefix of the same text.
 """
 import argparse
@@ -179,7 +180,8 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, be
               "| FETCH_SIZE, scaled | %.4g |" % fetch, "| WRITE_SIZE, scaled | %.4g |" % write,
               "| traffic (fetch + write) | %.4g |" % (fetch + write)]
     if algo:
-        lines += ["| algorithmic (16 B per window) | %.4g |" % algo,
+        lines += ["| algorithmic (the two prefix values per window: 8 B pre-filtered, 16 B "
+                  "otherwise) | %.4g |" % algo,
                   "| traffic / algorithmic | %.3f |" % ((fetch + write) / algo)]
     lines += ["", "Source hash (%s): %s" % (source, rec["source_sha256"])]
     with open(out_md, "w") as f:
