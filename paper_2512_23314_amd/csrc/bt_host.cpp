@@ -700,6 +700,19 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
                                       text.p, s));
   }
 
+  // Runs of the first level: one per non-empty text that enters there.  Each
+  // later level's count comes from the level before it (k_mark_facts), so no
+  // level waits for its own count; the device's count is checked against it
+  // at the level's first read-back.
+  uint64_t R_pred = 0;
+  for (uint32_t t = 0; t < T; ++t) R_pred += h_tcount[t] ? 1 : 0;
+  const auto check_runs = [&](uint64_t device_R, uint64_t R) {
+    if (device_R != R) {
+      ctx->err = "internal: predicted run count differs from the device's";
+      throw Fail{BT_E_INTERNAL};
+    }
+  };
+
   for (uint32_t step = 0; step < H; ++step) {
     const uint64_t b = b_at(step);
     const bool leaf_step = (step == H - 1);
@@ -709,11 +722,11 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint32_t> run = alloc<uint32_t>(ctx, c);
     HIPCHK(ctx, launch_run_flags(st.p, text.p, c, b, roff.p, s));
     scan(roff.p, c);
-    std::vector<uint64_t> rd;
-    read_words(ctx, {{roff.p + c, 1}}, rd);
-    const uint64_t R = rd[0];
-    Buf<uint64_t> rs = alloc<uint64_t>(ctx, R), re = alloc<uint64_t>(ctx, R);
-    Buf<uint32_t> rtext = alloc<uint32_t>(ctx, R);
+    const uint64_t R = R_pred;
+    // sized by c, which bounds any run count: the run table is indexed by the
+    // device's own count, which is checked against R only later
+    Buf<uint64_t> rs = alloc<uint64_t>(ctx, c), re = alloc<uint64_t>(ctx, c);
+    Buf<uint32_t> rtext = alloc<uint32_t>(ctx, c);
     HIPCHK(ctx, launch_run_table(st.p, text.p, c, b, tx, roff.p, run.p, rs.p, re.p, rtext.p, s));
     LevelDev lv{c, b, st.p, text.p, run.p, R, rs.p, re.p, rtext.p};
     Buf<uint32_t> ent_run;
@@ -748,7 +761,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       Buf<uint64_t> d_last = alloc<uint64_t>(ctx, T);
       HIPCHK(ctx, launch_last_block_len(lv, tx, d_tfirst.p, d_tcount.p, d_last.p, s));
       std::vector<uint64_t> last;
-      read_words(ctx, {{d_last.p, T}}, last);
+      read_words(ctx, {{d_last.p, T}, {roff.p + c, 1}}, last);
+      check_runs(last[T], R);
       for (uint32_t t = 0; t < T; ++t) {
         leaf_off[t] = h_tfirst[t] * b;
         leaf_bytes[t] = h_tcount[t] ? (h_tcount[t] - 1) * b + last[t] : 0;
@@ -893,13 +907,14 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     // ---- phase 1: pairs (a3, a4) and marks (a5)
     a.all_blocks = 0;
     run_phase(1, c - R);
-    Buf<uint64_t> uoff = alloc<uint64_t>(ctx, c + 1);
-    HIPCHK(ctx, launch_mark_facts(a, marked.p, facts.p, uoff.p, s));
+    Buf<uint64_t> uoff = alloc<uint64_t>(ctx, c + 1), nrun = alloc<uint64_t>(ctx, c + 1);
+    HIPCHK(ctx, launch_mark_facts(a, marked.p, facts.p, uoff.p, nrun.p, s));
 
     // ---- phase 2: unmarked blocks (a6) and pointers (a7)
     scan(uoff.p, c);
     std::vector<uint64_t> uu;
-    read_words(ctx, {{uoff.p + c, 1}}, uu);
+    read_words(ctx, {{uoff.p + c, 1}, {roff.p + c, 1}}, uu);
+    check_runs(uu[1], R);
     // When most blocks are unmarked the phase-2 scan costs the same with a key
     // for every block; the leftmost occurrences of the marked blocks then tell
     // the next level which windows are copies.  Not worth it before the last
@@ -928,11 +943,14 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     scan(ntfirst.p, T);
     Buf<uint64_t> tu = alloc<uint64_t>(ctx, T);
     HIPCHK(ctx, launch_text_deltas(uoff.p, d_tfirst.p, d_tcount.p, T, tu.p, s));
+    scan(nrun.p, c);
     std::vector<uint64_t> got;
-    read_words(ctx, {{ntcount.p, T}, {tu.p, T}, {uoff.p + c, 1}}, got);
+    read_words(ctx, {{ntcount.p, T}, {tu.p, T}, {uoff.p + c, 1}, {nrun.p + c, 1}}, got);
     std::vector<uint64_t> h_ntcount(got.begin(), got.begin() + T);
     std::vector<uint64_t> h_tu(got.begin() + T, got.begin() + 2 * T);
     const uint64_t u = got[2 * T];
+    R_pred = got[2 * T + 1];  // runs of the next level: groups of marked blocks ...
+    for (uint32_t t : ids) R_pred += ent[t] ? 1 : 0;  // ... and non-empty entering texts
 
     // ---- outputs of this level: marks (word range per text) and pointers
     std::vector<uint64_t> h_woff(T + 1, 0), h_poff(T + 1, 0);

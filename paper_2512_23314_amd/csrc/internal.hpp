@@ -206,9 +206,10 @@ hipError_t launch_retry(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s);
 
 // Step a5: marks from the phase-1 results (plus the isolated-block rule).
 hipError_t launch_mark(const PhaseArgs& a, uint8_t* marked, hipStream_t s);
-// marks, pair facts (bit 0) and the unmarked indicator in one pass
+// marks, pair facts (bit 0), the unmarked indicator and the next level's run
+// starts in one pass
 hipError_t launch_mark_facts(const PhaseArgs& a, uint8_t* marked, uint8_t* pf, uint64_t* ucnt,
-                             hipStream_t s);
+                             uint64_t* nrun, hipStream_t s);
 // Unmarked-prefix counts: cnt[j] = !marked[j].
 hipError_t launch_unmarked_counts(const uint8_t* marked, uint64_t c, uint64_t* cnt,
                                   hipStream_t s);

@@ -909,29 +909,40 @@ hipError_t launch_mark(const PhaseArgs& a, uint8_t* marked, hipStream_t s) {
   return hipGetLastError();
 }
 
-// After phase 1, in one pass: the marks (as k_mark), the pair facts (as
-// k_pair_facts) and the unmarked indicator that the pointer ranks scan from.
-__global__ void k_mark_facts(PhaseArgs a, uint8_t* marked, uint8_t* pf, uint64_t* ucnt) {
+// The mark of block j (as k_mark): its pair or its left neighbour's pair is
+// leftmost, or it has no consecutive neighbour.
+__device__ __forceinline__ bool mark_of(const PhaseArgs& a, uint64_t j) {
+  const LevelDev& lv = a.lv;
+  const auto leftmost = [&](uint64_t q) { return a.k.slot[q] != kNoKey && a.k.lm[q] == lv.st[q]; };
+  if (leftmost(j) || (j > 0 && leftmost(j - 1))) return true;
+  const uint32_t r = lv.run[j];
+  const bool left = j > 0 && lv.run[j - 1] == r;
+  const bool right = j + 1 < lv.c && lv.run[j + 1] == r;
+  return !left && !right;
+}
+
+// After phase 1, in one pass: the marks, the pair facts (as k_pair_facts), the
+// unmarked indicator that the pointer ranks scan from, and where the next
+// level's runs start.  The children of a maximal group of consecutive marked
+// blocks of one run are consecutive blocks of one run, so nrun[j] = 1 exactly
+// where such a group starts.
+__global__ void k_mark_facts(PhaseArgs a, uint8_t* marked, uint8_t* pf, uint64_t* ucnt,
+                             uint64_t* nrun) {
   const LevelDev lv = a.lv;
   GRID_STRIDE(j, lv.c) {
     const bool own = a.k.slot[j] != kNoKey;
-    const uint64_t lmj = own ? a.k.lm[j] : 0;
-    bool m = own && lmj == lv.st[j];
-    if (j > 0 && a.k.slot[j - 1] != kNoKey && a.k.lm[j - 1] == lv.st[j - 1]) m = true;
-    const uint32_t r = lv.run[j];
-    const bool left = j > 0 && lv.run[j - 1] == r;
-    const bool right = j + 1 < lv.c && lv.run[j + 1] == r;
-    if (!left && !right) m = true;  // a block with no consecutive neighbour
+    const bool m = mark_of(a, j);
     marked[j] = m ? 1 : 0;
-    pf[j] = (own && lmj < lv.st[j]) ? 1 : 0;
+    pf[j] = (own && a.k.lm[j] < lv.st[j]) ? 1 : 0;
     ucnt[j] = m ? 0 : 1;
+    nrun[j] = (m && (j == 0 || lv.run[j - 1] != lv.run[j] || !mark_of(a, j - 1))) ? 1 : 0;
   }
 }
 
 hipError_t launch_mark_facts(const PhaseArgs& a, uint8_t* marked, uint8_t* pf, uint64_t* ucnt,
-                             hipStream_t s) {
+                             uint64_t* nrun, hipStream_t s) {
   if (!a.lv.c) return hipSuccess;
-  k_mark_facts<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, marked, pf, ucnt);
+  k_mark_facts<<<grid_for(a.lv.c, 256), 256, 0, s>>>(a, marked, pf, ucnt, nrun);
   return hipGetLastError();
 }
 
