@@ -41,6 +41,8 @@ def lib():
         L.ora_plan.restype = i32
         L.ora_build.argtypes = [vp, u64, u32, u32, u64, i32, i32, ctypes.POINTER(i32)]
         L.ora_build.restype = vp
+        L.ora_prune.argtypes = [vp, vp]
+        L.ora_prune.restype = i32
         L.ora_free.argtypes = [vp]
         L.ora_tree_info.argtypes = [vp, pu64, pu32, pu64, pu64]
         L.ora_level_info.argtypes = [vp, u32, pu64, pu64, pu64]
@@ -103,8 +105,10 @@ class Tree:
 SEARCH_MEMMEM, SEARCH_NAIVE, SEARCH_RUNS = 0, 1, 2
 
 
-def build_tree(T, tau, leaf_len, b1=None, s_hint=1, exact_split=True, search=SEARCH_MEMMEM):
-    """Build the block tree of T by the definition.  Raises on a lemma breach."""
+def build_tree(T, tau, leaf_len, b1=None, s_hint=1, exact_split=True, search=SEARCH_MEMMEM,
+               prune=False):
+    """Build the block tree of T by the definition.  Raises on a lemma breach.
+    prune: also run the optional pruning phase (Section 4.1) on the result."""
     T = _text(T)
     n = T.size
     if b1 is None:
@@ -117,6 +121,10 @@ def build_tree(T, tau, leaf_len, b1=None, s_hint=1, exact_split=True, search=SEA
     try:
         if err.value != 0:
             raise AssertionError("oracle: a pointer target is not a marked block or pair (%d)" % err.value)
+        if prune:
+            rc = L.ora_prune(h, _ptr(T))
+            if rc != 0:
+                raise AssertionError("oracle: pruning failed (%d)" % rc)
         nn, hh, bb1, lb = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
         L.ora_tree_info(h, ctypes.byref(nn), ctypes.byref(hh), ctypes.byref(bb1), ctypes.byref(lb))
         levels = []

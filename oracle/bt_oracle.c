@@ -31,6 +31,9 @@
  * inside runs of consecutive blocks of the current level ("leftmost occurrence
  * on this level", Section 4); tests assert both scopes give the same tree.
  *
+ * Optional pruning (Section 4.1) is a separate pass over a built tree; its
+ * reading is stated where it is defined.
+ *
  * Also here: prefix Karp-Rabin fingerprints mod 2^61-1 by Horner's rule
  * (Section 2, the definition of phi), and counted-prefix access/rank/select
  * (Section 1, query definitions), each a plain definition.
@@ -264,6 +267,136 @@ void *ora_build(const uint8_t *T, uint64_t n, uint32_t tau, uint32_t leaf,
     st = nst; len = nlen; c = nc; b = nb;
   }
   return t;
+}
+
+/* ---- optional pruning (Section 4.1, the optional third phase) ----
+ *
+ * Marked blocks that no pointer targets are turned into pointers.  Reading
+ * (the paper gives the rule in one paragraph, without an order):
+ *   - internal levels are visited from the deepest up; within a level, blocks
+ *     from right to left (every pointer targets blocks to the left of its own,
+ *     so a block is judged after every pointer that can target it);
+ *   - a marked block j becomes a pointer when (i) no pointer of its level
+ *     targets it, counting those made by pruning, (ii) none of its children is
+ *     marked (children on the leaf level are leaves), and (iii) the leftmost
+ *     occurrence p of B_j among the windows inside runs of consecutive level
+ *     blocks ends at or before st_j (an occurrence that reaches into B_j would
+ *     need B_j to stay marked), and (iv) that occurrence lies in one block or
+ *     in two consecutive ones (always so when every block but a text's last
+ *     has full length);
+ *   - it then points at (t, p - st_t), t the block holding p, marks t (and t+1
+ *     when the occurrence spills into it) as targeted, and its children leave
+ *     the level below; the children's own pointers go with them, and levels
+ *     already visited are not visited again.
+ * T is the text the tree was built from. */
+int ora_prune(void *hdl, const uint8_t *T) {
+  otree *t = hdl;
+  int rc = ORA_OK;
+  for (int l = (int)t->h - 2; l >= 0; --l) {
+    olevel *L = &t->lv[l], *C = &t->lv[l + 1];
+    const int child_is_leaf = (l + 1 == (int)t->h - 1);
+    const uint64_t c = L->c, cc = C->c;
+    uint8_t *adj = calloc(c ? c : 1, 1), *tgt = calloc(c ? c : 1, 1);
+    uint8_t *gone = calloc(cc ? cc : 1, 1);
+    uint64_t *rs = malloc((c ? c : 1) * 8), *re = malloc((c ? c : 1) * 8);
+    uint64_t *qb = malloc((c ? c : 1) * 8), *qo = malloc((c ? c : 1) * 8);
+    uint64_t *cf = malloc((c + 1) * 8);
+    if (!adj || !tgt || !gone || !rs || !re || !qb || !qo || !cf) {
+      free(adj); free(tgt); free(gone); free(rs); free(re); free(qb); free(qo); free(cf);
+      return ORA_E_NOMEM;
+    }
+    uint64_t R = 0;
+    for (uint64_t j = 0; j < c; ++j) {
+      if (j + 1 < c) adj[j] = (L->st[j + 1] == L->st[j] + L->len[j]);
+      if (j == 0 || !adj[j - 1]) { rs[R] = L->st[j]; re[R] = L->st[j] + L->len[j]; ++R; }
+      else re[R - 1] = L->st[j] + L->len[j];
+    }
+    /* every unmarked block's pointer, indexed by block, and what it targets */
+    for (uint64_t j = 0, k = 0; j < c; ++j) {
+      if (L->marked[j]) continue;
+      qb[j] = L->pb[k]; qo[j] = L->po[k]; ++k;
+      tgt[qb[j]] = 1;
+      if (qo[j] + L->len[j] > L->len[qb[j]]) tgt[qb[j] + 1] = 1;
+    }
+    /* children: marked blocks, in order, own consecutive ranges of the level below */
+    cf[0] = 0;
+    for (uint64_t j = 0; j < c; ++j)
+      cf[j + 1] = cf[j] + (L->marked[j] ? (L->len[j] + C->b - 1) / C->b : 0);
+    uint64_t npruned = 0;
+    for (uint64_t j = c; j-- > 0;) {
+      if (!L->marked[j] || tgt[j]) continue;
+      int inner = 0;
+      if (!child_is_leaf)
+        for (uint64_t i = cf[j]; i < cf[j + 1]; ++i) inner |= C->marked[i];
+      if (inner) continue;
+      const uint64_t p = leftmost_in_runs(T, L->st[j], L->len[j], rs, re, R);
+      if (p + L->len[j] > L->st[j]) continue;
+      uint64_t lo = 0, hi = c;
+      while (hi - lo > 1) {
+        uint64_t mid = (lo + hi) / 2;
+        if (L->st[mid] <= p) lo = mid; else hi = mid;
+      }
+      const int spill = p + L->len[j] > L->st[lo] + L->len[lo];
+      /* (iv) a pointer names one block or a consecutive pair; a split into
+       * ceil(b/tau) can leave a short block inside a run, and an occurrence
+       * across three blocks keeps the block marked */
+      if (spill && (lo + 1 >= c || !adj[lo] ||
+                    p + L->len[j] > L->st[lo + 1] + L->len[lo + 1])) continue;
+      if (!L->marked[lo] || (spill && !L->marked[lo + 1])) { rc = ORA_E_LEMMA; continue; }
+      L->marked[j] = 0;
+      qb[j] = lo; qo[j] = p - L->st[lo];
+      tgt[lo] = 1;
+      if (spill) tgt[lo + 1] = 1;
+      for (uint64_t i = cf[j]; i < cf[j + 1]; ++i) gone[i] = 1;
+      ++npruned;
+    }
+    if (npruned) {
+      /* this level's pointer arrays, in block order */
+      uint64_t u = L->u + npruned;
+      uint64_t *pb = malloc(u * 8), *po = malloc(u * 8);
+      if (!pb || !po) { rc = ORA_E_NOMEM; free(pb); free(po); }
+      else {
+        for (uint64_t j = 0, k = 0; j < c; ++j)
+          if (!L->marked[j]) { pb[k] = qb[j]; po[k] = qo[j]; ++k; }
+        free(L->pb); free(L->po);
+        L->pb = pb; L->po = po; L->u = u;
+      }
+      /* the level below loses the children of pruned blocks */
+      uint64_t *nidx = malloc((cc ? cc : 1) * 8);
+      if (!nidx) rc = ORA_E_NOMEM;
+      else {
+        uint64_t kept = 0;
+        for (uint64_t i = 0; i < cc; ++i) { nidx[i] = kept; kept += !gone[i]; }
+        if (child_is_leaf) {
+          uint64_t src = 0, dst = 0;
+          for (uint64_t i = 0; i < cc; ++i) {
+            if (!gone[i]) memmove(t->leaves + dst, t->leaves + src, C->len[i]);
+            dst += gone[i] ? 0 : C->len[i];
+            src += C->len[i];
+          }
+          t->leaf_bytes = dst;
+        } else {
+          uint64_t k = 0, w = 0;
+          for (uint64_t i = 0; i < cc; ++i) {
+            if (C->marked[i]) continue;
+            if (!gone[i]) { C->pb[w] = nidx[C->pb[k]]; C->po[w] = C->po[k]; ++w; }
+            ++k;
+          }
+          C->u = w;
+        }
+        for (uint64_t i = 0; i < cc; ++i)
+          if (!gone[i]) {
+            C->st[nidx[i]] = C->st[i]; C->len[nidx[i]] = C->len[i];
+            C->marked[nidx[i]] = C->marked[i];
+          }
+        C->c = kept;
+        free(nidx);
+      }
+    }
+    free(adj); free(tgt); free(gone); free(rs); free(re); free(qb); free(qo); free(cf);
+    if (rc == ORA_E_NOMEM) return rc;
+  }
+  return rc;
 }
 
 void ora_free(void *h) { free_tree((otree *)h); }

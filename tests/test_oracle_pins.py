@@ -293,3 +293,141 @@ def test_rank_select_access_against_numpy():
             assert int(got[q]) == want
     ap = rng.integers(0, n, 1000).astype(np.uint64)
     assert (oracle.access(T, ap) == T[ap.astype(np.int64)]).all()
+
+
+# ---- optional pruning (Section 4.1)
+
+def test_fig1_pruned_worked_example():
+    """Section 4, Figure 1 as drawn: the pruned tree (the block "ra" at 8 is a
+    pointer to block 1; 8 leaves)."""
+    spec, rows, leaves = _load_fig1()
+    T = spec["text"].encode()
+    t = oracle.build_tree(T, int(spec["tau"]), int(spec["leaf"]), b1=int(spec["b1"]),
+                          exact_split=False, prune=True)
+    assert t.h == 3
+    for (b, marked, ptr), L in zip(rows["pruned"], t.levels):
+        assert L.b == b
+        assert L.marked.tolist() == marked
+        assert list(zip(L.ptr_block.tolist(), L.ptr_off.tolist())) == ptr
+    assert t.leaves.tobytes() == leaves["pruned"]
+    assert t.levels[-1].c == len(leaves["pruned"])
+    treecheck.check_pruned(treecheck.from_oracle(t, exact_split=False), T)
+
+
+def test_pruned_checker_rejects_unpruned_fig1():
+    """The pruned-tree checker is not vacuous: the unpruned Figure 1 tree keeps
+    a block that could be pruned."""
+    spec, _, _ = _load_fig1()
+    T = spec["text"].encode()
+    t = oracle.build_tree(T, int(spec["tau"]), int(spec["leaf"]), b1=int(spec["b1"]), exact_split=False)
+    with pytest.raises(AssertionError, match="Q3"):
+        treecheck.check_pruned(treecheck.from_oracle(t, exact_split=False), T)
+
+
+@pytest.mark.parametrize("sigma,nmax", [(2, 10), (3, 6)])
+def test_pruned_exhaustive(sigma, nmax):
+    """Every text over a tiny alphabet, tau in {2,3}, leaf in {1,2}, every b1:
+    the pruned oracle tree satisfies the pruning characterisation (Q1-Q3) and
+    still spells T."""
+    alph = b"ab" if sigma == 2 else b"abc"
+    cases = pruned = 0
+    for n in range(1, nmax + 1):
+        for word in itertools.product(alph, repeat=n):
+            T = bytes(word)
+            for tau in (2, 3):
+                for leaf in (1, 2):
+                    b1 = leaf
+                    while True:
+                        t = oracle.build_tree(T, tau, leaf, b1=b1, prune=True)
+                        treecheck.check_pruned(treecheck.from_oracle(t), T)
+                        u = oracle.build_tree(T, tau, leaf, b1=b1)
+                        pruned += u.canonical != t.canonical
+                        cases += 1
+                        if b1 >= n:
+                            break
+                        b1 *= tau
+    assert cases > 3000 and pruned > 100
+
+
+def test_pruned_general_split_random():
+    """ceil(b/tau) splits (Figure 1 style).  Such a split can leave a short
+    block between full ones, so that an occurrence spans three blocks and the
+    unpruned tree itself is not well formed; those draws are skipped."""
+    rng = np.random.default_rng(12)
+    done = 0
+    for _ in range(400):
+        n = int(rng.integers(1, 40))
+        T = bytes(rng.integers(97, 97 + int(rng.integers(1, 4)), n).astype(np.uint8))
+        tau = int(rng.integers(2, 5))
+        leaf = int(rng.integers(1, 3))
+        b1 = max(leaf, int(rng.integers(1, n + 1)))
+        try:
+            oracle.build_tree(T, tau, leaf, b1=b1, exact_split=False)
+        except AssertionError:
+            continue
+        t = oracle.build_tree(T, tau, leaf, b1=b1, exact_split=False, prune=True)
+        treecheck.check_pruned(treecheck.from_oracle(t, exact_split=False), T)
+        done += 1
+    assert done > 200
+
+
+def test_pruned_unary_closed_form():
+    """T = a^n: every pointer targets block 0 alone, so each level keeps only
+    block 0 marked; levels below the first have tau blocks; tau*leaf leaf bytes."""
+    for tau, leaf, n in ((2, 1, 200), (3, 2, 500), (4, 4, 1000), (2, 3, 97)):
+        b1 = leaf
+        while b1 * tau * 3 <= n:
+            b1 *= tau
+        T = b"a" * n
+        t = oracle.build_tree(T, tau, leaf, b1=b1, prune=True)
+        for li, L in enumerate(t.levels[:-1]):
+            assert L.marked.tolist() == [1] + [0] * (L.c - 1)
+            assert (L.ptr_block == 0).all() and (L.ptr_off == 0).all()
+            assert L.c == (-(-n // b1) if li == 0 else tau)
+        assert t.levels[-1].c == tau and t.leaves.tobytes() == b"a" * (tau * leaf)
+        treecheck.check_pruned(treecheck.from_oracle(t), T)
+
+
+def test_pruning_keeps_trees_without_earlier_copies():
+    """All-distinct text: no block has an earlier occurrence.  (ab)^m with odd
+    block lengths: block 1's only earlier copy overlaps it, and it is targeted.
+    Pruning leaves both trees as they are."""
+    rng = np.random.default_rng(3)
+    T = bytes(rng.permutation(256)[:200].astype(np.uint8))
+    for tau, leaf in ((2, 1), (3, 2)):
+        assert oracle.build_tree(T, tau, leaf, prune=True).canonical == oracle.build_tree(T, tau, leaf).canonical
+    T = b"ab" * 121
+    b1 = 1
+    while b1 * 9 <= len(T):
+        b1 *= 3
+    assert oracle.build_tree(T, 3, 1, b1=b1, prune=True).canonical == oracle.build_tree(T, 3, 1, b1=b1).canonical
+
+
+@pytest.mark.parametrize("name", ["cfg1_8k", "markov", "random", "periodic"])
+def test_pruned_invariants(name):
+    T = {
+        "cfg1_8k": lambda: synth.cfg1_text(1 << 13),
+        "markov": lambda: synth.markov_versions(20000, 2048, 8, 2e-3, 32, 21),
+        "random": lambda: synth.random_text(6000, 2, 8),
+        "periodic": lambda: synth.periodic_text(9001, 97, 2),
+    }[name]()
+    T = bytes(T)
+    for tau, leaf, s in ((2, 4, 1), (4, 4, 1), (3, 5, 1), (2, 8, 16)):
+        t = oracle.build_tree(T, tau, leaf, s_hint=s, prune=True)
+        u = oracle.build_tree(T, tau, leaf, s_hint=s)
+        assert sum(L.c for L in t.levels) <= sum(L.c for L in u.levels)
+        treecheck.check_pruned(treecheck.from_oracle(t), T)
+
+
+def test_pruned_random_small():
+    """Random texts of 8..200 bytes over 2-3 letters.  These reach the case the
+    exhaustive tiny texts miss: a child kept marked because a pointer targets
+    it through an occurrence that crosses its parent's right end, which must
+    keep the parent marked too."""
+    rng = np.random.default_rng(1)
+    for _ in range(150):
+        n = int(rng.integers(8, 200))
+        T = bytes(rng.integers(97, 97 + int(rng.integers(2, 4)), n).astype(np.uint8))
+        for tau, leaf in ((2, 1), (3, 1), (2, 2)):
+            t = oracle.build_tree(T, tau, leaf, prune=True)
+            treecheck.check_pruned(treecheck.from_oracle(t), T)

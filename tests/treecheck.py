@@ -134,3 +134,146 @@ def check(s, T, check_leftmost=True, max_leftmost=None):
 
 def level_sizes(s):
     return [len(m) for (_, m, _, _) in s.levels]
+
+
+def _runs(st, ln):
+    """Maximal runs of consecutive blocks, as (start, end) pairs."""
+    out = []
+    for a, l in zip(st.tolist(), ln.tolist()):
+        if out and out[-1][1] == a:
+            out[-1][1] = a + l
+        else:
+            out.append([a, a + l])
+    return out
+
+
+def _leftmost_on_level(Tb, runs, a, L):
+    """Smallest p with T[p..p+L) == T[a..a+L) inside one run (a itself qualifies)."""
+    X = Tb[a:a + L]
+    for rs, re in runs:
+        if rs > a:
+            break
+        p = Tb.find(X, rs, min(re, a + L))
+        if p >= 0:
+            return p
+    raise AssertionError("block at %d not found on its own level" % a)
+
+
+def check_pruned(s, T):
+    """Invariants of a pruned tree (Section 4.1, optional pruning), checked
+    without replaying the pruning sweep.
+
+    The tree the marking rule defines ("unpruned") is rebuilt level by level
+    from the definition alone.  A pruned tree keeps that block layout on every
+    level except for the children of pruned blocks.  Per level, with every
+    pointer that existed when the level was judged -- the final ones plus those
+    of blocks removed later with a pruned parent, each aimed at its block's
+    leftmost occurrence among the level's runs -- it asserts:
+      Q1  marks only go away: a marked block is marked by the definition
+      Q2  a pruned block (marked by the definition, unmarked or gone) is
+          untargeted, has no marked child, and its leftmost occurrence ends at
+          or before its start and lies in one block or a consecutive pair; a
+          stored pointer is that occurrence
+      Q3  a block that stays marked fails one of those conditions
+    plus I1, I3, I4 and I7 of check() (the pruned tree still spells T)."""
+    T = bytes(T)
+    h = len(s.levels)
+    n = len(T)
+
+    def nb_of(b):
+        return b // s.tau if s.exact_split else -(-b // s.tau)
+
+    def children(st, ln, sel, b):
+        nb = nb_of(b)
+        ms, ml = st[sel], ln[sel]
+        cnt = (ml + nb - 1) // nb
+        par = np.repeat(np.arange(ms.size), cnt)
+        first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        cst = ms[par] + (np.arange(par.size) - first) * nb
+        return cst, np.minimum(nb, ms[par] + ml[par] - cst), cnt
+
+    # unpruned layouts and definition marks, top-down
+    U = []
+    st = np.arange(0, n, s.b1, dtype=np.int64) if n else np.zeros(0, np.int64)
+    ln = np.minimum(s.b1, n - st)
+    for li in range(h):
+        c = len(st)
+        dm = np.zeros(c, bool)
+        if li < h - 1:
+            adj = np.zeros(c, bool)
+            if c > 1:
+                adj[:-1] = st[1:] == st[:-1] + ln[:-1]
+            for j in range(c):
+                if adj[j]:
+                    a, L = int(st[j]), int(ln[j] + ln[j + 1])
+                    if T.find(T[a:a + L], 0, a + L) == a:
+                        dm[j] = dm[j + 1] = True
+                if not (j > 0 and adj[j - 1]) and not adj[j]:
+                    dm[j] = True
+        U.append((st, ln, dm))
+        if li < h - 1:
+            st, ln, _ = children(st, ln, dm, s.levels[li][0])
+    # which unpruned blocks are present in the pruned tree, and their marks
+    # when their level was judged (a block removed later was unmarked then)
+    present = np.ones(len(U[0][0]), bool)
+    pres_all, jm_all = [], []
+    for li in range(h):
+        st, ln, dm = U[li]
+        fm = np.asarray(s.levels[li][1]).astype(bool)
+        assert int(present.sum()) == len(fm), "level %d: %d blocks, %d expected" % (
+            li + 1, len(fm), int(present.sum()))
+        jm = np.zeros(len(st), bool)
+        jm[present] = fm
+        assert not (jm & ~dm).any(), "Q1: level %d marks a block the definition leaves unmarked" % (li + 1)
+        pres_all.append(present)
+        jm_all.append(jm)
+        if li < h - 1:
+            _, _, cnt = children(st, ln, dm, s.levels[li][0])
+            present = np.repeat(jm[dm], cnt)
+    for li in range(h - 1):
+        st, ln, dm = U[li]
+        jm, present = jm_all[li], pres_all[li]
+        c = len(st)
+        runs = _runs(st, ln)
+        lm = np.array([_leftmost_on_level(T, runs, int(st[j]), int(ln[j])) for j in range(c)], np.int64)
+        tb = np.searchsorted(st, lm, side="right") - 1
+        spill = lm + ln > st[tb] + ln[tb] if c else np.zeros(0, bool)
+        tgt = np.zeros(c, bool)
+        for j in np.flatnonzero(~jm).tolist():
+            tgt[tb[j]] = True
+            if spill[j]:
+                tgt[tb[j] + 1] = True
+        _, _, cnt = children(st, ln, dm, s.levels[li][0])
+        cf = np.zeros(c + 1, np.int64)
+        cf[1:][dm] = cnt
+        cf = np.cumsum(cf)
+        below = jm_all[li + 1] if li + 1 < h - 1 else np.zeros(int(cf[-1]), bool)
+        for j in np.flatnonzero(dm).tolist():
+            inner = bool(below[cf[j]:cf[j + 1]].any())
+            t = int(tb[j])
+            # the occurrence fits one block or a consecutive pair
+            fits = not spill[j] or (t + 1 < c and st[t + 1] == st[t] + ln[t] and
+                                    lm[j] + ln[j] <= st[t + 1] + ln[t + 1])
+            early = lm[j] + ln[j] <= st[j] and fits
+            if jm[j]:
+                assert tgt[j] or inner or not early, \
+                    "Q3: level %d block at %d stays marked but could be pruned" % (li + 1, int(st[j]))
+            else:
+                why = "targeted" if tgt[j] else "has a marked child" if inner else "has no earlier occurrence"
+                assert not tgt[j] and not inner and early, \
+                    "Q2: level %d block at %d is pruned but %s" % (li + 1, int(st[j]), why)
+        # stored pointers of the present unmarked blocks
+        rank = np.full(c, -1, np.int64)
+        rank[present] = np.arange(int(present.sum()))
+        _, _, pb, po = s.levels[li]
+        k = 0
+        for j in np.flatnonzero(present & ~jm).tolist():
+            t = int(tb[j])
+            want = (int(rank[t]), int(lm[j] - st[t]))
+            assert k < len(pb) and (int(pb[k]), int(po[k])) == want, \
+                "Q2: level %d block at %d: pointer %s, expected %s" % (
+                    li + 1, int(st[j]), (int(pb[k]), int(po[k])) if k < len(pb) else None, want)
+            k += 1
+        assert k == len(pb), "level %d: %d pointers stored, %d expected" % (li + 1, len(pb), k)
+    check(s, T, check_leftmost=False)
+    return True
