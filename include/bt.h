@@ -63,6 +63,16 @@ extern "C" {
  * between its target block's start and its source.  Texts must be shorter than
  * 2^32 bytes.  bt_build always sets it. */
 #define BT_WITH_RANK_SELECT 1u
+/* Run the optional pruning phase (Section 4.1, after the two phases): marked
+ * blocks that no pointer targets become pointers to their leftmost occurrence
+ * on the level, deepest internal level first and right to left within a level,
+ * when none of their children is marked and that occurrence ends at or before
+ * the block and lies in one block or two consecutive ones; their children
+ * leave the level below.  The result is the same tree shape with fewer marked
+ * blocks (the worked example of Figure 1 is drawn pruned).  The build then
+ * scans every block's leftmost occurrence on every level, not only those of
+ * unmarked blocks. */
+#define BT_PRUNE 2u
 
 typedef struct bt_ctx bt_ctx;   /* device, stream, scratch pool, statistics */
 typedef struct bt_tree bt_tree; /* a finished tree, resident in device memory */
@@ -82,7 +92,7 @@ typedef struct bt_tree bt_tree; /* a finished tree, resident in device memory */
  *   hash_seed      seeds the Karp-Rabin base x in [2^8, 2^61-1); the tree does
  *                  not depend on it.
  *   debug_flags    BT_DBG_* bits.
- *   flags          BT_WITH_RANK_SELECT or 0.
+ *   flags          BT_WITH_RANK_SELECT and/or BT_PRUNE, or 0.
  * Block lengths are b_l = b1 / tau^(l-1); the tree has h = k + 1 levels and
  * level h holds the leaves.  Every block has length b_l except the one that
  * ends the text, which may be shorter.

@@ -18,6 +18,7 @@ BT_OK, BT_E_INVAL, BT_E_NOMEM, BT_E_DEVICE, BT_E_INTERNAL = 0, -1, -2, -3, -4
 BT_DBG_WEAK_HASH = 1
 BT_DBG_NO_QUEUE = 2
 BT_WITH_RANK_SELECT = 1
+BT_PRUNE = 2
 
 _lib = None
 
@@ -158,9 +159,9 @@ class Context:
     # ---- builds
     @staticmethod
     def params(tau, leaf_len, s_hint=1, root_block_len=0, hash_seed=0x0B10C7EE, debug_flags=0,
-               rank_select=False):
+               rank_select=False, prune=False):
         return bt_params(tau, leaf_len, root_block_len, s_hint, hash_seed, debug_flags,
-                         BT_WITH_RANK_SELECT if rank_select else 0)
+                         (BT_WITH_RANK_SELECT if rank_select else 0) | (BT_PRUNE if prune else 0))
 
     def build(self, text, sigma=256, tau=2, leaf_len=16, **kw):
         """Build the tree of a uint8 CUDA tensor; returns a Tree."""

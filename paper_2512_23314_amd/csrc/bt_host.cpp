@@ -638,10 +638,13 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     store->add(std::move(byte_of), S);
   }
   const bool rank_on = with_rank && S;
+  const bool prune = (prm.flags & BT_PRUNE) != 0;
 
   // ---- outputs
+  // per text, its levels (a text whose tree is shorter enters at a later step)
   std::vector<std::vector<TextLevelRec>> rec(T);
-  std::vector<LevelBufs> lbufs;
+  for (uint32_t t = 0; t < T; ++t) rec[t].resize(plan[t].h);
+  std::vector<LevelBufs> lbufs(H);  // by step
   uint8_t* leaves = nullptr;
   std::vector<uint64_t> leaf_off(T, 0), leaf_bytes(T, 0);
   Buf<uint64_t> d_err = alloc<uint64_t>(ctx, 1);
@@ -682,6 +685,101 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         cnt[t] = (h_n[t] + b - 1) / b;
       }
   };
+  const auto check_runs = [&](uint64_t device_R, uint64_t R) {
+    if (device_R != R) {
+      ctx->err = "internal: predicted run count differs from the device's";
+      throw Fail{BT_E_INTERNAL};
+    }
+  };
+  // ---- tree storage of an internal level: marks packed per text (with their
+  // ranks), the pointers (by unmarked rank; the buffers move into the storage)
+  // and the rank/select counters.  uoff: exclusive scan of the unmarked flags.
+  auto store_level = [&](uint32_t step, uint64_t b, uint64_t c, const uint64_t* st,
+                         const uint32_t* text, const uint8_t* marked, const uint64_t* uoff,
+                         Buf<uint64_t>& spb, Buf<uint64_t>& spo, uint64_t u,
+                         const std::vector<uint64_t>& tcount, const std::vector<uint64_t>& tfirst,
+                         const std::vector<uint64_t>& tu, const uint64_t* d_tf,
+                         const uint64_t* d_tc) {
+    std::vector<uint64_t> h_woff(T + 1, 0), h_poff(T + 1, 0);
+    for (uint32_t t = 0; t < T; ++t) {
+      h_woff[t + 1] = h_woff[t] + (tcount[t] + 63) / 64;
+      h_poff[t + 1] = h_poff[t] + tu[t];
+    }
+    const uint64_t nwords = h_woff[T];
+    Buf<uint64_t> d_woff = alloc<uint64_t>(ctx, T + 1);
+    upload(ctx, d_woff.p, h_woff.data(), T + 1);
+    Buf<uint64_t> words = alloc<uint64_t>(ctx, nwords), wrank = alloc<uint64_t>(ctx, nwords + 1);
+    Buf<uint64_t> wtmp = alloc<uint64_t>(ctx, nwords + 1);
+    HIPCHK(ctx, launch_pack_marks(marked, T, d_tf, d_tc, d_woff.p, nwords, words.p, s));
+    HIPCHK(ctx, launch_word_pop(words.p, nwords, wtmp.p, s));
+    scan(wtmp.p, nwords);
+    HIPCHK(ctx, launch_word_rank(wtmp.p, T, d_woff.p, nwords, wrank.p, s));
+    LevelBufs LB{store->add(std::move(words), nwords), store->add(std::move(wrank), nwords + 1),
+                 store->add(std::move(spb), u), store->add(std::move(spo), u), nullptr, nullptr,
+                 nullptr};
+    if (rank_on) {
+      Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
+      Buf<uint32_t> pcnt = alloc<uint32_t>(ctx, u * S);
+      Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
+      HIPCHK(ctx, launch_block_rank_counts(rc, st, text, c, d_Rt.p, cnt.p, s));
+      // the pointer arrays now belong to the storage (spb/spo were released)
+      HIPCHK(ctx, launch_pointer_rank_counts(rc, st, text, marked, c, uoff, d_tf, LB.pb, LB.po,
+                                             d_Rt.p, cnt.p, pcnt.p, s));
+      if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st, c * 8, hipMemcpyDeviceToDevice, s));
+      LB.cnt = store->add(std::move(cnt), c * S);
+      LB.pcnt = store->add(std::move(pcnt), u * S);
+      LB.st = store->add(std::move(stc), c);
+    }
+    lbufs[step] = LB;
+    for (uint32_t t = 0; t < T; ++t)
+      if (H - plan[t].h <= step)
+        rec[t][step - (H - plan[t].h)] = {b, tcount[t], tu[t], h_woff[t], h_poff[t], tfirst[t]};
+  };
+  // ---- tree storage of the leaf level: block j's bytes at j*b (only a text's
+  // last block is short, and it ends the text's region).  When runs_at is given,
+  // the device's run count there is checked against R in the same read-back.
+  auto store_leaf_level = [&](uint32_t step, uint64_t b, uint64_t c, const uint64_t* st,
+                              const uint32_t* text, const std::vector<uint64_t>& tcount,
+                              const std::vector<uint64_t>& tfirst, const uint64_t* d_tf,
+                              const uint64_t* d_tc, const uint64_t* runs_at, uint64_t R) {
+    LevelDev lvl{c, b, st, text, nullptr, 0, nullptr, nullptr, nullptr};
+    Buf<uint8_t> lb = alloc<uint8_t>(ctx, c * b);
+    HIPCHK(ctx, launch_leaves(d_base, lvl, tx, lb.p, s));
+    leaves = store->add(std::move(lb), c * b);
+    LevelBufs LL{};
+    if (rank_on) {
+      Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
+      HIPCHK(ctx, launch_block_rank_counts(rc, st, text, c, d_Rt.p, cnt.p, s));
+      Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
+      if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st, c * 8, hipMemcpyDeviceToDevice, s));
+      LL.cnt = store->add(std::move(cnt), c * S);
+      LL.st = store->add(std::move(stc), c);
+    }
+    lbufs[step] = LL;
+    Buf<uint64_t> d_last = alloc<uint64_t>(ctx, T);
+    HIPCHK(ctx, launch_last_block_len(lvl, tx, d_tf, d_tc, d_last.p, s));
+    std::vector<uint64_t> last;
+    read_words(ctx, {{d_last.p, T}, {runs_at, runs_at ? 1u : 0u}}, last);
+    if (runs_at) check_runs(last[T], R);
+    for (uint32_t t = 0; t < T; ++t) {
+      leaf_off[t] = tfirst[t] * b;
+      leaf_bytes[t] = tcount[t] ? (tcount[t] - 1) * b + last[t] : 0;
+      rec[t][plan[t].h - 1] = {b, tcount[t], 0, 0, 0, tfirst[t]};
+    }
+  };
+
+  // What the optional pruning pass needs of each level, kept from the build:
+  // the built (unpruned) layout, the marks, every block's leftmost occurrence
+  // on its level, and where each block's children start.
+  struct PruneLevel {
+    uint64_t b = 0, c = 0;
+    Buf<uint64_t> st, lm, cs, tfirst, tcount;
+    Buf<uint32_t> text, run;
+    Buf<uint8_t> marked;
+    std::vector<uint64_t> h_tcount, h_tfirst;
+  };
+  std::vector<PruneLevel> pl(prune ? H : 0);
+
   {
     const uint64_t b0 = b_at(0);
     std::vector<uint32_t> ids;
@@ -706,12 +804,6 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   // at the level's first read-back.
   uint64_t R_pred = 0;
   for (uint32_t t = 0; t < T; ++t) R_pred += h_tcount[t] ? 1 : 0;
-  const auto check_runs = [&](uint64_t device_R, uint64_t R) {
-    if (device_R != R) {
-      ctx->err = "internal: predicted run count differs from the device's";
-      throw Fail{BT_E_INTERNAL};
-    }
-  };
 
   for (uint32_t step = 0; step < H; ++step) {
     const uint64_t b = b_at(step);
@@ -745,28 +837,22 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     }
 
     if (leaf_step) {
-      Buf<uint8_t> lb = alloc<uint8_t>(ctx, c * b);
-      HIPCHK(ctx, launch_leaves(d_base, lv, tx, lb.p, s));
-      leaves = store->add(std::move(lb), c * b);
-      LevelBufs LL{};
-      if (rank_on) {
-        Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
-        HIPCHK(ctx, launch_block_rank_counts(rc, st.p, text.p, c, d_Rt.p, cnt.p, s));
-        Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
-        if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st.p, c * 8, hipMemcpyDeviceToDevice, s));
-        LL.cnt = store->add(std::move(cnt), c * S);
-        LL.st = store->add(std::move(stc), c);
-      }
-      lbufs.push_back(LL);
-      Buf<uint64_t> d_last = alloc<uint64_t>(ctx, T);
-      HIPCHK(ctx, launch_last_block_len(lv, tx, d_tfirst.p, d_tcount.p, d_last.p, s));
-      std::vector<uint64_t> last;
-      read_words(ctx, {{d_last.p, T}, {roff.p + c, 1}}, last);
-      check_runs(last[T], R);
-      for (uint32_t t = 0; t < T; ++t) {
-        leaf_off[t] = h_tfirst[t] * b;
-        leaf_bytes[t] = h_tcount[t] ? (h_tcount[t] - 1) * b + last[t] : 0;
-        rec[t].push_back({b, h_tcount[t], 0, 0, 0, h_tfirst[t]});
+      if (!prune) {
+        store_leaf_level(step, b, c, st.p, text.p, h_tcount, h_tfirst, d_tfirst.p, d_tcount.p,
+                         roff.p + c, R);
+      } else {
+        std::vector<uint64_t> rr;
+        read_words(ctx, {{roff.p + c, 1}}, rr);
+        check_runs(rr[0], R);
+        PruneLevel& K = pl[step];
+        K.b = b;
+        K.c = c;
+        K.st = std::move(st);
+        K.text = std::move(text);
+        K.tfirst = std::move(d_tfirst);
+        K.tcount = std::move(d_tcount);
+        K.h_tcount = h_tcount;
+        K.h_tfirst = h_tfirst;
       }
       break;
     }
@@ -919,13 +1005,19 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     // for every block; the leftmost occurrences of the marked blocks then tell
     // the next level which windows are copies.  Not worth it before the last
     // scanned level.
-    a.all_blocks = (4 * uu[0] >= c && step + 2 < H) ? 1 : 0;
+    // Pruning needs every block's leftmost occurrence, so it asks for all.
+    a.all_blocks = (prune || (4 * uu[0] >= c && step + 2 < H)) ? 1 : 0;
     run_phase(2, a.all_blocks ? c : uu[0]);
     if (a.all_blocks) HIPCHK(ctx, launch_block_facts(a, facts.p, s));
     // pointers of the unmarked blocks, compacted by unmarked rank: tree storage
-    Buf<uint64_t> spb = alloc<uint64_t>(ctx, uu[0]), spo = alloc<uint64_t>(ctx, uu[0]);
-    HIPCHK(ctx, launch_pointers(a, marked.p, uoff.p, d_tfirst.p, spb.p, spo.p,
-                                reinterpret_cast<uint32_t*>(d_err.p), s));
+    // (with pruning, written once the marks are final)
+    Buf<uint64_t> spb, spo;
+    if (!prune) {
+      spb = alloc<uint64_t>(ctx, uu[0]);
+      spo = alloc<uint64_t>(ctx, uu[0]);
+      HIPCHK(ctx, launch_pointers(a, marked.p, uoff.p, d_tfirst.p, spb.p, spo.p,
+                                  reinterpret_cast<uint32_t*>(d_err.p), s));
+    }
 
     // ---- split (a8): per-text counts of the next level
     const uint64_t bn = b / prm.tau;
@@ -953,40 +1045,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     for (uint32_t t : ids) R_pred += ent[t] ? 1 : 0;  // ... and non-empty entering texts
 
     // ---- outputs of this level: marks (word range per text) and pointers
-    std::vector<uint64_t> h_woff(T + 1, 0), h_poff(T + 1, 0);
-    for (uint32_t t = 0; t < T; ++t) {
-      h_woff[t + 1] = h_woff[t] + (h_tcount[t] + 63) / 64;
-      h_poff[t + 1] = h_poff[t] + h_tu[t];
-    }
-    const uint64_t nwords = h_woff[T];
-    Buf<uint64_t> d_woff = alloc<uint64_t>(ctx, T + 1);
-    upload(ctx, d_woff.p, h_woff.data(), T + 1);
-    Buf<uint64_t> words = alloc<uint64_t>(ctx, nwords), wrank = alloc<uint64_t>(ctx, nwords + 1);
-    Buf<uint64_t> wtmp = alloc<uint64_t>(ctx, nwords + 1);
-    HIPCHK(ctx, launch_pack_marks(marked.p, T, d_tfirst.p, d_tcount.p, d_woff.p, nwords, words.p, s));
-    HIPCHK(ctx, launch_word_pop(words.p, nwords, wtmp.p, s));
-    scan(wtmp.p, nwords);
-    HIPCHK(ctx, launch_word_rank(wtmp.p, T, d_woff.p, nwords, wrank.p, s));
-    LevelBufs LB{store->add(std::move(words), nwords), store->add(std::move(wrank), nwords + 1),
-                 store->add(std::move(spb), u), store->add(std::move(spo), u), nullptr, nullptr,
-                 nullptr};
-    if (rank_on) {
-      Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
-      Buf<uint32_t> pcnt = alloc<uint32_t>(ctx, u * S);
-      Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
-      HIPCHK(ctx, launch_block_rank_counts(rc, st.p, text.p, c, d_Rt.p, cnt.p, s));
-      // the pointer arrays now belong to the storage (spb/spo were released)
-      HIPCHK(ctx, launch_pointer_rank_counts(rc, st.p, text.p, marked.p, c, uoff.p, d_tfirst.p,
-                                             LB.pb, LB.po, d_Rt.p, cnt.p, pcnt.p, s));
-      if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st.p, c * 8, hipMemcpyDeviceToDevice, s));
-      LB.cnt = store->add(std::move(cnt), c * S);
-      LB.pcnt = store->add(std::move(pcnt), u * S);
-      LB.st = store->add(std::move(stc), c);
-    }
-    lbufs.push_back(LB);
-    for (uint32_t t = 0; t < T; ++t)
-      if (H - plan[t].h <= step)
-        rec[t].push_back({b, h_tcount[t], h_tu[t], h_woff[t], h_poff[t], h_tfirst[t]});
+    if (!prune)
+      store_level(step, b, c, st.p, text.p, marked.p, uoff.p, spb, spo, u, h_tcount, h_tfirst,
+                  h_tu, d_tfirst.p, d_tcount.p);
 
     // ---- next level's blocks
     uint64_t cn = 0;
@@ -1015,6 +1076,21 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       ent_child = std::move(nchild);
       have_entries = true;
     }
+    if (prune) {
+      PruneLevel& K = pl[step];
+      K.b = b;
+      K.c = c;
+      K.st = std::move(st);
+      K.text = std::move(text);
+      K.run = std::move(run);
+      K.marked = std::move(marked);
+      K.lm = std::move(klm);
+      K.cs = std::move(cs);
+      K.tfirst = std::move(d_tfirst);
+      K.tcount = std::move(d_tcount);
+      K.h_tcount = h_tcount;
+      K.h_tfirst = h_tfirst;
+    }
     std::swap(d_tcount, ntcount);
     std::swap(d_tfirst, ntfirst);
     h_tcount = h_ntcount;
@@ -1022,6 +1098,113 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     st = std::move(nst);
     text = std::move(ntext);
     c = cn;
+  }
+
+  // ---- optional pruning (Section 4.1), deepest internal level first.  A
+  // level's decisions need its children's final marks; a level's block set is
+  // final once the level above has been decided, and is stored then.
+  if (prune) {
+    uint32_t* err = reinterpret_cast<uint32_t*>(d_err.p);
+    Buf<uint64_t> open = alloc<uint64_t>(ctx, 1);
+    // drop the blocks flagged in gone (null: none) from level `step` and store it
+    auto compact_store = [&](uint32_t step, const uint8_t* gone) {
+      PruneLevel& K = pl[step];
+      const bool leaf = step + 1 == H;
+      const uint64_t c0 = K.c;
+      Buf<uint8_t> none;
+      if (!gone) {
+        none = alloc<uint8_t>(ctx, c0);
+        HIPCHK(ctx, launch_fill_u8(none.p, 0, c0, s));
+        gone = none.p;
+      }
+      Buf<uint64_t> keep = alloc<uint64_t>(ctx, c0 + 1), unmk = alloc<uint64_t>(ctx, c0 + 1);
+      HIPCHK(ctx, launch_keep_flags(gone, leaf ? nullptr : K.marked.p, c0, keep.p, unmk.p, s));
+      scan(keep.p, c0);
+      scan(unmk.p, c0);
+      Buf<uint64_t> ntf = alloc<uint64_t>(ctx, T + 1), ntc = alloc<uint64_t>(ctx, T + 1),
+                    ntu = alloc<uint64_t>(ctx, T + 1);
+      HIPCHK(ctx, launch_gather_firsts(keep.p, K.tfirst.p, T, ntf.p, s));
+      HIPCHK(ctx, launch_text_deltas(keep.p, K.tfirst.p, K.tcount.p, T, ntc.p, s));
+      HIPCHK(ctx, launch_text_deltas(unmk.p, K.tfirst.p, K.tcount.p, T, ntu.p, s));
+      Buf<uint64_t> nst = alloc<uint64_t>(ctx, c0), nlm = alloc<uint64_t>(ctx, c0),
+                    nuoff = alloc<uint64_t>(ctx, c0 + 1);
+      Buf<uint32_t> ntext = alloc<uint32_t>(ctx, c0);
+      Buf<uint8_t> nmarked = alloc<uint8_t>(ctx, c0);
+      CompactDev cd{c0,      keep.p,  unmk.p,   K.st.p,   K.text.p, leaf ? nullptr : K.marked.p,
+                    leaf ? nullptr : K.lm.p,    nst.p,    ntext.p,  nmarked.p,
+                    nlm.p,   nuoff.p};
+      HIPCHK(ctx, launch_compact(cd, s));
+      std::vector<uint64_t> got;
+      read_words(ctx, {{ntc.p, T}, {ntu.p, T}, {keep.p + c0, 1}, {unmk.p + c0, 1}}, got);
+      std::vector<uint64_t> tc(got.begin(), got.begin() + T), tu(got.begin() + T, got.begin() + 2 * T);
+      std::vector<uint64_t> tf(T + 1, 0);
+      for (uint32_t t = 0; t < T; ++t) tf[t + 1] = tf[t] + tc[t];
+      const uint64_t c = got[2 * T], u = got[2 * T + 1];
+      if (leaf) {
+        store_leaf_level(step, K.b, c, nst.p, ntext.p, tc, tf, ntf.p, ntc.p, nullptr, 0);
+      } else {
+        // runs of the stored level: a pointer that spills names two consecutive blocks
+        Buf<uint64_t> roff = alloc<uint64_t>(ctx, c + 1), rs = alloc<uint64_t>(ctx, c),
+                      re = alloc<uint64_t>(ctx, c);
+        Buf<uint32_t> run = alloc<uint32_t>(ctx, c), rtext = alloc<uint32_t>(ctx, c);
+        HIPCHK(ctx, launch_run_flags(nst.p, ntext.p, c, K.b, roff.p, s));
+        scan(roff.p, c);
+        HIPCHK(ctx, launch_run_table(nst.p, ntext.p, c, K.b, tx, roff.p, run.p, rs.p, re.p,
+                                     rtext.p, s));
+        PhaseArgs pa{};
+        pa.tx = tx;
+        pa.lv = LevelDev{c, K.b, nst.p, ntext.p, run.p, 0, rs.p, re.p, rtext.p};
+        pa.k.lm = nlm.p;
+        Buf<uint64_t> spb = alloc<uint64_t>(ctx, u), spo = alloc<uint64_t>(ctx, u);
+        if (c) HIPCHK(ctx, launch_pointers(pa, nmarked.p, nuoff.p, ntf.p, spb.p, spo.p, err, s));
+        store_level(step, K.b, c, nst.p, ntext.p, nmarked.p, nuoff.p, spb, spo, u, tc, tf, tu,
+                    ntf.p, ntc.p);
+      }
+      K = PruneLevel{};
+    };
+    for (int step = (int)H - 2; step >= 0; --step) {
+      PruneLevel& L = pl[step];
+      PruneLevel& C = pl[step + 1];
+      const bool child_leaf = step + 2 == (int)H;
+      const uint64_t c = L.c;
+      Buf<uint8_t> tgt = alloc<uint8_t>(ctx, c), state = alloc<uint8_t>(ctx, c);
+      Buf<uint64_t> tinfo = alloc<uint64_t>(ctx, c);
+      Buf<uint32_t> pending = alloc<uint32_t>(ctx, c);
+      Buf<uint8_t> cgone = alloc<uint8_t>(ctx, C.c);
+      HIPCHK(ctx, launch_fill_u8(tgt.p, 0, c, s));
+      HIPCHK(ctx, launch_fill_u8(cgone.p, 0, C.c, s));
+      PruneDev d{};
+      d.lv = LevelDev{c, L.b, L.st.p, L.text.p, L.run.p, 0, nullptr, nullptr, nullptr};
+      d.tx = tx;
+      d.lm = L.lm.p;
+      d.marked = L.marked.p;
+      d.tgt = tgt.p;
+      d.state = state.p;
+      d.tinfo = tinfo.p;
+      d.pending = pending.p;
+      d.counters = open.p;
+      d.cmarked = child_leaf ? nullptr : C.marked.p;
+      d.cgone = cgone.p;
+      d.cs = L.cs.p;
+      d.tfirst = L.tfirst.p;
+      d.ctfirst = C.tfirst.p;
+      d.err = err;
+      HIPCHK(ctx, launch_prune_decide_begin(d, s));
+      // every round settles at least one candidate
+      for (uint64_t round = 0;; ++round) {
+        HIPCHK(ctx, launch_prune_round(d, s));
+        std::vector<uint64_t> left;
+        read_words(ctx, {{open.p, 1}}, left);
+        if (!left[0]) break;
+        if (round > c) {
+          ctx->err = "internal: pruning rounds do not settle";
+          throw Fail{BT_E_INTERNAL};
+        }
+      }
+      HIPCHK(ctx, launch_prune_apply(d, s));
+      compact_store((uint32_t)step + 1, cgone.p);
+    }
+    compact_store(0, nullptr);
   }
 
   std::vector<uint64_t> fin;

@@ -252,8 +252,54 @@ hipError_t launch_pack_marks(const uint8_t* marked, uint32_t T, const uint64_t* 
 hipError_t launch_leaves(const uint8_t* T, const LevelDev& lv, const TextsDev& tx,
                          uint8_t* out, hipStream_t s);
 
-// Per-level counts the host reads after each level: stored in a small device
-// array; see bt_host.cpp for the layout.
-hipError_t launch_text_firsts(const uint64_t* tcount_scanned, uint32_t T, hipStream_t s);
+// ---- optional pruning (prune.hip) ----
+constexpr uint8_t kPruneNot = 0;       // not a candidate
+constexpr uint8_t kPruneOpen = 1;      // candidate, undecided
+constexpr uint8_t kPrunePruned = 2;
+constexpr uint8_t kPruneKept = 3;      // kept, targets not yet released
+constexpr uint8_t kPruneKeptDone = 4;
+struct PruneDev {
+  LevelDev lv;              // one level in its built (unpruned) layout, runs valid
+  TextsDev tx;
+  const uint64_t* lm;       // [c] leftmost occurrence of every block on the level
+  uint8_t* marked;          // [c] marks; pruned blocks are cleared in place
+  uint8_t* tgt;             // [c] zeroed: targeted by a pointer of the level
+  uint8_t* state;           // [c] kPrune*
+  uint64_t* tinfo;          // [c] a candidate's target block; bit 63: spills into the next
+  uint32_t* pending;        // [c] open candidates that target the block
+  uint64_t* counters;       // [1] candidates still open after a round
+  const uint8_t* cmarked;   // child level's final marks; null when the children are leaves
+  uint8_t* cgone;           // [child c] zeroed: set for children of pruned blocks
+  const uint64_t* cs;       // [c+1] exclusive scan of child counts
+  const uint64_t* tfirst;   // [T] first block of each text on this level
+  const uint64_t* ctfirst;  // [T] first block of each text on the child level
+  uint32_t* err;            // set to 1 on a broken invariant
+};
+// targets, candidates and the edges between candidates
+hipError_t launch_prune_decide_begin(const PruneDev& d, hipStream_t s);
+// one settling round; counters[0] = candidates still open afterwards
+hipError_t launch_prune_round(const PruneDev& d, hipStream_t s);
+hipError_t launch_prune_apply(const PruneDev& d, hipStream_t s);
+
+struct CompactDev {
+  uint64_t c;               // blocks before compaction
+  const uint64_t* kidx;     // [c+1] exclusive scan of the keep flags
+  const uint64_t* uold;     // [c+1] exclusive scan of the kept-and-unmarked flags
+  const uint64_t* st;
+  const uint32_t* text;
+  const uint8_t* marked;    // may be null (leaf level)
+  const uint64_t* lm;       // may be null (leaf level)
+  uint64_t* nst;
+  uint32_t* ntext;
+  uint8_t* nmarked;
+  uint64_t* nlm;
+  uint64_t* nuoff;          // [kept+1] unmarked ranks of the compacted level
+};
+// keep[i] = !gone[i]; unmk[i] = kept and unmarked (0 everywhere when marked is null)
+hipError_t launch_keep_flags(const uint8_t* gone, const uint8_t* marked, uint64_t c, uint64_t* keep,
+                             uint64_t* unmk, hipStream_t s);
+hipError_t launch_compact(const CompactDev& d, hipStream_t s);
+hipError_t launch_gather_firsts(const uint64_t* kidx, const uint64_t* tfirst, uint32_t T,
+                                uint64_t* out, hipStream_t s);
 
 }  // namespace bt
