@@ -12,7 +12,8 @@ fingerprint probe, the dominant kernel): its algorithmic bytes (the two prefix
 values each window reads: 8 bytes of 32-bit pre-filter hashes, or 16 bytes of
 61-bit prefix fingerprints where the scan does not pre-filter) over its
 HIP-event time on the library's stream.  The cpu_baseline object times the CPU oracle on a bounded
-prefix of the same text.
+prefix of the same text.  The pruned_build object times the same build with the
+optional pruning phase (--prune times that as the main step instead).
 """
 import argparse
 import hashlib
@@ -353,6 +354,28 @@ def bench_serve(args, sigma, tau, leaf, desc, seconds=10.0):
     print(json.dumps(out), flush=True)
 
 
+def pruned_leg(ctx, d, n, sigma, tau, leaf, s_hint, step, steps=3):
+    """The same build with the optional pruning phase: rate and marked blocks."""
+    import torch
+    step(prune=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(prune=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    marked = {}
+    for pr in (False, True):
+        tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, prune=pr)
+        marked[pr] = int(sum(int(tree.level(l)[1].sum()) for l in range(1, tree.height)))
+        leaves = int(tree.level_info(tree.height)[1])
+        marked[pr] = (marked[pr], leaves)
+        tree.free()
+    return {"value": round(n / 1e6 / (ms / 1e3), 2), "unit": "MB/s", "ms_per_step": round(ms, 3),
+            "steps": steps, "marked_blocks": marked[True][0], "marked_blocks_unpruned": marked[False][0],
+            "leaf_blocks": marked[True][1], "leaf_blocks_unpruned": marked[False][1]}
+
+
 def cpu_baseline(T, sigma, tau, leaf, s_hint, sample_bytes):
     import oracle
     S = T[:sample_bytes]
@@ -371,6 +394,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="versioned256m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prune", action="store_true",
+                    help="time builds with the optional pruning phase (BT_PRUNE)")
+    ap.add_argument("--no-pruned-leg", action="store_true",
+                    help="skip the short pruned-build measurement beside the main line")
     ap.add_argument("--cpu-sample-mib", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
@@ -424,8 +451,8 @@ def main():
     torch.cuda.synchronize()
     ctx = bt.Context(0)
 
-    def step():
-        tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint)
+    def step(prune=args.prune):
+        tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, prune=prune)
         h = tree.height
         tree.free()
         return h
@@ -462,6 +489,10 @@ def main():
                 "kernel": "probe_scan", "launches_per_step": ps["launches"] // max(args.steps, 1),
                 "bytes_per_launch": round(ps["bytes"] / max(ps["launches"], 1)),
                 "avg_launch_ms": round(ps["ms"] / max(ps["launches"], 1), 5)}
+    pruned = None
+    if not args.prune and not args.no_pruned_leg:
+        pruned = pruned_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
+        log("pruned build: %s" % pruned)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(T, sigma, tau, leaf, s_hint, args.cpu_sample_mib << 20)
@@ -472,9 +503,12 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": n, "sigma": sigma,
-                   "tau": tau, "leaf_len": leaf, "s_hint": s_hint, "levels": h},
+                   "tau": tau, "leaf_len": leaf, "s_hint": s_hint, "levels": h,
+                   "prune": bool(args.prune)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    if pruned is not None:
+        out["pruned_build"] = pruned
     print(json.dumps(out), flush=True)
     ctx.close()
 

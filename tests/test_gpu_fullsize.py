@@ -9,7 +9,9 @@ any size, plus exact oracle answers on samples:
   - sampled pointers: the source equals the block and is its leftmost
     occurrence (direct search in the text);
   - sampled consecutive pairs: marked when and only when leftmost;
-and the tree of the text's first 4 MiB equals the oracle's tree exactly."""
+and the tree of the text's first 4 MiB equals the oracle's tree exactly.  The same
+workload with pruning (BT_PRUNE) is checked against the unpruned tree block by
+block, and its 4 MiB prefix against the oracle's pruned tree."""
 import numpy as np
 import pytest
 
@@ -100,4 +102,103 @@ def test_prefix_4mib_matches_oracle(built):
     S = T[:4 << 20]
     ora = oracle.build_tree(S, TAU, LEAF)
     got = ctx.build(d[:4 << 20], sigma=SIGMA, tau=TAU, leaf_len=LEAF)
+    assert got.serialize() == ora.canonical
+
+
+# ---- the same workload with the optional pruning phase (Section 4.1)
+
+@pytest.fixture(scope="module")
+def pruned(built):
+    T, d, ctx, tree = built
+    pt = ctx.build(d, sigma=SIGMA, tau=TAU, leaf_len=LEAF, prune=True)
+    yield pt
+    pt.free()
+
+
+def _shape(tree):
+    b, c, _ = tree.level_info(tree.height)
+    return treecheck.Shape(tree.n, TAU, LEAF, tree.b1,
+                           [tree.level(l) for l in range(1, tree.height)] +
+                           [(b, np.zeros(c, np.uint8), None, None)], b"")
+
+
+def test_pruned_access_reconstructs_all(built, pruned):
+    torch = torch_cuda()
+    T, d, ctx, tree = built
+    n = T.size
+    step = 1 << 24
+    for a in range(0, n, step):
+        pos = torch.arange(a, min(n, a + step), device="cuda:0", dtype=torch.int64).to(torch.uint64)
+        assert bool((pruned.access(pos) == d[a:a + step]).all()), "access differs in [%d, %d)" % (a, a + step)
+
+
+def test_pruned_against_unpruned(built, pruned):
+    """Level by level, blocks matched by their start: the pruned tree keeps a
+    subset of the unpruned tree's blocks, marks only go away, blocks unmarked in
+    both keep their source, every pruned block is targeted by no pointer and
+    its source ends before it; sampled pruned blocks: the source spells the
+    block and is its leftmost occurrence among the windows inside runs of the
+    unpruned level."""
+    T, d, ctx, tree = built
+    assert pruned.height == tree.height
+    su, sp = _shape(tree), _shape(pruned)
+    lu, lp = treecheck.block_layout(su), treecheck.block_layout(sp)
+    Tb = T.tobytes()
+    rng = np.random.default_rng(11)
+    sampled = total_pruned = 0
+    for li in range(tree.height - 1):
+        stu, lnu = lu[li]
+        stp, lnp = lp[li]
+        mu = su.levels[li][1].astype(bool)
+        mp = sp.levels[li][1].astype(bool)
+        idx = np.searchsorted(stu, stp)
+        assert (idx < stu.size).all() and (stu[idx] == stp).all(), "level %d: a block not in the unpruned tree" % (li + 1)
+        assert not (mp & ~mu[idx]).any(), "level %d: pruning marked a block" % (li + 1)
+
+        def sources(s, st, m):
+            _, _, pb, po = s.levels[li]
+            src = np.full(st.size, -1, np.int64)
+            src[~m] = st[pb.astype(np.int64)] + po.astype(np.int64)
+            return src, pb.astype(np.int64)
+        srcu, _ = sources(su, stu, mu)
+        srcp, tp = sources(sp, stp, mp)
+        both = ~mp & ~mu[idx]
+        assert (srcp[both] == srcu[idx][both]).all(), "level %d: a pointer changed" % (li + 1)
+        # targets of the pruned tree's pointers
+        tgt = np.zeros(stp.size, bool)
+        um = np.flatnonzero(~mp)
+        tgt[tp] = True
+        spill = srcp[um] + lnp[um] > stp[tp] + lnp[tp]
+        tgt[tp[spill] + 1] = True
+        pr = np.flatnonzero(~mp & mu[idx])
+        total_pruned += pr.size
+        assert not tgt[pr].any(), "level %d: a pruned block is targeted" % (li + 1)
+        assert (srcp[pr] + lnp[pr] <= stp[pr]).all()
+        if pr.size:
+            brk = np.flatnonzero(stu[1:] != stu[:-1] + lnu[:-1])
+            rs = np.concatenate([[stu[0]], stu[brk + 1]])
+            re = np.concatenate([stu[brk] + lnu[brk], [stu[-1] + lnu[-1]]])
+            runs = list(zip(rs.tolist(), re.tolist()))
+            for j in rng.choice(pr, min(10, pr.size), replace=False).tolist():
+                a, L, p = int(stp[j]), int(lnp[j]), int(srcp[j])
+                X = Tb[a:a + L]
+                assert Tb[p:p + L] == X
+                first = -1
+                for r0, r1 in runs:
+                    if r0 > p:
+                        break
+                    q = Tb.find(X, r0, min(r1, p + L))
+                    if q >= 0:
+                        first = q
+                        break
+                assert first == p, "level %d block at %d: source %d, leftmost on the level %d" % (li + 1, a, p, first)
+                sampled += 1
+    assert total_pruned > 1000 and sampled > 30
+
+
+def test_pruned_prefix_4mib_matches_oracle(built):
+    T, d, ctx, tree = built
+    S = T[:4 << 20]
+    ora = oracle.build_tree(S, TAU, LEAF, prune=True)
+    got = ctx.build(d[:4 << 20], sigma=SIGMA, tau=TAU, leaf_len=LEAF, prune=True)
     assert got.serialize() == ora.canonical
