@@ -903,6 +903,16 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.marked = marked.p;
     a.filt = filt.p;
     a.filt2 = filt2.p;
+    // parent facts per block: keys inside a parent region that occurs earlier
+    // are known copies and stay out of the table
+    Buf<uint8_t> cflag;
+    if (have_entries && c) {
+      cflag = alloc<uint8_t>(ctx, c);
+      HIPCHK(ctx, launch_fill_u8(cflag.p, 0, c, s));
+      HIPCHK(ctx, launch_child_flags(sg, b, ent_child.p, cflag.p, s));
+      a.cflag = cflag.p;
+    }
+    a.exact_all = prune ? 1 : 0;
 
     // Phase-2 segments come from this level's blocks and pair facts.
     Buf<uint64_t> bwc = alloc<uint64_t>(ctx, c + 1), bhd = alloc<uint64_t>(ctx, c + 1);

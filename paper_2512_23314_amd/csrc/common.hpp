@@ -14,6 +14,9 @@ constexpr uint64_t kP61 = 0x1FFFFFFFFFFFFFFFull;
 constexpr uint64_t kEmpty = ~0ull;          // empty hash slot / "no position"
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;    // block has no key in this phase
 constexpr uint32_t kOddKey = 0xFFFFFFFEu;   // key of non-standard length (text tail)
+// The key's string is known to occur earlier (from the level above); it is not
+// inserted, and its leftmost occurrence is recorded as "before its start".
+constexpr uint32_t kCopyKey = 0xFFFFFFFDu;
 constexpr uint64_t kWeakMask = 0xFFFull;    // BT_DBG_WEAK_HASH truncation
 
 // a * b mod (2^61 - 1) for a, b < 2^61 - 1.  The 122-bit product is split at

@@ -62,7 +62,7 @@ struct LevelDev {
 struct KeysDev {
   uint64_t* fp;     // [c]
   uint64_t* len;    // [c]
-  uint32_t* slot;   // [c] table slot, kNoKey or kOddKey
+  uint32_t* slot;   // [c] table slot, kNoKey, kOddKey or kCopyKey
   uint64_t* lm;     // [c] leftmost occurrence (result)
 };
 
@@ -123,11 +123,17 @@ struct PhaseArgs {
   // queued.
   uint32_t* filt2;
   uint32_t filt2_words;
+  // Facts about each block's parent (kSkip* of its scan entry, plus
+  // kLastChild), or null.  A key whose string lies inside a parent region that
+  // the level above proved to be a copy is not inserted (kCopyKey).
+  const uint8_t* cflag;
+  uint32_t exact_all;  // phase 2 over all blocks needs every block's exact leftmost occurrence
 };
 
 // Scan entries and segments (level.hip, "scan segments").
 constexpr uint8_t kSkipInterior = 1;  // windows ending inside the entry are copies
 constexpr uint8_t kSkipCross = 2;     // every window starting in the entry is a copy
+constexpr uint8_t kLastChild = 4;     // (per block) the last child of its parent
 struct SegDev {
   uint64_t E;             // entries
   const uint64_t* ea;     // [E] entry start
@@ -177,6 +183,11 @@ hipError_t launch_entries_next(const LevelDev& lv, const TextsDev& tx, const uin
                                uint8_t* ef, uint64_t* echild, hipStream_t s);
 hipError_t launch_entry_runs(const uint64_t* echild, uint64_t E, const uint32_t* run,
                              uint32_t* erun, hipStream_t s);
+// Per-block parent facts from the level's entries: cflag (c bytes, zeroed by
+// the caller) gets the entry's kSkip* flags on each child of a flagged entry,
+// plus kLastChild on its last child.  b: this level's block length.
+hipError_t launch_child_flags(const SegDev& sg, uint64_t b, const uint64_t* echild, uint8_t* cflag,
+                              hipStream_t s);
 // Per-segment window counts into woff[0..E) (then scanned by the caller).
 hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff, hipStream_t s);
 // Phase-2 segments from this level's pair facts (bit 0 of pf); see level.hip.

@@ -60,6 +60,23 @@ __global__ void k_keys(PhaseArgs a) {
       a.k.slot[j] = kNoKey;
       continue;
     }
+    if (a.cflag) {
+      // Strings inside a parent region that occurs earlier occur earlier too:
+      // a pair window of length 2b <= b_parent starting in a parent whose pair
+      // with the next parent occurs earlier, or lying inside a parent that
+      // occurs earlier (itself, or as part of its pair with the previous one).
+      // Marks and facts only need "before its start" for these; phase 2 needs
+      // exact positions for unmarked blocks, and for all blocks when pruning.
+      const uint8_t f = a.cflag[j];
+      const bool copy = (a.phase == 1)
+                            ? ((f & kSkipCross) || ((f & kSkipInterior) && !(f & kLastChild)))
+                            : (!a.exact_all && a.marked[j] && (f & (kSkipCross | kSkipInterior)));
+      if (copy) {
+        a.k.slot[j] = kCopyKey;
+        a.k.lm[j] = st - 1;
+        continue;
+      }
+    }
     const uint64_t xp = (L == a.Lmain) ? a.xLmain : pow61(a.x, L);
     const uint64_t fp = finish_fp(window_fp(a.P, st, L, xp), a.tx.tsalt[t], a.fpmask);
     a.k.fp[j] = fp;
@@ -215,6 +232,23 @@ hipError_t launch_entries_next(const LevelDev& lv, const TextsDev& tx, const uin
   if (E)
     k_entries_entering<<<grid_for(E, 256), 256, 0, s>>>(ids, E, tx, nmarked, ntfirst, ea, ee, ef,
                                                           echild);
+  return hipGetLastError();
+}
+
+__global__ void k_child_flags(SegDev sg, uint64_t b, const uint64_t* echild, uint8_t* cflag) {
+  GRID_STRIDE(k, sg.E) {
+    const uint8_t f = sg.ef[k];
+    if (!f) continue;
+    const uint64_t n = (sg.ee[k] - sg.ea[k] + b - 1) / b;
+    const uint64_t c0 = echild[k];
+    for (uint64_t i = 0; i < n; ++i) cflag[c0 + i] = f | (i + 1 == n ? kLastChild : 0);
+  }
+}
+
+hipError_t launch_child_flags(const SegDev& sg, uint64_t b, const uint64_t* echild, uint8_t* cflag,
+                              hipStream_t s) {
+  if (!sg.E) return hipSuccess;
+  k_child_flags<<<grid_for(sg.E, 256), 256, 0, s>>>(sg, b, echild, cflag);
   return hipGetLastError();
 }
 
@@ -697,7 +731,7 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(PhaseArgs a, Verify
     uint64_t best = 0;
     if (j < c) {
       const uint32_t s = a.k.slot[j];
-      if (s != kNoKey) {
+      if (s != kNoKey && s != kCopyKey) {
         const uint64_t pos = a.lv.st[j];
         best = (s == kOddKey) ? a.odd.best[a.lv.text[j]] : a.tab.slots[s].best;
         if (best == pos) a.k.lm[j] = pos;
