@@ -472,7 +472,7 @@ def main():
     ms = dt / args.steps * 1e3
     value = n / 1e6 / (ms / 1e3)
 
-    stats = {k: ctx.kernel_stats(k) for k in ("probe_scan", "prefix_fp", "verify")}
+    stats = {k: ctx.kernel_stats(k) for k in ("probe_scan", "byte_scan", "prefix_fp", "prefix_h32", "verify")}
     for k, s in stats.items():
         if s["launches"]:
             log("%-10s launches %5d  total %8.3f ms  avg %.4f ms  units %.3e  GB/s %.1f" % (
@@ -507,6 +507,13 @@ def main():
                    "prune": bool(args.prune)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    # per-kernel figures of the timed steps (HIP events on the library stream;
+    # algorithmic bytes as in the roofline: 8 or 16 B per probe-scan window,
+    # 1 B per byte-scan window, 9 B per text byte for the prefix scan)
+    out["kernels"] = {k: {"launches_per_step": s["launches"] // max(args.steps, 1),
+                          "ms_per_step": round(s["ms"] / max(args.steps, 1), 4),
+                          "algorithmic_GBps": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1)}
+                      for k, s in stats.items() if s["launches"]}
     if pruned is not None:
         out["pruned_build"] = pruned
     print(json.dumps(out), flush=True)

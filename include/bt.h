@@ -56,6 +56,10 @@ extern "C" {
  * otherwise taken only past the queues' packing limits (more than 2^24 texts
  * in a batch, or positions beyond 2^40); the output must not change. */
 #define BT_DBG_NO_QUEUE 2u
+/* Scan every phase with the 32-bit hash pre-filter, also where the byte scan
+ * (a filter on each window's first eight bytes, used for phases with few keys)
+ * would be taken; the output must not change. */
+#define BT_DBG_NO_BYTE_SCAN 4u
 
 /* ---- build flags (bt_params.flags) ---- */
 /* Also build the counters that bt_rank and bt_select need: per block and per
@@ -126,7 +130,7 @@ BT_API int bt_ctx_trim(bt_ctx* ctx);
  * kernel's algorithmic traffic (the bytes the method must move; defined with
  * each kernel in the design notes) and `units` its work units (windows for the
  * probe scan, text bytes for the prefix scan).  Names: "prefix_fp",
- * "probe_scan", "verify". */
+ * "prefix_h32", "probe_scan", "byte_scan", "verify". */
 BT_API int bt_ctx_profile(bt_ctx* ctx, int enable);
 BT_API int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches,
                         double* total_ms, double* bytes, double* units);

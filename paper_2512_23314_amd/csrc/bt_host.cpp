@@ -950,10 +950,26 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         scan_mode = 2;
         fbits = 19;
       }
+      // The byte scan: phase 1 of the upper levels, whose few keys (pairs of
+      // 2b >= 32 bytes, short final pairs of more than b) are all at least 8
+      // bytes long.  A 2^19-bit filter of the keys' first eight bytes replaces
+      // the hash filters.  Its queue entries pack a position below 2^40, a
+      // text below 2^23 and a fit bit.
+      const bool byte_scan = phase == 1 && b >= 16 && nkeys <= 128 && T < (1u << 23) &&
+                             offs[T] < (1ull << 40) && !(prm.debug_flags & BT_DBG_NO_BYTE_SCAN);
+      uint32_t bbits = 0;
+      if (byte_scan) {
+        bbits = 19;
+        fbits = 0;
+        f2words = 0;
+        scan_mode = 1;
+      }
       a.filt_bits = fbits;
-      a.filt_two = 8 * nkeys <= (1ull << fbits);
-      a.pre32 = scan_mode == 1;
+      a.filt_two = fbits && 8 * nkeys <= (1ull << fbits);
+      a.pre32 = !byte_scan && scan_mode == 1;
       a.filt2_words = f2words;
+      a.bfilt = byte_scan ? filt.p : nullptr;
+      a.bfilt_bits = bbits;
       a.x32L = host_pow32(x32, a.Lmain);
       {
         FillList f;
@@ -961,7 +977,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         f.add(tags.p, cap / 4, 0);
         f.add(oddb.p, 14 * (uint64_t)T, 0);
         f.add(vcnt.p, 4, 0);
-        f.add(filt.p, (1ull << fbits) / 32, 0);
+        f.add(filt.p, (1ull << (byte_scan ? bbits : fbits)) / 32, 0);
         if (f2words) f.add(filt2.p, 1ull << f2words, 0);
         HIPCHK(ctx, launch_fill_many(f, s));
       }
@@ -991,9 +1007,16 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         HIPCHK(ctx, hipMemcpyAsync(wst, swoff + as.lv.R, 8, hipMemcpyDeviceToDevice, s));
       // algorithmic bytes per window: the two prefix values it reads (8-byte
       // 61-bit prefixes, or 4-byte 32-bit hashes when pre-filtering)
-      timed(ctx, "probe_scan", 0, 0, wst, a.pre32 ? 8.0 : 16.0, [&] {
-        return launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
-      });
+      if (byte_scan) {
+        // algorithmic bytes per window: the one text byte each window start adds
+        timed(ctx, "byte_scan", 0, 0, wst, 1.0, [&] {
+          return launch_byte_scan(as, swoff, has_odd, has_salt, c * b, s);
+        });
+      } else {
+        timed(ctx, "probe_scan", 0, 0, wst, a.pre32 ? 8.0 : 16.0, [&] {
+          return launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
+        });
+      }
       HIPCHK(ctx, launch_resolve(a, vb, s));
       timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });
       HIPCHK(ctx, launch_finish(a, vb, s));

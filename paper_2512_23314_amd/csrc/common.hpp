@@ -98,6 +98,13 @@ __device__ __forceinline__ uint32_t filter2_mask(uint32_t h) {
   return (1u << (m >> 27)) | (1u << ((m >> 22) & 31));
 }
 
+// Filter bit of a string's first eight bytes (lo = bytes 0..3, hi = bytes
+// 4..7, little endian) in a filter of 2^bits bits: equal strings of length 8 or
+// more share it.  The top bits of each product depend on every bit of its word.
+__device__ __forceinline__ uint32_t prefix8_bit(uint32_t lo, uint32_t hi, uint32_t bits) {
+  return ((lo * 0x9E3779B1u) ^ (hi * 0x85EBCA77u)) >> (32 - bits);
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

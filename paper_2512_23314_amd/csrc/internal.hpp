@@ -128,6 +128,10 @@ struct PhaseArgs {
   // the level above proved to be a copy is not inserted (kCopyKey).
   const uint8_t* cflag;
   uint32_t exact_all;  // phase 2 over all blocks needs every block's exact leftmost occurrence
+  // Byte scan (few keys, all at least 8 bytes long): a bit filter of the keys'
+  // first eight bytes (2^bfilt_bits bits, 0 = off), tested on the text itself.
+  uint32_t* bfilt;
+  uint32_t bfilt_bits;
 };
 
 // Scan entries and segments (level.hip, "scan segments").
@@ -196,6 +200,10 @@ hipError_t launch_block_seg_counts(const PhaseArgs& a, const uint8_t* pf, uint64
 hipError_t launch_block_segments(const PhaseArgs& a, const uint64_t* wcs, const uint64_t* hs,
                                  uint64_t* ws, uint64_t* sre, uint32_t* stext, uint64_t* woff,
                                  hipStream_t s);
+// The byte scan: every window's first eight text bytes against the keys'
+// prefix filter; windows that pass form their fingerprint and probe the table.
+hipError_t launch_byte_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd, bool has_salt,
+                            uint64_t max_windows, hipStream_t s);
 // The sliding-window probe.  max_windows bounds the grid; mode 0: no filter,
 // 1: LDS key filter and per-wave candidate queues, 2: LDS key filter, inline probe.
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,

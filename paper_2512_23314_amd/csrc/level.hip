@@ -41,6 +41,17 @@ __device__ __forceinline__ uint64_t block_len(const LevelDev& lv, const TextsDev
 
 // ---------------------------------------------------------------- keys (a3, a6)
 
+// The key at st (at least 8 bytes long) in the byte scan's prefix filter.
+__device__ __forceinline__ void set_prefix_bit(const PhaseArgs& a, uint64_t st) {
+  uint32_t lo = 0, hi = 0;
+  for (int k = 0; k < 4; ++k) {
+    lo |= (uint32_t)a.T[st + k] << (8 * k);
+    hi |= (uint32_t)a.T[st + 4 + k] << (8 * k);
+  }
+  const uint32_t bit = prefix8_bit(lo, hi, a.bfilt_bits);
+  atomicOr(&a.bfilt[bit >> 5], 1u << (bit & 31));
+}
+
 __global__ void k_keys(PhaseArgs a) {
   const LevelDev lv = a.lv;
   GRID_STRIDE(j, lv.c) {
@@ -108,6 +119,7 @@ __global__ void k_keys(PhaseArgs a) {
         atomicOr(&a.filt[f1 >> 5], 1u << (f1 & 31));
         if (a.filt_two) atomicOr(&a.filt[f2 >> 5], 1u << (f2 & 31));
       }
+      if (a.bfilt_bits) set_prefix_bit(a, st);
     } else {
       // the one key of this text that ends at the text's end with a short block
       a.k.slot[j] = kOddKey;
@@ -123,6 +135,7 @@ __global__ void k_keys(PhaseArgs a) {
       }
       const uint32_t h = a.P32[st + L] - a.P32[st] * x32p + (uint32_t)a.tx.tsalt[t];
       a.odd.h32[t] = (uint64_t)h | ((uint64_t)x32p << 32);
+      if (a.bfilt_bits) set_prefix_bit(a, st);
     }
   }
 }
@@ -707,6 +720,208 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
   }
 #undef BT_PROBE_SALT
 #undef BT_PROBE_LAUNCH
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- byte scan (a4)
+//
+// For phases with few keys (the upper levels, whose blocks are longer than the
+// spacing of the text's differences, so that no window is skipped), reading
+// two prefix hashes per window is the whole cost.  Here a window is first
+// tested on its own first eight bytes against a filter of the keys' first
+// eight bytes: 1 byte of text per window instead of 8 bytes of hashes.  Equal
+// strings share their first eight bytes, so every occurrence of a key passes.
+// The windows that pass (in a repetitive text, mostly true copies of a key's
+// first eight bytes) go to the per-wave LDS queue of the probe scan and form
+// their 61-bit fingerprints 64 at a time.
+//
+// A wave takes 1024 consecutive window numbers; lane l takes 16 consecutive
+// ones.  When they lie in one segment the lane loads the 28 aligned bytes that
+// cover them and takes each window's eight bytes with byte-aligns.
+constexpr int kByteThreads = 1024;
+constexpr int kByteK = 16;  // windows per lane
+// Queue entries: position in bits 0..39, text in bits 40..62, and bit 63 set
+// when the main-length window does not fit its run.
+constexpr uint64_t kByteTextMask = (1ull << 23) - 1;
+
+template <bool ODD, bool SALT>
+__global__ __launch_bounds__(kByteThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
+  extern __shared__ uint64_t s_lds[];
+  uint32_t* s_bf = reinterpret_cast<uint32_t*>(s_lds);
+  const uint32_t bits = a.bfilt_bits;
+  {
+    const uint32_t nq = 1u << (bits - 7);  // uint4 words
+    const uint4* src = reinterpret_cast<const uint4*>(a.bfilt);
+    uint4* dst = reinterpret_cast<uint4*>(s_bf);
+    for (uint32_t k = threadIdx.x; k < nq; k += blockDim.x) dst[k] = src[k];
+    __syncthreads();
+  }
+  const int lane = lane_id();
+  uint64_t* q = s_lds + (1ull << (bits - 6)) + (uint64_t)(threadIdx.x >> 6) * kQueue;
+  uint32_t qn = 0;  // wave-uniform queue length
+  const uint64_t R = a.lv.R;
+  const uint64_t W = woff[R];
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint8_t* __restrict__ T = a.T;
+  const uint64_t* __restrict__ P = a.P;
+  const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
+  Slot* __restrict__ slots = a.tab.slots;
+  const uint8_t* __restrict__ tags = a.tab.tag;
+  const uint64_t mask = a.tab.mask;
+  const auto has = [&](uint32_t lo, uint32_t hi) {
+    const uint32_t b = prefix8_bit(lo, hi, bits);
+    return ((s_bf[b >> 5] >> (b & 31)) & 1u) != 0;
+  };
+  // A queued window: its fingerprints against the keys.  Bit 63 of the entry
+  // says whether the main-length window fits its run.  A window of the short
+  // final key's length always fits (segments hold the windows of the shorter
+  // of the two lengths), so only the text's end bounds it.
+  const auto check = [&](uint64_t e) {
+    const uint64_t i = e & kQPosMask;
+    const uint32_t t = (uint32_t)((e >> kQPosBits) & kByteTextMask);  // bit 63 is the fit bit
+    const uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
+    if (!(e >> 63)) {
+      uint64_t f = sub61(P[i + L], mul61(P[i], xL));
+      if (SALT) f = add61(f, salt);
+      probe(slots, tags, mask, f & fmask, i);
+    }
+    if (ODD) {
+      const uint64_t oL = a.odd.L[t];
+      if (oL && i + oL <= a.tx.tend[t] && i < a.odd.pos[t]) {
+        uint64_t g = sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+        if (SALT) g = add61(g, salt);
+        if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
+          atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
+      }
+    }
+  };
+  // whole wave: append the lanes' candidates; check 64 once 64 are waiting.
+  // Bit 63 of an entry: the main-length window does not fit the run.
+  const auto push = [&](bool cand, uint64_t e) {
+    const uint64_t bal = __ballot(cand);
+    if (!bal) return;
+    const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+    if (cand) q[qn + my] = e;
+    qn += (uint32_t)__popcll(bal);
+    if (qn >= 64) {
+      wave_sync();
+      const uint64_t e0 = q[lane];
+      const bool mv = (uint32_t)lane < qn - 64;
+      const uint64_t e2 = mv ? q[64 + lane] : 0;
+      wave_sync();
+      if (mv) q[lane] = e2;
+      qn -= 64;
+      check(e0);
+      wave_sync();
+    }
+  };
+
+  for (uint64_t ch = gw; ch * (64ull * kByteK) < W; ch += nw) {
+    const uint64_t w0 = ch * (64ull * kByteK) + (uint64_t)lane * kByteK;
+    const bool any = w0 < W;  // lanes past the last window hold no segment
+    uint64_t r = 0, wo = 0, wn = 0, rs = 0, re = 0;
+    uint32_t t = 0;
+    if (any) {
+      uint64_t lo = 0, hi = R;
+      while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (woff[mid] <= w0) lo = mid; else hi = mid;
+      }
+      r = lo;
+      wo = woff[r];
+      wn = woff[r + 1];
+      rs = a.lv.rs[r];
+      re = a.lv.re[r];
+      t = a.lv.rtext[r];
+    }
+    const uint64_t i0 = rs + (w0 - wo);
+    const bool fast = any && w0 + (kByteK - 1) < wn && i0 + (kByteK - 1) + L <= re;
+    if (__ballot(fast) == ~0ull) {
+      // The 28 bytes from the 4-byte aligned address at or below T + i0 cover
+      // [i0, i0 + 23).  They end inside the lane's last window, which ends at
+      // or before the run end (L >= 16 > 12), and they start no lower than the
+      // aligned base of the allocation holding the text.
+      const uintptr_t ad = reinterpret_cast<uintptr_t>(T + i0);
+      const uint32_t* wp = reinterpret_cast<const uint32_t*>(ad & ~(uintptr_t)3);
+      uint32_t w[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) w[k] = wp[k];
+      const uint32_t sh = (uint32_t)(ad & 3);
+      uint32_t x[6];  // x[k] = bytes [i0 + 4k, i0 + 4k + 4)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) x[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+      uint32_t m = 0;  // bit k: window i0 + k passes
+#pragma unroll
+      for (int k = 0; k < kByteK; ++k) {
+        const int qq = k >> 2, o = k & 3;
+        const uint32_t l4 = o ? __builtin_amdgcn_alignbyte(x[qq + 1], x[qq], o) : x[qq];
+        const uint32_t h4 = o ? __builtin_amdgcn_alignbyte(x[qq + 2], x[qq + 1], o) : x[qq + 1];
+        m |= (has(l4, h4) ? 1u : 0u) << k;
+      }
+      if (__ballot(m != 0)) {  // most chunks of the upper levels have no candidate
+        const uint64_t tag = (uint64_t)t << kQPosBits;
+        for (int k = 0; k < kByteK; ++k) push((m >> k) & 1u, tag | (i0 + k));
+      }
+      continue;
+    }
+    for (int k = 0; k < kByteK; ++k) {
+      const uint64_t wi = w0 + k;
+      const bool live = wi < W;  // every lane stays in the loop (the queue is wave-wide)
+      if (live && wi >= wn) {
+        do {
+          ++r;
+          wo = wn;
+          wn = woff[r + 1];
+        } while (wi >= wn);
+        rs = a.lv.rs[r];
+        re = a.lv.re[r];
+        t = a.lv.rtext[r];
+      }
+      // every window of a segment has at least 8 bytes before the run end
+      const uint64_t i = rs + (wi - wo);
+      bool cand = false;
+      if (live) {
+        uint32_t l4 = 0, h4 = 0;
+        for (int b = 0; b < 4; ++b) {
+          l4 |= (uint32_t)T[i + b] << (8 * b);
+          h4 |= (uint32_t)T[i + 4 + b] << (8 * b);
+        }
+        cand = has(l4, h4);
+      }
+      const uint64_t nofit = (i + L > re) ? (1ull << 63) : 0;
+      push(cand, nofit | ((uint64_t)t << kQPosBits) | i);
+    }
+  }
+  if (qn) {
+    wave_sync();
+    if ((uint32_t)lane < qn) check(q[lane]);
+  }
+}
+
+hipError_t launch_byte_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd, bool has_salt,
+                            uint64_t max_windows, hipStream_t s) {
+  if (a.lv.R == 0) return hipSuccess;
+  if (a.bfilt_bits < 12 || a.bfilt_bits > 19) return hipErrorInvalidValue;
+  const uint64_t waves = (max_windows + 64 * kByteK - 1) / (64 * kByteK);
+  const unsigned grid = grid_for(waves * 64, kByteThreads, 512);
+  // filter up to 64 KiB + queues 16 KiB: two 1024-thread workgroups per CU
+  const size_t lds = ((size_t)1 << (a.bfilt_bits - 3)) + (size_t)(kByteThreads / 64) * kQueue * 8;
+#define BT_BYTE_LAUNCH(O, S)                                                               \
+  do {                                                                                     \
+    if (lds > 65536) {                                                                     \
+      const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_byte_scan<O, S>), lds); \
+      if (e != hipSuccess) return e;                                                       \
+    }                                                                                      \
+    k_byte_scan<O, S><<<grid, kByteThreads, lds, s>>>(a, woff);                            \
+  } while (0)
+  if (has_odd) {
+    if (has_salt) BT_BYTE_LAUNCH(true, true); else BT_BYTE_LAUNCH(true, false);
+  } else {
+    if (has_salt) BT_BYTE_LAUNCH(false, true); else BT_BYTE_LAUNCH(false, false);
+  }
+#undef BT_BYTE_LAUNCH
   return hipGetLastError();
 }
 

@@ -79,7 +79,8 @@ def test_batch_with_offset_and_weak_hash(ctx):
     offs = [13]
     for T in texts:
         offs.append(offs[-1] + len(T))
-    for flags in (0, bt.BT_DBG_WEAK_HASH, bt.BT_DBG_NO_QUEUE, bt.BT_DBG_NO_QUEUE | bt.BT_DBG_WEAK_HASH):
+    for flags in (0, bt.BT_DBG_WEAK_HASH, bt.BT_DBG_NO_QUEUE, bt.BT_DBG_NO_QUEUE | bt.BT_DBG_WEAK_HASH,
+                  bt.BT_DBG_NO_BYTE_SCAN):
         trees = ctx.build_batch(to_device(concat), offs, tau=2, leaf_len=4, debug_flags=flags)
         for T, tr in zip(texts, trees):
             assert tr.serialize() == oracle.build_tree(T, 2, 4).canonical

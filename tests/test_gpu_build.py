@@ -98,6 +98,11 @@ def test_hash_independence_and_weak_hash(ctx):
         assert _build(ctx, T, 2, 4, debug_flags=bt.BT_DBG_NO_QUEUE).serialize() == ref
         assert _build(ctx, T, 2, 4,
                       debug_flags=bt.BT_DBG_NO_QUEUE | bt.BT_DBG_WEAK_HASH).serialize() == ref
+        # the hash pre-filter where the byte scan would be taken, and the byte
+        # scan with forced collisions
+        assert _build(ctx, T, 2, 4, debug_flags=bt.BT_DBG_NO_BYTE_SCAN).serialize() == ref
+        assert _build(ctx, T, 2, 16, debug_flags=bt.BT_DBG_WEAK_HASH).serialize() == \
+            oracle.build_tree(T, 2, 16).canonical
 
 
 @pytest.mark.parametrize("n,tau,leaf", [(0, 2, 16), (1, 2, 16), (15, 2, 16), (16, 2, 16),
@@ -113,6 +118,17 @@ def test_edge_sizes(ctx, n, tau, leaf):
     else:
         tree = _build(ctx, T, tau, leaf)
     assert_same_tree(tree, ora)
+
+
+def test_build_from_unaligned_views(ctx):
+    """Texts that start 1..3 bytes past a 4-byte boundary: the byte scan reads
+    aligned words around each lane's windows."""
+    T = synth.markov_versions(200003, 8192, 20, 2e-3, 32, 23)
+    d = to_device(T)
+    for off in (1, 2, 3, 5):
+        for tau, leaf in ((4, 16), (2, 8)):
+            tree = ctx.build(d[off:], tau=tau, leaf_len=leaf)
+            assert tree.serialize() == oracle.build_tree(T[off:], tau, leaf).canonical
 
 
 def test_root_block_len_override(ctx):
