@@ -952,14 +952,19 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       }
       // The byte scan: phase 1 of the upper levels, whose few keys (pairs of
       // 2b >= 32 bytes, short final pairs of more than b) are all at least 8
-      // bytes long.  A 2^19-bit filter of the keys' first eight bytes replaces
-      // the hash filters.  Its queue entries pack a position below 2^40, a
-      // text below 2^23 and a fit bit.
+      // bytes long.  A filter of the keys' first eight bytes replaces the hash
+      // filters.  Its queue entries pack a position below 2^40, a text below
+      // 2^23 and a fit bit.  (Measured: with more keys, or in phase 2, the
+      // windows that share a key's first eight bytes cost more than the hash
+      // filters save.)
       const bool byte_scan = phase == 1 && b >= 16 && nkeys <= 128 && T < (1u << 23) &&
                              offs[T] < (1ull << 40) && !(prm.debug_flags & BT_DBG_NO_BYTE_SCAN);
       uint32_t bbits = 0;
       if (byte_scan) {
-        bbits = 19;
+        // at least 2048 bits per key (chance passes below 1/2048 of windows);
+        // every workgroup copies the filter into LDS
+        bbits = 12;
+        while (bbits < 19 && (1ull << bbits) < 2048 * nkeys) ++bbits;
         fbits = 0;
         f2words = 0;
         scan_mode = 1;
@@ -982,6 +987,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         HIPCHK(ctx, launch_fill_many(f, s));
       }
       HIPCHK(ctx, launch_keys(a, s));
+      // no keys: the slots say so (kNoKey), and there is nothing to scan for
+      if (nkeys == 0) return;
       PhaseArgs as = a;  // the scan walks segments in place of runs
       uint64_t* swoff = woff.p;
       uint64_t* wst = wstats.p + 2 * step + (phase - 1);

@@ -837,11 +837,14 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
       t = a.lv.rtext[r];
     }
     const uint64_t i0 = rs + (w0 - wo);
+    // the lane's 16 windows in one segment, all of main length inside the run
     const bool fast = any && w0 + (kByteK - 1) < wn && i0 + (kByteK - 1) + L <= re;
-    if (__ballot(fast) == ~0ull) {
+    uint32_t m = 0;  // bit k: window w0 + k passes
+    if (fast) {
       // The 28 bytes from the 4-byte aligned address at or below T + i0 cover
       // [i0, i0 + 23).  They end inside the lane's last window, which ends at
-      // or before the run end (L >= 16 > 12), and they start no lower than the
+      // or before the run end (L >= 16 > 12: keys of the byte scan are blocks
+      // or pairs of blocks of b >= 16), and they start no lower than the
       // aligned base of the allocation holding the text.
       const uintptr_t ad = reinterpret_cast<uintptr_t>(T + i0);
       const uint32_t* wp = reinterpret_cast<const uint32_t*>(ad & ~(uintptr_t)3);
@@ -852,7 +855,6 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
       uint32_t x[6];  // x[k] = bytes [i0 + 4k, i0 + 4k + 4)
 #pragma unroll
       for (int k = 0; k < 6; ++k) x[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
-      uint32_t m = 0;  // bit k: window i0 + k passes
 #pragma unroll
       for (int k = 0; k < kByteK; ++k) {
         const int qq = k >> 2, o = k & 3;
@@ -860,38 +862,50 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         const uint32_t h4 = o ? __builtin_amdgcn_alignbyte(x[qq + 2], x[qq + 1], o) : x[qq + 1];
         m |= (has(l4, h4) ? 1u : 0u) << k;
       }
-      if (__ballot(m != 0)) {  // most chunks of the upper levels have no candidate
-        const uint64_t tag = (uint64_t)t << kQPosBits;
-        for (int k = 0; k < kByteK; ++k) push((m >> k) & 1u, tag | (i0 + k));
-      }
-      continue;
-    }
-    for (int k = 0; k < kByteK; ++k) {
-      const uint64_t wi = w0 + k;
-      const bool live = wi < W;  // every lane stays in the loop (the queue is wave-wide)
-      if (live && wi >= wn) {
-        do {
-          ++r;
-          wo = wn;
-          wn = woff[r + 1];
-        } while (wi >= wn);
-        rs = a.lv.rs[r];
-        re = a.lv.re[r];
-        t = a.lv.rtext[r];
-      }
-      // every window of a segment has at least 8 bytes before the run end
-      const uint64_t i = rs + (wi - wo);
-      bool cand = false;
-      if (live) {
+    } else if (any) {
+      // windows across segment ends: walk them one by one (this lane only)
+      uint64_t r2 = r, wo2 = wo, wn2 = wn, rs2 = rs;
+      for (int k = 0; k < kByteK; ++k) {
+        const uint64_t wi = w0 + k;
+        if (wi >= W) break;
+        while (wi >= wn2) {
+          ++r2;
+          wo2 = wn2;
+          wn2 = woff[r2 + 1];
+          rs2 = a.lv.rs[r2];
+        }
+        // every window of a segment has at least 8 bytes before the run end
+        const uint64_t i = rs2 + (wi - wo2);
         uint32_t l4 = 0, h4 = 0;
         for (int b = 0; b < 4; ++b) {
           l4 |= (uint32_t)T[i + b] << (8 * b);
           h4 |= (uint32_t)T[i + 4 + b] << (8 * b);
         }
-        cand = has(l4, h4);
+        m |= (has(l4, h4) ? 1u : 0u) << k;
       }
-      const uint64_t nofit = (i + L > re) ? (1ull << 63) : 0;
-      push(cand, nofit | ((uint64_t)t << kQPosBits) | i);
+    }
+    if (!__ballot(m != 0)) continue;  // most chunks hold no candidate
+    // queue the candidates, 16 wave-wide steps; lanes that walked segments
+    // walk them again, now with the run end and text of each window
+    for (int k = 0; k < kByteK; ++k) {
+      uint64_t e = 0;
+      const bool c = (m >> k) & 1u;
+      if (c) {
+        const uint64_t wi = w0 + k;
+        if (!fast) {
+          while (wi >= wn) {
+            ++r;
+            wo = wn;
+            wn = woff[r + 1];
+            rs = a.lv.rs[r];
+            re = a.lv.re[r];
+            t = a.lv.rtext[r];
+          }
+        }
+        const uint64_t i = rs + (wi - wo);
+        e = ((i + L > re) ? (1ull << 63) : 0) | ((uint64_t)t << kQPosBits) | i;
+      }
+      push(c, e);
     }
   }
   if (qn) {
