@@ -13,7 +13,9 @@ values each window reads: 8 bytes of 32-bit pre-filter hashes, or 16 bytes of
 61-bit prefix fingerprints where the scan does not pre-filter) over its
 HIP-event time on the library's stream.  The cpu_baseline object times the CPU oracle on a bounded
 prefix of the same text.  The pruned_build object times the same build with the
-optional pruning phase (--prune times that as the main step instead).
+optional pruning phase (--prune times that as the main step instead); the
+lean_build object times it with sampled prefix fingerprints (--lean) and gives
+both builds' peak device memory.
 """
 import argparse
 import hashlib
@@ -376,6 +378,37 @@ def pruned_leg(ctx, d, n, sigma, tau, leaf, s_hint, step, steps=3):
             "leaf_blocks": marked[True][1], "leaf_blocks_unpruned": marked[False][1]}
 
 
+def peak_build_bytes(ctx, d, sigma, tau, leaf, s_hint, lean):
+    """Most device memory the pool hands out during one build (scratch plus the
+    finished tree's storage), over what it held before."""
+    import torch
+    torch.cuda.synchronize()
+    base = ctx.memory()["in_use"]
+    ctx.reset_peak()
+    tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, lean=lean)
+    peak = ctx.memory()["peak"] - base
+    tree.free()
+    return peak
+
+
+def lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step, steps=3):
+    """The same build with sampled prefix fingerprints: rate and peak memory."""
+    import torch
+    step(prune=False, lean=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(prune=False, lean=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    dense = peak_build_bytes(ctx, d, sigma, tau, leaf, s_hint, False)
+    lean = peak_build_bytes(ctx, d, sigma, tau, leaf, s_hint, True)
+    return {"value": round(n / 1e6 / (ms / 1e3), 2), "unit": "MB/s", "ms_per_step": round(ms, 3),
+            "steps": steps, "peak_build_bytes": lean, "peak_build_bytes_dense": dense,
+            "peak_bytes_per_text_byte": round(lean / n, 3),
+            "peak_bytes_per_text_byte_dense": round(dense / n, 3)}
+
+
 def cpu_baseline(T, sigma, tau, leaf, s_hint, sample_bytes):
     import oracle
     S = T[:sample_bytes]
@@ -398,6 +431,10 @@ def main():
                     help="time builds with the optional pruning phase (BT_PRUNE)")
     ap.add_argument("--no-pruned-leg", action="store_true",
                     help="skip the short pruned-build measurement beside the main line")
+    ap.add_argument("--lean", action="store_true",
+                    help="time memory-lean builds (BT_LEAN: sampled prefix fingerprints)")
+    ap.add_argument("--no-lean-leg", action="store_true",
+                    help="skip the short memory-lean measurement beside the main line")
     ap.add_argument("--cpu-sample-mib", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
@@ -451,8 +488,8 @@ def main():
     torch.cuda.synchronize()
     ctx = bt.Context(0)
 
-    def step(prune=args.prune):
-        tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, prune=prune)
+    def step(prune=args.prune, lean=args.lean):
+        tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, prune=prune, lean=lean)
         h = tree.height
         tree.free()
         return h
@@ -493,6 +530,10 @@ def main():
     if not args.prune and not args.no_pruned_leg:
         pruned = pruned_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
         log("pruned build: %s" % pruned)
+    leanr = None
+    if not args.lean and not args.no_lean_leg:
+        leanr = lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
+        log("lean build: %s" % leanr)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(T, sigma, tau, leaf, s_hint, args.cpu_sample_mib << 20)
@@ -504,7 +545,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": n, "sigma": sigma,
                    "tau": tau, "leaf_len": leaf, "s_hint": s_hint, "levels": h,
-                   "prune": bool(args.prune)},
+                   "prune": bool(args.prune), "lean": bool(args.lean)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     # per-kernel figures of the timed steps (HIP events on the library stream;
@@ -516,6 +557,8 @@ def main():
                       for k, s in stats.items() if s["launches"]}
     if pruned is not None:
         out["pruned_build"] = pruned
+    if leanr is not None:
+        out["lean_build"] = leanr
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -77,6 +77,14 @@ extern "C" {
  * scans every block's leftmost occurrence on every level, not only those of
  * unmarked blocks. */
 #define BT_PRUNE 2u
+/* Memory-lean fingerprints: keep the prefix fingerprints mod 2^61-1 sampled,
+ * one value per 16 text bytes (0.5 bytes per text byte instead of 8), and form
+ * any other one from its sample and at most 15 text bytes where it is needed
+ * (key fingerprints, the scan's candidates, collision retries).  The 32-bit
+ * pre-filter hashes stay dense (4 bytes per text byte).  The tree does not
+ * change.  Taken when the scan queues its candidates: texts of a batch below
+ * 2^24, positions below 2^40, and not BT_DBG_NO_QUEUE; otherwise ignored. */
+#define BT_LEAN 4u
 
 typedef struct bt_ctx bt_ctx;   /* device, stream, scratch pool, statistics */
 typedef struct bt_tree bt_tree; /* a finished tree, resident in device memory */
@@ -96,7 +104,7 @@ typedef struct bt_tree bt_tree; /* a finished tree, resident in device memory */
  *   hash_seed      seeds the Karp-Rabin base x in [2^8, 2^61-1); the tree does
  *                  not depend on it.
  *   debug_flags    BT_DBG_* bits.
- *   flags          BT_WITH_RANK_SELECT and/or BT_PRUNE, or 0.
+ *   flags          BT_WITH_RANK_SELECT, BT_PRUNE and BT_LEAN bits, or 0.
  * Block lengths are b_l = b1 / tau^(l-1); the tree has h = k + 1 levels and
  * level h holds the leaves.  Every block has length b_l except the one that
  * ends the text, which may be shorter.
@@ -135,6 +143,12 @@ BT_API int bt_ctx_profile(bt_ctx* ctx, int enable);
 BT_API int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches,
                         double* total_ms, double* bytes, double* units);
 BT_API int bt_ctx_reset_stats(bt_ctx* ctx);
+/* Device memory of the context's pool, in bytes: handed out and not yet
+ * returned (scratch of a build in flight plus the storage of live trees), the
+ * most of that since the last bt_ctx_reset_peak, and all that the pool holds
+ * (cached blocks included).  Any output may be NULL.  Errors: BT_E_INVAL. */
+BT_API int bt_ctx_memory(const bt_ctx* ctx, uint64_t* in_use, uint64_t* peak, uint64_t* held);
+BT_API int bt_ctx_reset_peak(bt_ctx* ctx);
 
 /* ---- step (a2) on its own: prefix fingerprints ----
  * Section 2, the Karp-Rabin fingerprint phi, with q = 2^61-1 and r = x:

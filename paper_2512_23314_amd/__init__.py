@@ -20,6 +20,7 @@ BT_DBG_NO_QUEUE = 2
 BT_DBG_NO_BYTE_SCAN = 4
 BT_WITH_RANK_SELECT = 1
 BT_PRUNE = 2
+BT_LEAN = 4
 
 _lib = None
 
@@ -52,6 +53,8 @@ SIGNATURES = {
     "bt_ctx_profile": (_i32, [_vp, _i32]),
     "bt_ctx_kernel_stats": (_i32, [_vp, ctypes.c_char_p, _pu64, _pd, _pd, _pd]),
     "bt_ctx_reset_stats": (_i32, [_vp]),
+    "bt_ctx_memory": (_i32, [_vp, _pu64, _pu64, _pu64]),
+    "bt_ctx_reset_peak": (_i32, [_vp]),
     "bt_prefix_fingerprints": (_i32, [_vp, _vp, _u64, _u64, _vp]),
     "bt_build": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, ctypes.POINTER(_vp)]),
     "bt_build_ex": (_i32, [_vp, _vp, _u64, _u32, ctypes.POINTER(bt_params), ctypes.POINTER(_vp)]),
@@ -148,6 +151,15 @@ class Context:
     def trim(self):
         self._check(lib().bt_ctx_trim(self.h))
 
+    def memory(self):
+        """Pool bytes: in use, peak since reset_peak(), held (cached included)."""
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(lib().bt_ctx_memory(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"in_use": a.value, "peak": b.value, "held": c.value}
+
+    def reset_peak(self):
+        self._check(lib().bt_ctx_reset_peak(self.h))
+
     # ---- step a2
     def prefix_fingerprints(self, text, x, out=None):
         torch = _torch()
@@ -160,9 +172,10 @@ class Context:
     # ---- builds
     @staticmethod
     def params(tau, leaf_len, s_hint=1, root_block_len=0, hash_seed=0x0B10C7EE, debug_flags=0,
-               rank_select=False, prune=False):
+               rank_select=False, prune=False, lean=False):
         return bt_params(tau, leaf_len, root_block_len, s_hint, hash_seed, debug_flags,
-                         (BT_WITH_RANK_SELECT if rank_select else 0) | (BT_PRUNE if prune else 0))
+                         (BT_WITH_RANK_SELECT if rank_select else 0) | (BT_PRUNE if prune else 0) |
+                         (BT_LEAN if lean else 0))
 
     def build(self, text, sigma=256, tau=2, leaf_len=16, **kw):
         """Build the tree of a uint8 CUDA tensor; returns a Tree."""

@@ -56,6 +56,8 @@ class Pool {
     auto it = free_.lower_bound(want);
     if (it != free_.end() && it->first <= want + want / 4) {
       void* p = it->second;
+      in_use_ += it->first;
+      if (in_use_ > peak_) peak_ = in_use_;
       free_.erase(it);
       return p;
     }
@@ -82,6 +84,8 @@ class Pool {
     }
     size_[p] = want;
     held_ += want;
+    in_use_ += want;
+    if (in_use_ > peak_) peak_ = in_use_;
     return p;
   }
   void put(void* p) {
@@ -89,6 +93,7 @@ class Pool {
     std::lock_guard<std::mutex> g(mu_);
     auto it = size_.find(p);
     if (it == size_.end()) return;
+    in_use_ -= it->second;
     free_.emplace(it->second, p);
   }
   void trim() {
@@ -101,6 +106,13 @@ class Pool {
     free_.clear();
   }
   uint64_t held() const { return held_; }
+  // bytes handed out and not returned; the most of that since reset_peak()
+  uint64_t in_use() const { return in_use_; }
+  uint64_t peak() const { return peak_; }
+  void reset_peak() {
+    std::lock_guard<std::mutex> g(mu_);
+    peak_ = in_use_;
+  }
 
  private:
   static size_t round(size_t b) {
@@ -116,7 +128,7 @@ class Pool {
   std::mutex mu_;
   std::multimap<size_t, void*> free_;
   std::unordered_map<void*, size_t> size_;
-  uint64_t held_ = 0;
+  uint64_t held_ = 0, in_use_ = 0, peak_ = 0;
 };
 
 template <typename T>
@@ -578,19 +590,28 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         return BT_E_INVAL;
       }
 
-  // ---- step a2: prefix fingerprints of the concatenation, once
-  Buf<uint64_t> d_P = alloc<uint64_t>(ctx, N + 1);
+  // ---- step a2: prefix fingerprints of the concatenation, once.  A
+  // memory-lean build keeps one value in 16 (0.5 instead of 8 bytes per text
+  // byte) and forms the others where a fingerprint is needed: keys, queued
+  // candidates and retries.  Only the queued scan takes candidates that way.
+  const bool lean = (prm.flags & BT_LEAN) && T <= (1u << 24) && offs[T] < (1ull << 40) &&
+                    !(prm.debug_flags & BT_DBG_NO_QUEUE);
+  Buf<uint64_t> d_P = alloc<uint64_t>(ctx, lean ? N / 16 + 1 : N + 1);
   Buf<PfPow> d_pw = alloc<PfPow>(ctx, 1);
   fill_pow(ctx->h_pw, x);
   HIPCHK(ctx, hipMemcpyAsync(d_pw.p, ctx->h_pw, sizeof(PfPow), hipMemcpyHostToDevice, s));
   const uint64_t tiles = (N + kPfTile - 1) / kPfTile;
   Buf<uint64_t> d_status = alloc<uint64_t>(ctx, tiles + 1);
   Buf<uint64_t> d_ctr = alloc<uint64_t>(ctx, 1);
-  timed(ctx, "prefix_fp", (double)N + 8.0 * (double)(N + 1), (double)N, nullptr, 0, [&] {
-    return launch_prefix_fp(d_base + o0, N, d_P.p, d_pw.p, d_status.p,
-                            reinterpret_cast<uint32_t*>(d_ctr.p), s);
-  });
-  const uint64_t* P = d_P.p - o0;  // P[i] belongs to text position i; never read below o0
+  timed(ctx, "prefix_fp", (double)N + 8.0 * (double)(lean ? N / 16 + 1 : N + 1), (double)N, nullptr, 0,
+        [&] {
+          return lean ? launch_prefix_fp_sampled(d_base + o0, N, d_P.p, d_pw.p, d_status.p,
+                                                 reinterpret_cast<uint32_t*>(d_ctr.p), s)
+                      : launch_prefix_fp(d_base + o0, N, d_P.p, d_pw.p, d_status.p,
+                                         reinterpret_cast<uint32_t*>(d_ctr.p), s);
+        });
+  // P[i] belongs to text position i (never read below o0); null when sampled
+  const uint64_t* P = lean ? nullptr : d_P.p - o0;
 
   // 32-bit pre-filter hashes of the concatenation (same indexing as P)
   const uint32_t x32 = base32_from_seed(prm.hash_seed);
@@ -890,6 +911,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     PhaseArgs a{};
     a.T = d_base;
     a.P = P;
+    a.Ps = lean ? d_P.p : nullptr;
+    a.pbase = o0;
     a.P32 = H32;
     a.tx = tx;
     a.lv = lv;
@@ -1423,6 +1446,20 @@ int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches,
 int bt_ctx_reset_stats(bt_ctx* ctx) {
   if (!ctx) return BT_E_INVAL;
   ctx->stats.clear();
+  return BT_OK;
+}
+
+int bt_ctx_memory(const bt_ctx* ctx, uint64_t* in_use, uint64_t* peak, uint64_t* held) {
+  if (!ctx) return BT_E_INVAL;
+  if (in_use) *in_use = ctx->pool->in_use();
+  if (peak) *peak = ctx->pool->peak();
+  if (held) *held = ctx->pool->held();
+  return BT_OK;
+}
+
+int bt_ctx_reset_peak(bt_ctx* ctx) {
+  if (!ctx) return BT_E_INVAL;
+  ctx->pool->reset_peak();
   return BT_OK;
 }
 

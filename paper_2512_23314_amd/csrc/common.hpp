@@ -105,6 +105,17 @@ __device__ __forceinline__ uint32_t prefix8_bit(uint32_t lo, uint32_t hi, uint32
   return ((lo * 0x9E3779B1u) ^ (hi * 0x85EBCA77u)) >> (32 - bits);
 }
 
+// P[i] from prefix fingerprints sampled every 16 positions (Ps[q] = P[base +
+// 16 q]): the sample at or below i, then Horner's rule over the bytes between.
+__device__ __forceinline__ uint64_t prefix_at(const uint64_t* __restrict__ Ps,
+                                              const uint8_t* __restrict__ T, uint64_t base,
+                                              uint64_t x, uint64_t i) {
+  const uint64_t r = i - base;
+  uint64_t v = Ps[r >> 4];
+  for (uint64_t j = i - (r & 15); j < i; ++j) v = add61(mul61(v, x), T[j]);
+  return v;
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

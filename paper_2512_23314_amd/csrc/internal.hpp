@@ -32,6 +32,9 @@ struct PfPow32 {
 // status: ceil(n / tile) words, zeroed by the wrapper; ctr: one word.
 hipError_t launch_prefix_fp(const uint8_t* T, uint64_t n, uint64_t* P, const PfPow* pw,
                             uint64_t* status, uint32_t* ctr, hipStream_t s);
+// The same, stored sampled: Ps[q] = P[16 q] for 16 q <= n (n / 16 + 1 words).
+hipError_t launch_prefix_fp_sampled(const uint8_t* T, uint64_t n, uint64_t* Ps, const PfPow* pw,
+                                    uint64_t* status, uint32_t* ctr, hipStream_t s);
 // 32-bit prefix hashes H[0] = 0, H[i+1] = H[i] * x32 + T[i] (mod 2^32), the
 // cheap pre-filter of the probe scan (n + 1 outputs; status: tiles + 1 words).
 hipError_t launch_prefix_h32(const uint8_t* T, uint64_t n, uint32_t* H, const PfPow32* pw,
@@ -94,7 +97,9 @@ struct TableDev {
 
 struct PhaseArgs {
   const uint8_t* T;
-  const uint64_t* P;
+  const uint64_t* P;      // prefix fingerprints by text position, or null when sampled:
+  const uint64_t* Ps;     // Ps[q] = P[pbase + 16 q] (memory-lean builds)
+  uint64_t pbase;
   TextsDev tx;
   LevelDev lv;
   KeysDev k;

@@ -39,6 +39,20 @@ __device__ __forceinline__ uint64_t block_len(const LevelDev& lv, const TextsDev
   return te - st < lv.b ? te - st : lv.b;
 }
 
+// Window fingerprint P[i+L] - P[i] x^L from dense prefix fingerprints, or
+// (LEAN) from the samples of a memory-lean build.
+template <bool LEAN>
+__device__ __forceinline__ uint64_t win61(const PhaseArgs& a, uint64_t i, uint64_t L, uint64_t xL) {
+  if (LEAN)
+    return sub61(prefix_at(a.Ps, a.T, a.pbase, a.x, i + L),
+                 mul61(prefix_at(a.Ps, a.T, a.pbase, a.x, i), xL));
+  return sub61(a.P[i + L], mul61(a.P[i], xL));
+}
+__device__ __forceinline__ uint64_t win61_any(const PhaseArgs& a, uint64_t i, uint64_t L,
+                                              uint64_t xL) {
+  return a.P ? win61<false>(a, i, L, xL) : win61<true>(a, i, L, xL);
+}
+
 // ---------------------------------------------------------------- keys (a3, a6)
 
 // The key at st (at least 8 bytes long) in the byte scan's prefix filter.
@@ -89,7 +103,7 @@ __global__ void k_keys(PhaseArgs a) {
       }
     }
     const uint64_t xp = (L == a.Lmain) ? a.xLmain : pow61(a.x, L);
-    const uint64_t fp = finish_fp(window_fp(a.P, st, L, xp), a.tx.tsalt[t], a.fpmask);
+    const uint64_t fp = finish_fp(win61_any(a, st, L, xp), a.tx.tsalt[t], a.fpmask);
     a.k.fp[j] = fp;
     a.k.len[j] = L;
     a.odd.nkeys[t] = 1;
@@ -472,11 +486,12 @@ constexpr uint64_t kQPosMask = (1ull << kQPosBits) - 1;
 //
 // Two 1024-thread workgroups per CU need 8 waves per SIMD: the register budget
 // (SGPRs included) is held to that.
-template <int MODE, bool ODD, bool SALT, bool PRE>
+template <int MODE, bool ODD, bool SALT, bool PRE, bool LEAN>
 __global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(8)))
 void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   constexpr bool FILTER = MODE != 0;
   static_assert(!PRE || MODE == 1, "the 32-bit hash feeds the queued filter only");
+  static_assert(!LEAN || MODE == 1, "sampled prefixes serve queued candidates only");
   extern __shared__ uint64_t s_lds[];
   const uint32_t fbits = a.filt_bits;
   const bool two = a.filt_two != 0;
@@ -507,7 +522,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   const uint64_t mask = a.tab.mask;
 
   const auto fp61 = [&](uint64_t i, uint64_t salt) {
-    uint64_t f = sub61(P[i + L], mul61(P[i], xL));
+    uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
     if (SALT) f = add61(f, salt);
     return f & fmask;
   };
@@ -658,7 +673,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
       if (ODD && live && oL && i + oL <= re && i < opos) {
         const uint32_t ho = H[i + oL] - H[i] * ox + (SALT ? (uint32_t)salt : 0u);
         if (ho == oh) {
-          uint64_t g = sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+          uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
           if (SALT) g = add61(g, salt);
           if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
             atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
@@ -692,28 +707,36 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
   // the keys filled the filter from the hash kind that pre32 names
   if (a.pre32 && mode != 1) return hipErrorInvalidValue;
   const bool pre = a.pre32 != 0;
-#define BT_PROBE_LAUNCH(M, O, S, Q)                                                      \
+#define BT_PROBE_LAUNCH(M, O, S, Q, LN)                                                  \
   do {                                                                                   \
     if (lds > 65536) {                                                                   \
-      const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_probe_scan<M, O, S, Q>), lds); \
+      const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_probe_scan<M, O, S, Q, LN>), lds); \
       if (e != hipSuccess) return e;                                                     \
     }                                                                                    \
-    k_probe_scan<M, O, S, Q><<<grid, kProbeThreads, lds, s>>>(a, woff);                  \
+    k_probe_scan<M, O, S, Q, LN><<<grid, kProbeThreads, lds, s>>>(a, woff);              \
   } while (0)
-#define BT_PROBE_SALT(M, O, Q) \
-  if (has_salt) BT_PROBE_LAUNCH(M, O, true, Q); else BT_PROBE_LAUNCH(M, O, false, Q);
+#define BT_PROBE_SALT(M, O, Q, LN) \
+  if (has_salt) BT_PROBE_LAUNCH(M, O, true, Q, LN); else BT_PROBE_LAUNCH(M, O, false, Q, LN);
+  const bool lean = a.P == nullptr;
+  if (lean && mode != 1) return hipErrorInvalidValue;  // sampled prefixes need the queue
   if (mode == 1) {
     if (!pre) return hipErrorInvalidValue;  // queued scans always pre-filter
-    if (has_odd) {
-      BT_PROBE_SALT(1, true, true)
+    if (lean) {
+      if (has_odd) {
+        BT_PROBE_SALT(1, true, true, true)
+      } else {
+        BT_PROBE_SALT(1, false, true, true)
+      }
+    } else if (has_odd) {
+      BT_PROBE_SALT(1, true, true, false)
     } else {
-      BT_PROBE_SALT(1, false, true)
+      BT_PROBE_SALT(1, false, true, false)
     }
   } else if (mode == 2) {
     if (has_odd) {
-      BT_PROBE_SALT(2, true, false)
+      BT_PROBE_SALT(2, true, false, false)
     } else {
-      BT_PROBE_SALT(2, false, false)
+      BT_PROBE_SALT(2, false, false, false)
     }
   } else {
     return hipErrorInvalidValue;  // every scan filters (mode 1 or 2)
@@ -744,7 +767,7 @@ constexpr int kByteK = 16;  // windows per lane
 // when the main-length window does not fit its run.
 constexpr uint64_t kByteTextMask = (1ull << 23) - 1;
 
-template <bool ODD, bool SALT>
+template <bool ODD, bool SALT, bool LEAN>
 __global__ __launch_bounds__(kByteThreads) __attribute__((amdgpu_waves_per_eu(8)))
 void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   extern __shared__ uint64_t s_lds[];
@@ -783,14 +806,14 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     const uint32_t t = (uint32_t)((e >> kQPosBits) & kByteTextMask);  // bit 63 is the fit bit
     const uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
     if (!(e >> 63)) {
-      uint64_t f = sub61(P[i + L], mul61(P[i], xL));
+      uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
       if (SALT) f = add61(f, salt);
       probe(slots, tags, mask, f & fmask, i);
     }
     if (ODD) {
       const uint64_t oL = a.odd.L[t];
       if (oL && i + oL <= a.tx.tend[t] && i < a.odd.pos[t]) {
-        uint64_t g = sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+        uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
         if (SALT) g = add61(g, salt);
         if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
           atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
@@ -922,19 +945,28 @@ hipError_t launch_byte_scan(const PhaseArgs& a, const uint64_t* woff, bool has_o
   const unsigned grid = grid_for(waves * 64, kByteThreads, 512);
   // filter up to 64 KiB + queues 16 KiB: two 1024-thread workgroups per CU
   const size_t lds = ((size_t)1 << (a.bfilt_bits - 3)) + (size_t)(kByteThreads / 64) * kQueue * 8;
-#define BT_BYTE_LAUNCH(O, S)                                                               \
+#define BT_BYTE_LAUNCH(O, S, LN)                                                           \
   do {                                                                                     \
     if (lds > 65536) {                                                                     \
-      const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_byte_scan<O, S>), lds); \
+      const hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_byte_scan<O, S, LN>), lds); \
       if (e != hipSuccess) return e;                                                       \
     }                                                                                      \
-    k_byte_scan<O, S><<<grid, kByteThreads, lds, s>>>(a, woff);                            \
+    k_byte_scan<O, S, LN><<<grid, kByteThreads, lds, s>>>(a, woff);                        \
   } while (0)
-  if (has_odd) {
-    if (has_salt) BT_BYTE_LAUNCH(true, true); else BT_BYTE_LAUNCH(true, false);
+#define BT_BYTE_SALT(O, LN) \
+  if (has_salt) BT_BYTE_LAUNCH(O, true, LN); else BT_BYTE_LAUNCH(O, false, LN);
+  if (a.P == nullptr) {
+    if (has_odd) {
+      BT_BYTE_SALT(true, true)
+    } else {
+      BT_BYTE_SALT(false, true)
+    }
+  } else if (has_odd) {
+    BT_BYTE_SALT(true, false)
   } else {
-    if (has_salt) BT_BYTE_LAUNCH(false, true); else BT_BYTE_LAUNCH(false, false);
+    BT_BYTE_SALT(false, false)
   }
+#undef BT_BYTE_SALT
 #undef BT_BYTE_LAUNCH
   return hipGetLastError();
 }
@@ -1125,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_retry(PhaseArgs a, VerifyBufs v) {
     bool done = false;
     for (uint64_t p0 = lb; p0 <= pos && !done; p0 += 64) {
       const uint64_t p = p0 + lane;
-      const bool m = p <= pos && finish_fp(window_fp(a.P, p, L, xp), salt, a.fpmask) == fpk;
+      const bool m = p <= pos && finish_fp(win61_any(a, p, L, xp), salt, a.fpmask) == fpk;
       uint64_t bal = __ballot(m);
       while (bal) {
         const uint64_t q = p0 + (uint64_t)(__ffsll((unsigned long long)bal) - 1);

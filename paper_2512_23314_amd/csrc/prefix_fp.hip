@@ -19,7 +19,10 @@
 //   4. row by row, each thread re-runs its four chains from its prefix and
 //      stages the 16 outputs in LDS so that the global stores are contiguous.
 // Tile order comes from an atomic counter, so every tile a workgroup waits on
-// was taken by a workgroup that started earlier.  Returning atomics on one
+// was taken by a workgroup that started earlier.  The sampled form (SAMPLED)
+// stores every 16th value only, P[16 q] for 16 q <= n: each thread's value
+// before its 16 bytes, plus P[n] when n is a multiple of 16; any other value is
+// 15 Horner steps or fewer from its sample.  Returning atomics on one
 // address serialize (about 10 ns apart), which is why a tile spans four rows:
 // one counter update per 16 KiB.
 #include "common.hpp"
@@ -56,7 +59,7 @@ struct Mod32 {
   }
 };
 
-template <class A>
+template <class A, bool SAMPLED>
 __global__ __launch_bounds__(kPfThreads) void k_prefix(const uint8_t* __restrict__ T, uint64_t n,
                                                        typename A::V* __restrict__ P,
                                                        const typename A::Pow* __restrict__ pw,
@@ -100,6 +103,7 @@ __global__ __launch_bounds__(kPfThreads) void k_prefix(const uint8_t* __restrict
   //    g[r][c] = the first c chains joined (g[r][0] = 0)
   V g[kPfRows][4];
   V E[kPfRows];
+  V hrow[kPfRows];  // the thread's 16-byte fold per row
 #pragma unroll
   for (int r = 0; r < kPfRows; ++r) {
     V hc[4];
@@ -115,6 +119,7 @@ __global__ __launch_bounds__(kPfThreads) void k_prefix(const uint8_t* __restrict
     g[r][2] = A::add(A::mul(g[r][1], x4), hc[1]);
     g[r][3] = A::add(A::mul(g[r][2], x4), hc[2]);
     const V h = A::add(A::mul(g[r][3], x4), hc[3]);
+    hrow[r] = h;
 
     // 2. wave inclusive scan: I = sum_{u <= lane} h_u x^(16 (lane - u))
     V I = h;
@@ -179,6 +184,18 @@ __global__ __launch_bounds__(kPfThreads) void k_prefix(const uint8_t* __restrict
   // 4. outputs P[row + 16t + 1 .. row + 16t + 16], row by row
   V xr = 1;  // x^(row r)
   const V excl = s_excl;
+  if (SAMPLED) {
+#pragma unroll
+    for (int r = 0; r < kPfRows; ++r) {
+      const uint64_t pos = base + r * kPfRow + (uint64_t)t * kPfBytes;
+      const V before_row = A::add(A::mul(excl, xr), rp[r]);
+      const V C = A::add(A::mul(before_row, pw->x16[t]), local[r]);  // P[pos]
+      if (pos <= n) P[pos >> 4] = C;
+      if (pos + kPfBytes == n) P[n >> 4] = A::add(A::mul(C, pw->x16[1]), hrow[r]);
+      xr = A::mul(xr, xrow);
+    }
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < kPfRows; ++r) {
     const uint64_t rowbase = base + r * kPfRow;
@@ -212,7 +229,7 @@ __global__ void k_zero(V* p, uint64_t n) {
     p[i] = 0;
 }
 
-template <class A>
+template <class A, bool SAMPLED = false>
 static hipError_t launch_prefix(const uint8_t* T, uint64_t n, typename A::V* P,
                                 const typename A::Pow* pw, uint64_t* status, uint32_t* ctr,
                                 hipStream_t s) {
@@ -226,13 +243,18 @@ static hipError_t launch_prefix(const uint8_t* T, uint64_t n, typename A::V* P,
   const unsigned zb = (unsigned)((tiles + 255) / 256 < 4096 ? (tiles + 255) / 256 : 4096);
   k_zero<uint64_t><<<zb, 256, 0, s>>>(status, tiles);
   k_zero<uint32_t><<<1, 64, 0, s>>>(ctr, 1);
-  k_prefix<A><<<(unsigned)tiles, kPfThreads, 0, s>>>(T, n, P, pw, status, ctr);
+  k_prefix<A, SAMPLED><<<(unsigned)tiles, kPfThreads, 0, s>>>(T, n, P, pw, status, ctr);
   return hipGetLastError();
 }
 
 hipError_t launch_prefix_fp(const uint8_t* T, uint64_t n, uint64_t* P, const PfPow* pw,
                             uint64_t* status, uint32_t* ctr, hipStream_t s) {
   return launch_prefix<Mod61>(T, n, P, pw, status, ctr, s);
+}
+
+hipError_t launch_prefix_fp_sampled(const uint8_t* T, uint64_t n, uint64_t* Ps, const PfPow* pw,
+                                    uint64_t* status, uint32_t* ctr, hipStream_t s) {
+  return launch_prefix<Mod61, true>(T, n, Ps, pw, status, ctr, s);
 }
 
 hipError_t launch_prefix_h32(const uint8_t* T, uint64_t n, uint32_t* H, const PfPow32* pw,
