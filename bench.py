@@ -15,7 +15,8 @@ HIP-event time on the library's stream.  The cpu_baseline object times the CPU o
 prefix of the same text.  The pruned_build object times the same build with the
 optional pruning phase (--prune times that as the main step instead); the
 lean_build object times it with sampled prefix fingerprints (--lean) and gives
-both builds' peak device memory.
+both builds' peak device memory; the sort_phase_build object times it with the
+sort-based phases of Section 5.1 in place of the hash-table scan.
 """
 import argparse
 import hashlib
@@ -409,6 +410,31 @@ def lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step, steps=3):
             "peak_bytes_per_text_byte_dense": round(dense / n, 3)}
 
 
+def sort_leg(ctx, d, n, sigma, tau, leaf, s_hint, hash_ms, steps=2):
+    """The same build with the sort-based phases of Section 5.1 in place of the
+    hash-table scan (same tree): rate, and its sort time per build."""
+    import torch
+    import paper_2512_23314_amd as bt
+
+    def one():
+        ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint,
+                  debug_flags=bt.BT_DBG_SORT_PHASES).free()
+    one()
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    ctx.profile(False)
+    st = ctx.kernel_stats("sort_phase")
+    return {"value": round(n / 1e6 / (ms / 1e3), 2), "unit": "MB/s", "ms_per_step": round(ms, 3),
+            "steps": steps, "sort_ms_per_step": round(st["ms"] / steps, 3),
+            "slowdown_vs_hashing": round(ms / hash_ms, 2)}
+
+
 def cpu_baseline(T, sigma, tau, leaf, s_hint, sample_bytes):
     import oracle
     S = T[:sample_bytes]
@@ -435,6 +461,8 @@ def main():
                     help="time memory-lean builds (BT_LEAN: sampled prefix fingerprints)")
     ap.add_argument("--no-lean-leg", action="store_true",
                     help="skip the short memory-lean measurement beside the main line")
+    ap.add_argument("--no-sort-leg", action="store_true",
+                    help="skip the build with the sort-based phases of Section 5.1")
     ap.add_argument("--cpu-sample-mib", type=int, default=8)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
@@ -534,6 +562,10 @@ def main():
     if not args.lean and not args.no_lean_leg:
         leanr = lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
         log("lean build: %s" % leanr)
+    sortr = None
+    if not args.no_sort_leg:
+        sortr = sort_leg(ctx, d, n, sigma, tau, leaf, s_hint, ms)
+        log("sort-phase build: %s" % sortr)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(T, sigma, tau, leaf, s_hint, args.cpu_sample_mib << 20)
@@ -559,6 +591,8 @@ def main():
         out["pruned_build"] = pruned
     if leanr is not None:
         out["lean_build"] = leanr
+    if sortr is not None:
+        out["sort_phase_build"] = sortr
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -60,6 +60,13 @@ extern "C" {
  * (a filter on each window's first eight bytes, used for phases with few keys)
  * would be taken; the output must not change. */
 #define BT_DBG_NO_BYTE_SCAN 4u
+/* Find each phase's leftmost occurrences with the sort-based algorithm of
+ * Section 5.1 in place of the hash-table scan: every scanned window's and every
+ * key's fingerprint sorted together, the first position of each fingerprint
+ * broadcast by a scan.  For comparison with hashing; the output must not
+ * change.  Needs fewer than 2^31 windows per phase (else BT_E_INVAL) and about
+ * 40 bytes of device memory per window. */
+#define BT_DBG_SORT_PHASES 8u
 
 /* ---- build flags (bt_params.flags) ---- */
 /* Also build the counters that bt_rank and bt_select need: per block and per

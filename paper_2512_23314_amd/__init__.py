@@ -18,6 +18,7 @@ BT_OK, BT_E_INVAL, BT_E_NOMEM, BT_E_DEVICE, BT_E_INTERNAL = 0, -1, -2, -3, -4
 BT_DBG_WEAK_HASH = 1
 BT_DBG_NO_QUEUE = 2
 BT_DBG_NO_BYTE_SCAN = 4
+BT_DBG_SORT_PHASES = 8
 BT_WITH_RANK_SELECT = 1
 BT_PRUNE = 2
 BT_LEAN = 4

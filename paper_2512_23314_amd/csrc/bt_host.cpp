@@ -1037,7 +1037,33 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         HIPCHK(ctx, hipMemcpyAsync(wst, swoff + as.lv.R, 8, hipMemcpyDeviceToDevice, s));
       // algorithmic bytes per window: the two prefix values it reads (8-byte
       // 61-bit prefixes, or 4-byte 32-bit hashes when pre-filtering)
-      if (byte_scan) {
+      if (prm.debug_flags & BT_DBG_SORT_PHASES) {
+        // Section 5.1: sort (fingerprint, position) of every window and key
+        std::vector<uint64_t> wv;
+        read_words(ctx, {{swoff + as.lv.R, 1}}, wv);
+        const uint64_t W = wv[0], n2 = W + c;
+        if (n2 >= (1ull << 31)) {
+          ctx->err = "sort-based phase: 2^31 windows or more";
+          throw Fail{BT_E_INVAL};
+        }
+        const uint64_t none = (a.fpmask == ~0ull) ? (1ull << 61) : a.fpmask + 1;
+        int end_bit = 1;
+        while (end_bit < 64 && (1ull << end_bit) <= none) ++end_bit;
+        Buf<uint64_t> f1 = alloc<uint64_t>(ctx, n2), p1 = alloc<uint64_t>(ctx, n2),
+                      f2 = alloc<uint64_t>(ctx, n2), p2 = alloc<uint64_t>(ctx, n2),
+                      gx = alloc<uint64_t>(ctx, n2 + 1), gf = alloc<uint64_t>(ctx, n2);
+        size_t tb = 0;
+        HIPCHK(ctx, sort_pairs_u64(nullptr, tb, f1.p, f2.p, p1.p, p2.p, n2, end_bit, s));
+        Buf<uint8_t> tmp = alloc<uint8_t>(ctx, tb);
+        timed(ctx, "sort_phase", 0, 0, nullptr, 0, [&] {
+          hipError_t e = launch_sort_emit(as, swoff, W, none, f1.p, p1.p, s);
+          if (e == hipSuccess) e = sort_pairs_u64(tmp.p, tb, f1.p, f2.p, p1.p, p2.p, n2, end_bit, s);
+          if (e == hipSuccess) e = launch_sort_heads(f2.p, n2, gx.p, s);
+          if (e != hipSuccess) return e;
+          scan(gx.p, n2);  // group numbers
+          return launch_sort_groups(a, f2.p, p2.p, gx.p, n2, gf.p, s);
+        });
+      } else if (byte_scan) {
         // algorithmic bytes per window: the one text byte each window start adds
         timed(ctx, "byte_scan", 0, 0, wst, 1.0, [&] {
           return launch_byte_scan(as, swoff, has_odd, has_salt, c * b, s);

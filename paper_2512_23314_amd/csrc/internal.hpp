@@ -205,6 +205,20 @@ hipError_t launch_block_seg_counts(const PhaseArgs& a, const uint8_t* pf, uint64
 hipError_t launch_block_segments(const PhaseArgs& a, const uint64_t* wcs, const uint64_t* hs,
                                  uint64_t* ws, uint64_t* sre, uint32_t* stext, uint64_t* woff,
                                  hipStream_t s);
+// Sort-based phases (sort_phase.hip): windows and keys as (fingerprint,
+// position or key block), sorted by fingerprint; none marks entries that match
+// nothing (above every fingerprint).
+hipError_t launch_sort_emit(const PhaseArgs& a, const uint64_t* woff, uint64_t W, uint64_t none,
+                            uint64_t* fpv, uint64_t* posv, hipStream_t s);
+// hipCUB's stable radix sort of n pairs by the low end_bit key bits; with tmp
+// null it only sets tmp_bytes.
+hipError_t sort_pairs_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uint64_t* kout,
+                          const uint64_t* vin, uint64_t* vout, uint64_t n, int end_bit,
+                          hipStream_t s);
+hipError_t launch_sort_heads(const uint64_t* fp, uint64_t n, uint64_t* h, hipStream_t s);
+// gx: exclusive scan of the head flags; gfirst: n words
+hipError_t launch_sort_groups(const PhaseArgs& a, const uint64_t* fp, const uint64_t* pos,
+                              const uint64_t* gx, uint64_t n, uint64_t* gfirst, hipStream_t s);
 // The byte scan: every window's first eight text bytes against the keys'
 // prefix filter; windows that pass form their fingerprint and probe the table.
 hipError_t launch_byte_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd, bool has_salt,
