@@ -578,8 +578,17 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
       }
     };
     if (ODD && w0 < W) load_odd();
+    // the short key's 61-bit fingerprint at i, against the key's (text t)
+    const auto odd61 = [&](uint64_t i, uint64_t sl) {
+      uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+      if (SALT) g = add61(g, sl);
+      if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
+        atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
+    };
 
-    if (!ODD) {
+    // (the short final key's windows, shorter than the main ones, fit wherever
+    // a main window does; the unqueued scan tests it on the per-step path)
+    if (!ODD || PRE) {
       const uint64_t wl = w0 + 64ull * (kScanK - 1);
       const bool lane_ok = wl < wn && rs + (wl - wo) + L <= re;
       if (__ballot(lane_ok) == ~0ull) {
@@ -593,6 +602,21 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
             for (int k = 0; k < 8; ++k) {
               const uint64_t i = i0 + 64ull * (k0 + k);
               hv[k] = H[i + L] - H[i] * x32L + s32;
+            }
+            if (ODD && oL) {
+              // the short key's 32-bit hashes (H[i] again, from L1); the rare
+              // matches form their 61-bit fingerprints one at a time
+              uint32_t om = 0;
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const uint64_t i = i0 + 64ull * (k0 + k);
+                if (i < opos && H[i + oL] - H[i] * ox + s32 == oh) om |= 1u << k;
+              }
+              while (om) {
+                const int k = __builtin_ctz(om);
+                om &= om - 1;
+                odd61(i0 + 64ull * (k0 + k), salt);
+              }
             }
             bool ok[8];
 #pragma unroll
@@ -659,12 +683,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
       // the 61-bit fingerprint only where that matches
       if (ODD && live && oL && i + oL <= re && i < opos) {
         const uint32_t ho = H[i + oL] - H[i] * ox + (SALT ? (uint32_t)salt : 0u);
-        if (ho == oh) {
-          uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
-          if (SALT) g = add61(g, salt);
-          if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
-            atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
-        }
+        if (ho == oh) odd61(i, salt);
       }
     }
   }
