@@ -537,7 +537,7 @@ def main():
     ms = dt / args.steps * 1e3
     value = n / 1e6 / (ms / 1e3)
 
-    stats = {k: ctx.kernel_stats(k) for k in ("probe_scan", "byte_scan", "prefix_fp", "prefix_h32", "verify")}
+    stats = {k: ctx.kernel_stats(k) for k in ("probe_scan", "byte_scan", "prefix_fp", "verify")}
     for k, s in stats.items():
         if s["launches"]:
             log("%-10s launches %5d  total %8.3f ms  avg %.4f ms  units %.3e  GB/s %.1f" % (
@@ -582,7 +582,8 @@ def main():
     }
     # per-kernel figures of the timed steps (HIP events on the library stream;
     # algorithmic bytes as in the roofline: 8 or 16 B per probe-scan window,
-    # 1 B per byte-scan window, 9 B per text byte for the prefix scan)
+    # 1 B per byte-scan window, 13 B per text byte for the prefix scan: 1 read,
+    # 8 + 4 written)
     out["kernels"] = {k: {"launches_per_step": s["launches"] // max(args.steps, 1),
                           "ms_per_step": round(s["ms"] / max(args.steps, 1), 4),
                           "algorithmic_GBps": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1)}

@@ -144,8 +144,9 @@ BT_API int bt_ctx_trim(bt_ctx* ctx);
  * each launch of the named kernel while enabled.  `bytes` accumulates the
  * kernel's algorithmic traffic (the bytes the method must move; defined with
  * each kernel in the design notes) and `units` its work units (windows for the
- * probe scan, text bytes for the prefix scan).  Names: "prefix_fp",
- * "prefix_h32", "probe_scan", "byte_scan", "verify". */
+ * probe scan, text bytes for the prefix scan).  Names: "prefix_fp" (the
+ * prefix scan: fingerprints and, in builds, the 32-bit hashes), "probe_scan",
+ * "byte_scan", "verify", "sort_phase". */
 BT_API int bt_ctx_profile(bt_ctx* ctx, int enable);
 BT_API int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches,
                         double* total_ms, double* bytes, double* units);
@@ -165,6 +166,18 @@ BT_API int bt_ctx_reset_peak(bt_ctx* ctx);
  * x must be in [1, 2^61-1).  Errors: BT_E_INVAL. */
 BT_API int bt_prefix_fingerprints(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
                            uint64_t* d_P);
+
+/* ---- both prefix arrays of a build, in one pass ----
+ * The fingerprints of bt_prefix_fingerprints (base x) and the 32-bit
+ * pre-filter hashes of the probe scan (a bit filter on these prunes windows
+ * before any fingerprint is formed, Section 4.1 step a4):
+ *   d_H[0] = 0,  d_H[i+1] = (d_H[i] * x32 + d_text[i]) mod 2^32.
+ * sampled = 0: d_P holds n+1 uint64 as in bt_prefix_fingerprints;
+ * sampled = 1: d_P[q] = P[16 q] for 16 q <= n (n/16 + 1 uint64), the form a
+ * memory-lean build keeps.  d_H: n+1 uint32.  All device, caller-owned.
+ * x must be in [1, 2^61-1); any x32.  Errors: BT_E_INVAL. */
+BT_API int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
+                          uint32_t x32, int sampled, uint64_t* d_P, uint32_t* d_H);
 
 /* ---- builds ----
  * Build the block tree of the n bytes at d_text (device, caller-owned).

@@ -57,6 +57,7 @@ SIGNATURES = {
     "bt_ctx_memory": (_i32, [_vp, _pu64, _pu64, _pu64]),
     "bt_ctx_reset_peak": (_i32, [_vp]),
     "bt_prefix_fingerprints": (_i32, [_vp, _vp, _u64, _u64, _vp]),
+    "bt_prefix_scan": (_i32, [_vp, _vp, _u64, _u64, _u32, _i32, _vp, _vp]),
     "bt_build": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, ctypes.POINTER(_vp)]),
     "bt_build_ex": (_i32, [_vp, _vp, _u64, _u32, ctypes.POINTER(bt_params), ctypes.POINTER(_vp)]),
     "bt_build_batch": (_i32, [_vp, _vp, _vp, _u32, _u32, ctypes.POINTER(bt_params), _vp]),
@@ -169,6 +170,17 @@ class Context:
             out = torch.empty(n + 1, dtype=torch.uint64, device=text.device)
         self._check(lib().bt_prefix_fingerprints(self.h, _ptr(text), n, x, _ptr(out)))
         return out
+
+    def prefix_scan(self, text, x, x32, sampled=False):
+        """Fingerprints (dense, or P[16 q] when sampled) and 32-bit hashes of one
+        pass; returns (P, H): uint64, and int32 holding the uint32 values."""
+        torch = _torch()
+        n = text.numel()
+        P = torch.empty(n // 16 + 1 if sampled else n + 1, dtype=torch.uint64, device=text.device)
+        H = torch.empty(n + 1, dtype=torch.int32, device=text.device)  # uint32 bits
+        self._check(lib().bt_prefix_scan(self.h, _ptr(text), n, x, x32, 1 if sampled else 0,
+                                         _ptr(P), _ptr(H)))
+        return P, H
 
     # ---- builds
     @staticmethod

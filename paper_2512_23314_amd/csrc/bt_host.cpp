@@ -191,7 +191,7 @@ struct bt_ctx {
   std::vector<hipEvent_t> ev_free;
   uint64_t* h_small = nullptr;  // pinned host words for count read-back
   size_t h_small_words = 0;
-  PfPow* h_pw = nullptr;        // pinned staging for the power table
+  PfTab* h_tab = nullptr;       // pinned staging for the prefix-scan tables
   // pinned staging of host-to-device uploads: a bump region that is reused
   // only after the stream has been synchronized (every earlier upload is done)
   uint64_t* h_stage = nullptr;
@@ -321,25 +321,43 @@ uint32_t host_pow32(uint32_t x, uint64_t e) {
   return r;
 }
 
-void fill_pow32(PfPow32* pw, uint32_t x) {
-  pw->x1[0] = 1;
-  for (int k = 1; k <= 16; ++k) pw->x1[k] = pw->x1[k - 1] * x;
-  pw->x16[0] = 1;
-  for (int k = 1; k <= 256; ++k) pw->x16[k] = pw->x16[k - 1] * pw->x1[16];
-  const uint32_t xt = host_pow32(x, kPfTile);
-  pw->xt[0] = 1;
-  for (int k = 1; k <= 64; ++k) pw->xt[k] = pw->xt[k - 1] * xt;
-}
-
-void fill_pow(PfPow* pw, uint64_t x) {
-  pw->x1[0] = 1;
-  for (int k = 1; k <= 16; ++k) pw->x1[k] = host_mul61(pw->x1[k - 1], x);
-  const uint64_t x16 = pw->x1[16];
-  pw->x16[0] = 1;
-  for (int k = 1; k <= 256; ++k) pw->x16[k] = host_mul61(pw->x16[k - 1], x16);
+// Tables of the prefix scan: g[j-1][b] = b x^j (j = 1..7), t[k] = x^(64 k),
+// xt[k] = x^(tile k), c[c] = x^(16 c), for both bases.
+void fill_tab(PfTab* tb, uint64_t x, uint32_t x32) {
+  uint64_t xj = 1;
+  uint32_t yj = 1;
+  for (int j = 1; j <= 7; ++j) {
+    xj = host_mul61(xj, x);
+    yj *= x32;
+    for (int b = 0; b < 256; ++b) {
+      tb->g61[j - 1][b] = host_mul61(xj, (uint64_t)b);
+      tb->g32[j - 1][b] = yj * (uint32_t)b;
+    }
+  }
+  tb->x1_61 = x;
+  tb->x8_61 = host_mul61(xj, x);
+  tb->x1_32 = x32;
+  tb->x8_32 = yj * x32;
+  const uint64_t x64 = host_pow61(x, 64);
+  const uint32_t y64 = host_pow32(x32, 64);
+  tb->t61[0] = 1;
+  tb->t32[0] = 1;
+  for (int k = 1; k <= kPfThreads; ++k) {
+    tb->t61[k] = host_mul61(tb->t61[k - 1], x64);
+    tb->t32[k] = tb->t32[k - 1] * y64;
+  }
   const uint64_t xt = host_pow61(x, kPfTile);
-  pw->xt[0] = 1;
-  for (int k = 1; k <= 64; ++k) pw->xt[k] = host_mul61(pw->xt[k - 1], xt);
+  const uint32_t yt = host_pow32(x32, kPfTile);
+  tb->xt61[0] = 1;
+  tb->xt32[0] = 1;
+  for (int k = 1; k <= 64; ++k) {
+    tb->xt61[k] = host_mul61(tb->xt61[k - 1], xt);
+    tb->xt32[k] = tb->xt32[k - 1] * yt;
+  }
+  for (int c = 0; c < 4; ++c) {
+    tb->c61[c] = host_pow61(x, 16 * c);
+    tb->c32[c] = host_pow32(x32, 16 * c);
+  }
 }
 
 hipEvent_t get_event(bt_ctx* ctx) {
@@ -564,17 +582,39 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   upload(ctx, d_tx.p, h_tx.data(), 3 * (uint64_t)T);
   TextsDev tx{T, d_tx.p, d_tx.p + T, d_tx.p + 2 * T};
 
+  // ---- which byte values occur (read back after the prefix scan is queued)
+  Buf<uint64_t> d_seen = alloc<uint64_t>(ctx, 4);
+  HIPCHK(ctx, launch_fill_u64(d_seen.p, 0, 4, s));
+  HIPCHK(ctx, launch_byte_presence(d_base + o0, N, reinterpret_cast<uint32_t*>(d_seen.p), s));
+
+  // ---- step a2: prefix fingerprints of the concatenation, once, and in the
+  // same pass the 32-bit pre-filter hashes (same indexing).  A memory-lean
+  // build keeps one fingerprint in 16 (0.5 instead of 8 bytes per text byte)
+  // and forms the others where a fingerprint is needed: keys, queued
+  // candidates and retries.  Only the queued scan takes candidates that way.
+  const bool lean = (prm.flags & BT_LEAN) && T <= (1u << 24) && offs[T] < (1ull << 40) &&
+                    !(prm.debug_flags & BT_DBG_NO_QUEUE);
+  const uint32_t x32 = base32_from_seed(prm.hash_seed);
+  Buf<uint64_t> d_P = alloc<uint64_t>(ctx, lean ? N / 16 + 1 : N + 1);
+  Buf<uint32_t> d_H = alloc<uint32_t>(ctx, N + 1);
+  Buf<PfTab> d_tab = alloc<PfTab>(ctx, 1);
+  fill_tab(ctx->h_tab, x, x32);
+  HIPCHK(ctx, hipMemcpyAsync(d_tab.p, ctx->h_tab, sizeof(PfTab), hipMemcpyHostToDevice, s));
+  Buf<uint64_t> d_status = alloc<uint64_t>(ctx, prefix_status_words(N));
+  timed(ctx, "prefix_fp", (double)N + 8.0 * (double)(lean ? N / 16 + 1 : N + 1) + 4.0 * (double)(N + 1),
+        (double)N, nullptr, 0,
+        [&] { return launch_prefix(d_base + o0, N, d_P.p, lean, d_H.p, d_tab.p, d_status.p, s); });
+  // P[i] belongs to text position i (never read below o0); null when sampled
+  const uint64_t* P = lean ? nullptr : d_P.p - o0;
+
   // ---- distinct byte values must not exceed sigma; dense symbols for rank/select
-  Buf<uint64_t> d_hist = alloc<uint64_t>(ctx, 256);
-  HIPCHK(ctx, launch_fill_u64(d_hist.p, 0, 256, s));
-  HIPCHK(ctx, launch_histogram(d_base + o0, N, d_hist.p, s));
-  std::vector<uint64_t> hist;
-  read_words(ctx, {{d_hist.p, 256}}, hist);
+  std::vector<uint64_t> seen;
+  read_words(ctx, {{d_seen.p, 4}}, seen);
   uint32_t S = 0;
   std::vector<int16_t> h_sym(256, -1);
   std::vector<uint8_t> h_byte_of;
   for (int ch = 0; ch < 256; ++ch)
-    if (hist[ch]) {
+    if ((seen[ch >> 6] >> (ch & 63)) & 1) {
       h_sym[ch] = (int16_t)S++;
       h_byte_of.push_back((uint8_t)ch);
     }
@@ -589,44 +629,6 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         ctx->err = "rank/select support needs texts shorter than 2^32 bytes";
         return BT_E_INVAL;
       }
-
-  // ---- step a2: prefix fingerprints of the concatenation, once.  A
-  // memory-lean build keeps one value in 16 (0.5 instead of 8 bytes per text
-  // byte) and forms the others where a fingerprint is needed: keys, queued
-  // candidates and retries.  Only the queued scan takes candidates that way.
-  const bool lean = (prm.flags & BT_LEAN) && T <= (1u << 24) && offs[T] < (1ull << 40) &&
-                    !(prm.debug_flags & BT_DBG_NO_QUEUE);
-  Buf<uint64_t> d_P = alloc<uint64_t>(ctx, lean ? N / 16 + 1 : N + 1);
-  Buf<PfPow> d_pw = alloc<PfPow>(ctx, 1);
-  fill_pow(ctx->h_pw, x);
-  HIPCHK(ctx, hipMemcpyAsync(d_pw.p, ctx->h_pw, sizeof(PfPow), hipMemcpyHostToDevice, s));
-  const uint64_t tiles = (N + kPfTile - 1) / kPfTile;
-  Buf<uint64_t> d_status = alloc<uint64_t>(ctx, tiles + 1);
-  Buf<uint64_t> d_ctr = alloc<uint64_t>(ctx, 1);
-  timed(ctx, "prefix_fp", (double)N + 8.0 * (double)(lean ? N / 16 + 1 : N + 1), (double)N, nullptr, 0,
-        [&] {
-          return lean ? launch_prefix_fp_sampled(d_base + o0, N, d_P.p, d_pw.p, d_status.p,
-                                                 reinterpret_cast<uint32_t*>(d_ctr.p), s)
-                      : launch_prefix_fp(d_base + o0, N, d_P.p, d_pw.p, d_status.p,
-                                         reinterpret_cast<uint32_t*>(d_ctr.p), s);
-        });
-  // P[i] belongs to text position i (never read below o0); null when sampled
-  const uint64_t* P = lean ? nullptr : d_P.p - o0;
-
-  // 32-bit pre-filter hashes of the concatenation (same indexing as P)
-  const uint32_t x32 = base32_from_seed(prm.hash_seed);
-  Buf<uint32_t> d_H = alloc<uint32_t>(ctx, N + 1);
-  Buf<PfPow32> d_pw32 = alloc<PfPow32>(ctx, 1);
-  {
-    PfPow32 hp;
-    fill_pow32(&hp, x32);
-    upload(ctx, reinterpret_cast<uint32_t*>(d_pw32.p), reinterpret_cast<const uint32_t*>(&hp),
-           sizeof(PfPow32) / 4);
-  }
-  timed(ctx, "prefix_h32", (double)N + 4.0 * (double)(N + 1), (double)N, nullptr, 0, [&] {
-    return launch_prefix_h32(d_base + o0, N, d_H.p, d_pw32.p, d_status.p,
-                             reinterpret_cast<uint32_t*>(d_ctr.p), s);
-  });
   const uint32_t* H32 = d_H.p - o0;
 
   auto store = std::make_shared<Storage>();
@@ -1416,7 +1418,7 @@ int bt_ctx_create(int device, void* hip_stream, bt_ctx** out) {
   c->dev = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->pool = std::make_shared<Pool>(device);
-  if (hipHostMalloc((void**)&c->h_pw, sizeof(PfPow), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->h_tab, sizeof(PfTab), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return BT_E_NOMEM;
   }
@@ -1435,7 +1437,7 @@ void bt_ctx_destroy(bt_ctx* ctx) {
   for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
-  if (ctx->h_pw) (void)hipHostFree(ctx->h_pw);
+  if (ctx->h_tab) (void)hipHostFree(ctx->h_tab);
   ctx->pool->trim();
   delete ctx;
 }
@@ -1498,16 +1500,37 @@ int bt_prefix_fingerprints(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint6
   }
   return guarded(ctx, [&] {
     HIPCHK(ctx, hipSetDevice(ctx->dev));
-    Buf<PfPow> d_pw = alloc<PfPow>(ctx, 1);
-    fill_pow(ctx->h_pw, x);
-    HIPCHK(ctx, hipMemcpyAsync(d_pw.p, ctx->h_pw, sizeof(PfPow), hipMemcpyHostToDevice,
+    Buf<PfTab> d_tab = alloc<PfTab>(ctx, 1);
+    fill_tab(ctx->h_tab, x, 1u);
+    HIPCHK(ctx, hipMemcpyAsync(d_tab.p, ctx->h_tab, sizeof(PfTab), hipMemcpyHostToDevice,
                                ctx->stream));
-    const uint64_t tiles = (n + kPfTile - 1) / kPfTile;
-    Buf<uint64_t> d_status = alloc<uint64_t>(ctx, tiles + 1);
-    Buf<uint64_t> d_ctr = alloc<uint64_t>(ctx, 1);
+    Buf<uint64_t> d_status = alloc<uint64_t>(ctx, prefix_status_words(n));
     timed(ctx, "prefix_fp", (double)n + 8.0 * (double)(n + 1), (double)n, nullptr, 0, [&] {
-      return launch_prefix_fp(d_text, n, d_P, d_pw.p, d_status.p,
-                              reinterpret_cast<uint32_t*>(d_ctr.p), ctx->stream);
+      return launch_prefix(d_text, n, d_P, false, nullptr, d_tab.p, d_status.p, ctx->stream);
+    });
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    collect_events(ctx);
+    return BT_OK;
+  });
+}
+
+int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x, uint32_t x32,
+                   int sampled, uint64_t* d_P, uint32_t* d_H) {
+  if (!ctx) return BT_E_INVAL;
+  if (x == 0 || x >= kP61Host || !d_P || !d_H || (!d_text && n)) {
+    ctx->err = "bt_prefix_scan: need 1 <= x < 2^61-1 and valid pointers";
+    return BT_E_INVAL;
+  }
+  return guarded(ctx, [&] {
+    HIPCHK(ctx, hipSetDevice(ctx->dev));
+    Buf<PfTab> d_tab = alloc<PfTab>(ctx, 1);
+    fill_tab(ctx->h_tab, x, x32);
+    HIPCHK(ctx, hipMemcpyAsync(d_tab.p, ctx->h_tab, sizeof(PfTab), hipMemcpyHostToDevice,
+                               ctx->stream));
+    Buf<uint64_t> d_status = alloc<uint64_t>(ctx, prefix_status_words(n));
+    const double pw = sampled ? 8.0 * (double)(n / 16 + 1) : 8.0 * (double)(n + 1);
+    timed(ctx, "prefix_fp", (double)n + pw + 4.0 * (double)(n + 1), (double)n, nullptr, 0, [&] {
+      return launch_prefix(d_text, n, d_P, sampled != 0, d_H, d_tab.p, d_status.p, ctx->stream);
     });
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     collect_events(ctx);

@@ -9,36 +9,37 @@ namespace bt {
 
 // ---- prefix fingerprints (step a2) ----
 constexpr int kPfThreads = 256;
-constexpr int kPfBytes = 16;                            // bytes per thread per row
-constexpr uint64_t kPfRow = kPfThreads * kPfBytes;      // bytes per row (4 KiB)
-constexpr int kPfRows = 4;                              // rows per tile
-constexpr uint64_t kPfTile = kPfRow * kPfRows;          // bytes per tile (16 KiB)
+constexpr int kPfBytes = 64;                            // consecutive bytes per thread
+constexpr uint64_t kPfTile = kPfThreads * kPfBytes;     // bytes per tile (16 KiB)
 
-// Powers of the base used by the prefix scan, computed on the host
-// (x^(16 * 256) = x^row is x16[256]).
-struct PfPow {
-  uint64_t x1[17];    // x^k,          k = 0..16
-  uint64_t x16[257];  // x^(16 k),     k = 0..256
-  uint64_t xt[65];    // x^(tile k),   k = 0..64
+// Tables of the prefix scan for one pair of bases, computed on the host: x mod
+// 2^61-1 (the fingerprints) and x32 mod 2^32 (the pre-filter hashes).
+struct PfTab {
+  uint64_t g61[7][256];          // b x^j, j = 1..7 (row j - 1), b = 0..255
+  uint64_t t61[kPfThreads + 1];  // x^(64 k), k = 0..256
+  uint64_t xt61[65];             // x^(tile k), k = 0..64
+  uint64_t c61[4];               // x^(16 c), c = 0..3
+  uint64_t x1_61, x8_61;         // x, x^8
+  uint32_t g32[7][256];
+  uint32_t t32[kPfThreads + 1];
+  uint32_t xt32[65];
+  uint32_t c32[4];
+  uint32_t x1_32, x8_32;
 };
 
-// The same powers for the 32-bit prefix hash (arithmetic mod 2^32).
-struct PfPow32 {
-  uint32_t x1[17];
-  uint32_t x16[257];
-  uint32_t xt[65];
-};
+// Status words of the prefix scan's look-back for n text bytes: two arrays of
+// tiles + 1 words and the tile counter.  The launch wrapper zeroes them.
+inline uint64_t prefix_status_words(uint64_t n) {
+  return 2 * ((n + kPfTile - 1) / kPfTile + 1) + 1;
+}
 
-// status: ceil(n / tile) words, zeroed by the wrapper; ctr: one word.
-hipError_t launch_prefix_fp(const uint8_t* T, uint64_t n, uint64_t* P, const PfPow* pw,
-                            uint64_t* status, uint32_t* ctr, hipStream_t s);
-// The same, stored sampled: Ps[q] = P[16 q] for 16 q <= n (n / 16 + 1 words).
-hipError_t launch_prefix_fp_sampled(const uint8_t* T, uint64_t n, uint64_t* Ps, const PfPow* pw,
-                                    uint64_t* status, uint32_t* ctr, hipStream_t s);
-// 32-bit prefix hashes H[0] = 0, H[i+1] = H[i] * x32 + T[i] (mod 2^32), the
-// cheap pre-filter of the probe scan (n + 1 outputs; status: tiles + 1 words).
-hipError_t launch_prefix_h32(const uint8_t* T, uint64_t n, uint32_t* H, const PfPow32* pw,
-                             uint64_t* status, uint32_t* ctr, hipStream_t s);
+// P[0] = 0, P[i+1] = P[i] x + T[i] (mod 2^61 - 1) for i < n, stored dense
+// (n + 1 words) or, when sampled, as Ps[q] = P[16 q] for 16 q <= n (n / 16 + 1
+// words); and, when H is not null, H[0] = 0, H[i+1] = H[i] x32 + T[i] (mod
+// 2^32), the pre-filter hashes of the probe scan (n + 1 words), from the same
+// pass over the text.  status: prefix_status_words(n) words.
+hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled, uint32_t* H,
+                         const PfTab* tab, uint64_t* status, hipStream_t s);
 
 // ---- level data (device arrays; positions are offsets into the text base) ----
 struct TextsDev {

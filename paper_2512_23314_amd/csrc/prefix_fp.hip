@@ -1,51 +1,79 @@
 // Step (a2): prefix Karp-Rabin fingerprints over the whole text, computed once
 // per build.  P[0] = 0, P[i+1] = P[i] * x + T[i] (mod 2^61 - 1); any window's
 // fingerprint is then P[i+L] - P[i] * x^L (Section 2, phi with r = x).  The
-// same scan, in arithmetic mod 2^32 with another (odd) base, gives the 32-bit
-// pre-filter hashes H of the probe scan.
+// same pass computes, in arithmetic mod 2^32 with another (odd) base, the
+// 32-bit pre-filter hashes H of the probe scan.
 //
 // The recurrence is a prefix operation under the associative combine
 // (h1, len1) o (h2, len2) = (h1 * x^len2 + h2, len1 + len2) (Section 2.2, the
-// all-prefix operation).  One workgroup of 256 threads owns a 16 KiB tile of
-// four 4 KiB rows; in each row a thread owns 16 consecutive bytes:
-//   1. each thread folds its 16 bytes of every row by Horner's rule, as four
-//      independent 4-byte chains joined with x^4 (short dependency chains);
-//   2. per row, a wave64 shuffle scan and a 4-entry LDS pass give every thread
-//      the fingerprint of the row prefix before it; the row aggregates fold
-//      into the tile aggregate;
-//   3. the tile's carry-in comes from a decoupled look-back over the tile
+// all-prefix operation).  Workgroups of 256 threads stay resident and take
+// 16 KiB tiles in order from an atomic counter; in a tile each thread owns 64
+// consecutive bytes.
+//   1. Fold: the thread's bytes in groups of eight; a group's value
+//      sum_k b_k x^(7-k) is seven lookups in LDS tables of b x^j plus one
+//      reduction, and the eight groups join with x^8.  No multiplication per
+//      byte here.
+//   2. A wave64 shuffle scan and a 4-entry LDS pass give each thread the fold
+//      of the tile before it, and the tile aggregate.
+//   3. The tile's carry-in comes from a decoupled look-back over the tile
 //      status words (value plus two flag bits: aggregate ready, inclusive
-//      prefix ready);
-//   4. row by row, each thread re-runs its four chains from its prefix and
-//      stages the 16 outputs in LDS so that the global stores are contiguous.
-// Tile order comes from an atomic counter, so every tile a workgroup waits on
-// was taken by a workgroup that started earlier.  The sampled form (SAMPLED)
-// stores every 16th value only, P[16 q] for 16 q <= n: each thread's value
-// before its 16 bytes, plus P[n] when n is a multiple of 16; any other value is
-// 15 Horner steps or fewer from its sample.  Returning atomics on one
-// address serialize (about 10 ns apart), which is why a tile spans four rows:
-// one counter update per 16 KiB.
+//      prefix ready); wave 0 runs it for the fingerprints and wave 1 for the
+//      32-bit hashes, side by side.
+//   4. Outputs: every 16th value (the thread's prefix times x^(16 c) plus the
+//      folds of step 1) goes to LDS; then, row by row (4 KiB of the tile), each
+//      thread runs 16 Horner steps from one of them (one multiply-add per
+//      output), and each wave stages its outputs in LDS so that its stores are
+//      lane-contiguous.  The sampled form stores every 16th value only:
+//      P[16 q] for 16 q <= n.
+// Tile order comes from the counter, so a tile waits only on tiles that
+// running workgroups hold.  The text is read once for both results.
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace bt {
+namespace {
 
-// Arithmetic of the two scans.
-struct Mod61 {
+constexpr unsigned kPfGrid = 1024;  // resident workgroups
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+constexpr uint64_t kM29 = (1ull << 29) - 1;
+
+// (a b + c) mod (2^61 - 1) for a, b, c < 2^61.  The product is
+// p11 2^64 + mid 2^32 + p00 from four 32 x 32-bit products; with 2^61 = 1
+// every part folds to a term below 2^61, and the sum stays below 2^63.
+__device__ __forceinline__ uint64_t mad61(uint64_t a, uint64_t b, uint64_t c) {
+  const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+  const uint64_t p00 = a0 * b0;
+  const uint64_t mid = a0 * b1 + a1 * b0;  // < 2^62
+  const uint64_t p11 = a1 * b1;            // < 2^58
+  uint64_t s = (p11 << 3) + (mid >> 29) + ((mid & kM29) << 32) + (p00 >> 61) + (p00 & kP61) + c;
+  s = (s & kP61) + (s >> 61);
+  return s >= kP61 ? s - kP61 : s;
+}
+
+// s mod (2^61 - 1) for any 64-bit s.
+__device__ __forceinline__ uint64_t fold61(uint64_t s) {
+  s = (s & kP61) + (s >> 61);
+  return s >= kP61 ? s - kP61 : s;
+}
+
+struct A61 {
   using V = uint64_t;
-  using Pow = PfPow;
   static constexpr uint64_t kAgg = 1ull << 61;  // status flags above the value
   static constexpr uint64_t kInc = 1ull << 62;
-  __device__ static V mul(V a, V b) { return mul61(a, b); }
+  __device__ static V mul(V a, V b) { return mad61(a, b, 0); }
   __device__ static V add(V a, V b) { return add61(a, b); }
   __device__ static V value(uint64_t w) { return w & kP61; }
   __device__ static bool ready(uint64_t w) { return (w >> 61) != 0; }
   __device__ static V wave_sum(V v) { return wave_sum61(v); }
 };
 
-struct Mod32 {
+struct A32 {
   using V = uint32_t;
-  using Pow = PfPow32;
   static constexpr uint64_t kAgg = 1ull << 32;
   static constexpr uint64_t kInc = 1ull << 33;
   __device__ static V mul(V a, V b) { return a * b; }
@@ -59,167 +87,299 @@ struct Mod32 {
   }
 };
 
-template <class A, bool SAMPLED>
-__global__ __launch_bounds__(kPfThreads) void k_prefix(const uint8_t* __restrict__ T, uint64_t n,
-                                                       typename A::V* __restrict__ P,
-                                                       const typename A::Pow* __restrict__ pw,
-                                                       uint64_t* __restrict__ status,
-                                                       uint32_t* __restrict__ ctr) {
+// One wave: publish the tile aggregate, fold the predecessors' values (64 at a
+// time, stopping at the first inclusive prefix), publish the inclusive prefix.
+// Returns the fold of everything before the tile (all lanes).  xt[k] is the
+// power for k tiles.
+template <class A>
+__device__ typename A::V look_back(uint64_t* status, uint64_t tile, typename A::V agg,
+                                   const typename A::V* __restrict__ xt) {
   using V = typename A::V;
-  __shared__ V s_out[kPfThreads * 17];
-  __shared__ V s_wave[kPfRows][kPfThreads / 64];
-  __shared__ V s_excl;
-  __shared__ uint32_t s_tile;
-
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wv = t >> 6;
-  if (t == 0) s_tile = atomicAdd(ctr, 1u);
-  __syncthreads();
-  const uint64_t tile = s_tile;
-  const uint64_t base = tile * kPfTile;
-  const V x = pw->x1[1];
-  const V x4 = pw->x1[4];
-  const V xrow = pw->x16[256];
-
-  // 16 bytes per thread and row; zero beyond the end (those outputs are not
-  // stored, and only the last tile, whose aggregate nobody reads, has any)
-  uint32_t w[kPfRows][4];
-#pragma unroll
-  for (int r = 0; r < kPfRows; ++r) {
-    const uint64_t pos = base + r * kPfRow + (uint64_t)t * kPfBytes;
-    w[r][0] = w[r][1] = w[r][2] = w[r][3] = 0;
-    if (pos + kPfBytes <= n && ((reinterpret_cast<uintptr_t>(T) & 15) == 0)) {
-      const uint4 v = *reinterpret_cast<const uint4*>(T + pos);
-      w[r][0] = v.x; w[r][1] = v.y; w[r][2] = v.z; w[r][3] = v.w;
-    } else {
-      for (int k = 0; k < kPfBytes; ++k)
-        if (pos + k < n) w[r][k >> 2] |= (uint32_t)T[pos + k] << (8 * (k & 3));
-    }
+  const int lane = lane_id();
+  if (tile == 0) {
+    if (lane == 0) st_relaxed(&status[0], A::kInc | (uint64_t)agg);
+    return 0;
   }
-  const auto byte_at = [&](int r, int k) { return (V)((w[r][k >> 2] >> (8 * (k & 3))) & 0xFF); };
-
-  // 1. thread aggregates: four 4-byte Horner chains per row joined with x^4;
-  //    g[r][c] = the first c chains joined (g[r][0] = 0)
-  V g[kPfRows][4];
-  V E[kPfRows];
-  V hrow[kPfRows];  // the thread's 16-byte fold per row
-#pragma unroll
-  for (int r = 0; r < kPfRows; ++r) {
-    V hc[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      V v = byte_at(r, 4 * c);
-#pragma unroll
-      for (int k = 1; k < 4; ++k) v = A::add(A::mul(v, x), byte_at(r, 4 * c + k));
-      hc[c] = v;
+  if (lane == 0) st_relaxed(&status[tile], A::kAgg | (uint64_t)agg);
+  const V xl = xt[lane], x64 = xt[64];
+  V excl = 0, mult = 1;
+  int64_t look = (int64_t)tile - 1;
+  while (true) {
+    const int64_t pred = look - lane;
+    uint64_t v = 0;
+    if (pred >= 0) {
+      do { v = ld_relaxed(&status[pred]); } while (!A::ready(v));
     }
-    g[r][0] = 0;
-    g[r][1] = hc[0];
-    g[r][2] = A::add(A::mul(g[r][1], x4), hc[1]);
-    g[r][3] = A::add(A::mul(g[r][2], x4), hc[2]);
-    const V h = A::add(A::mul(g[r][3], x4), hc[3]);
-    hrow[r] = h;
+    const uint64_t inc = __ballot(pred >= 0 && (v & A::kInc));
+    const int stop = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
+    const V term = (lane <= stop && pred >= 0) ? A::mul(A::value(v), xl) : (V)0;
+    excl = A::add(excl, A::mul(A::wave_sum(term), mult));
+    if (inc) break;
+    mult = A::mul(mult, x64);
+    look -= 64;
+  }
+  if (lane == 0) st_relaxed(&status[tile], A::kInc | (uint64_t)A::add(A::mul(excl, xt[1]), agg));
+  return excl;
+}
 
-    // 2. wave inclusive scan: I = sum_{u <= lane} h_u x^(16 (lane - u))
-    V I = h;
+template <bool SAMPLED, bool WH>
+__global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_prefix(const uint8_t* __restrict__ T, uint64_t n,
+                                                       uint64_t* __restrict__ P,
+                                                       uint32_t* __restrict__ H,
+                                                       const PfTab* __restrict__ tb,
+                                                       uint64_t* __restrict__ st61,
+                                                       uint64_t* __restrict__ st32,
+                                                       uint32_t* __restrict__ ctr, uint64_t tiles) {
+  __shared__ uint64_t s_g61[7 * 256];
+  __shared__ uint32_t s_g32[WH ? 7 * 256 : 1];
+  __shared__ uint64_t s_w61[kPfThreads / 64];
+  __shared__ uint32_t s_w32[kPfThreads / 64];
+  __shared__ uint64_t s_ex61;
+  __shared__ uint32_t s_ex32;
+  __shared__ uint32_t s_tile;
+  // chain starts P[16 m], H[16 m] of the tile (m = 0..1023), and per wave a
+  // staging area: 64 rows of 8 fingerprints, or of 16 hashes (row strides 9
+  // and 17 words keep the lanes on different banks)
+  constexpr bool DENSE = !SAMPLED;
+  __shared__ uint64_t s_st61[DENSE ? kPfTile / 16 : 1];
+  __shared__ uint32_t s_st32[WH ? kPfTile / 16 : 1];
+  __shared__ uint64_t s_out[(DENSE || WH) ? (kPfThreads / 64) * 64 * 9 : 1];
+
+  const int t0 = threadIdx.x;
+  for (int k = t0; k < 7 * 256; k += kPfThreads) {
+    s_g61[k] = (&tb->g61[0][0])[k];
+    if (WH) s_g32[k] = (&tb->g32[0][0])[k];
+  }
+  const uint64_t x1 = tb->x1_61, x8 = tb->x8_61;
+  const uint32_t y1 = tb->x1_32, y8 = tb->x8_32;
+  const bool t_al = (reinterpret_cast<uintptr_t>(T) & 15) == 0;
+
+  while (true) {
+    // The thread index is hidden from the optimizer in every pass: otherwise
+    // the addresses derived from it are hoisted out of the tile loop and held
+    // in registers for its whole length.
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const int lane = t & 63;
+    const int wv = t >> 6;
+    if (t == 0) s_tile = atomicAdd(ctr, 1u);
+    __syncthreads();  // (first pass: the tables are in LDS too)
+    const uint64_t tile = s_tile;
+    if (tile >= tiles) break;
+    const uint64_t pos = tile * kPfTile + (uint64_t)t * kPfBytes;
+    const bool full = pos + kPfBytes <= n;
+
+    // the thread's 64 bytes, zero past the end (no stored value depends on
+    // them, and only the last tile, whose aggregate nobody reads, has any)
+    uint32_t w[16];
+    if (t_al && full) {
+      const uint4* src = reinterpret_cast<const uint4*>(T + pos);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint4 v = src[q];
+        w[4 * q] = v.x;
+        w[4 * q + 1] = v.y;
+        w[4 * q + 2] = v.z;
+        w[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) w[k] = 0;
+#pragma unroll
+      for (int k = 0; k < kPfBytes; ++k)
+        if (pos + k < n) w[k >> 2] |= (uint32_t)T[pos + k] << (8 * (k & 3));
+    }
+    const auto byte_at = [&](int k) { return (w[k >> 2] >> (8 * (k & 3))) & 0xFFu; };
+
+    // 1. folds: h = all 64 bytes; F[c] = the first 16 c bytes (c = 1..3)
+    uint64_t h61 = 0, F61[4] = {0, 0, 0, 0};
+    uint32_t h32 = 0, F32[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      uint64_t g = byte_at(8 * q + 7);
+      uint32_t g32 = byte_at(8 * q + 7);
+#pragma unroll
+      for (int j = 1; j < 8; ++j) {
+        const uint32_t b = byte_at(8 * q + 7 - j);
+        g += s_g61[(j - 1) * 256 + b];  // eight terms below 2^61: no overflow
+        if (WH) g32 += s_g32[(j - 1) * 256 + b];
+      }
+      g = fold61(g);
+      h61 = q ? mad61(h61, x8, g) : g;
+      if (WH) h32 = q ? h32 * y8 + g32 : g32;
+      if ((q & 1) && q < 7) {
+        F61[(q + 1) >> 1] = h61;
+        F32[(q + 1) >> 1] = h32;
+      }
+      // one group's lookups in flight at a time (registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // 16 bytes of a row of step 4 (row r: tile offset 4096 r + 16 t)
+    const uint64_t tb0 = tile * kPfTile;
+    const auto load_row = [&](int r, uint32_t* bw) {
+      const uint64_t q = tb0 + 4096 * r + 16 * (uint64_t)t;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bw[e] = 0;
+      if (t_al && q + 16 <= n) {
+        const uint4 x = *reinterpret_cast<const uint4*>(T + q);
+        bw[0] = x.x;
+        bw[1] = x.y;
+        bw[2] = x.z;
+        bw[3] = x.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (q + k < n) bw[k >> 2] |= (uint32_t)T[q + k] << (8 * (k & 3));
+      }
+    };
+    // row 0 is requested now: the scan and the look-back hide its latency
+    uint32_t rw[4];
+    if (DENSE || WH) load_row(0, rw);
+
+    // 2. inclusive wave scan with x^(64 d); the exclusive value, the wave
+    //    aggregates, the fold of the earlier waves and the tile aggregate
+    uint64_t I = h61;
+    uint32_t I32 = h32;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const V o = __shfl_up(I, d);
-      if (lane >= d) I = A::add(A::mul(o, pw->x16[d]), I);
-    }
-    V e = __shfl_up(I, 1);
-    if (lane == 0) e = 0;
-    E[r] = e;
-    if (lane == 63) s_wave[r][wv] = I;
-  }
-  __syncthreads();
-  // per row: prefix of the earlier waves (local) and the row aggregate; rows
-  // fold into the tile aggregate, rp[r] = rows 0 .. r-1 of this tile
-  V local[kPfRows], rp[kPfRows];
-  V agg = 0;
-#pragma unroll
-  for (int r = 0; r < kPfRows; ++r) {
-    V wp = 0, ra = 0;
-#pragma unroll
-    for (int v = 0; v < kPfThreads / 64; ++v) {
-      if (v < wv) wp = A::add(A::mul(wp, pw->x16[64]), s_wave[r][v]);
-      ra = A::add(A::mul(ra, pw->x16[64]), s_wave[r][v]);
-    }
-    local[r] = A::add(A::mul(wp, pw->x16[lane]), E[r]);
-    rp[r] = agg;
-    agg = A::add(A::mul(agg, xrow), ra);
-  }
-
-  // 3. carry-in from earlier tiles
-  if (wv == 0) {
-    V excl = 0;
-    if (tile == 0) {
-      if (lane == 0) st_relaxed(&status[0], A::kInc | (uint64_t)agg);
-    } else {
-      if (lane == 0) st_relaxed(&status[tile], A::kAgg | (uint64_t)agg);
-      V mult = 1;
-      int64_t look = (int64_t)tile - 1;
-      while (true) {
-        const int64_t pred = look - lane;
-        uint64_t v = 0;
-        if (pred >= 0) {
-          do { v = ld_relaxed(&status[pred]); } while (!A::ready(v));
-        }
-        const uint64_t inc = __ballot(pred >= 0 && (v & A::kInc));
-        const int stop = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
-        const V term = (lane <= stop && pred >= 0) ? A::mul(A::value(v), pw->xt[lane]) : (V)0;
-        excl = A::add(excl, A::mul(A::wave_sum(term), mult));
-        if (inc) break;
-        mult = A::mul(mult, pw->xt[64]);
-        look -= 64;
+      const uint64_t o = __shfl_up(I, d);
+      const uint32_t o32 = WH ? __shfl_up(I32, d) : 0u;
+      if (lane >= d) {
+        I = mad61(o, tb->t61[d], I);
+        if (WH) I32 = o32 * tb->t32[d] + I32;
       }
-      if (lane == 0)
-        st_relaxed(&status[tile], A::kInc | (uint64_t)A::add(A::mul(excl, pw->xt[1]), agg));
     }
-    if (lane == 0) s_excl = excl;
-  }
-  __syncthreads();
-
-  // 4. outputs P[row + 16t + 1 .. row + 16t + 16], row by row
-  V xr = 1;  // x^(row r)
-  const V excl = s_excl;
-  if (SAMPLED) {
-#pragma unroll
-    for (int r = 0; r < kPfRows; ++r) {
-      const uint64_t pos = base + r * kPfRow + (uint64_t)t * kPfBytes;
-      const V before_row = A::add(A::mul(excl, xr), rp[r]);
-      const V C = A::add(A::mul(before_row, pw->x16[t]), local[r]);  // P[pos]
-      if (pos <= n) P[pos >> 4] = C;
-      if (pos + kPfBytes == n) P[n >> 4] = A::add(A::mul(C, pw->x16[1]), hrow[r]);
-      xr = A::mul(xr, xrow);
+    uint64_t E = __shfl_up(I, 1);
+    uint32_t E32 = WH ? __shfl_up(I32, 1) : 0u;
+    if (lane == 0) {
+      E = 0;
+      E32 = 0;
     }
-    return;
-  }
-#pragma unroll
-  for (int r = 0; r < kPfRows; ++r) {
-    const uint64_t rowbase = base + r * kPfRow;
-    const V before_row = A::add(A::mul(excl, xr), rp[r]);
-    const V C = A::add(A::mul(before_row, pw->x16[t]), local[r]);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      V v = c ? A::add(A::mul(C, pw->x1[4 * c]), g[r][c]) : C;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        v = A::add(A::mul(v, x), byte_at(r, 4 * c + k));
-        s_out[t * 17 + 4 * c + k] = v;
-      }
+    if (lane == 63) {
+      s_w61[wv] = I;
+      if (WH) s_w32[wv] = I32;
     }
     __syncthreads();
+    uint64_t wp = 0, agg = 0;
+    uint32_t wp32 = 0, agg32 = 0;
+    const uint64_t xw = tb->t61[64];
+    const uint32_t yw = tb->t32[64];
 #pragma unroll
-    for (int q = 0; q < kPfBytes; ++q) {
-      const uint64_t m = (uint64_t)t + (uint64_t)kPfThreads * q;
-      if (rowbase + m < n) P[rowbase + 1 + m] = s_out[(m >> 4) * 17 + (m & 15)];
+    for (int v = 0; v < kPfThreads / 64; ++v) {
+      const uint64_t a = s_w61[v];
+      if (v < wv) wp = mad61(wp, xw, a);
+      agg = mad61(agg, xw, a);
+      if (WH) {
+        const uint32_t a32 = s_w32[v];
+        if (v < wv) wp32 = wp32 * yw + a32;
+        agg32 = agg32 * yw + a32;
+      }
     }
-    __syncthreads();  // s_out is reused by the next row
-    xr = A::mul(xr, xrow);
+    const uint64_t local = mad61(wp, tb->t61[lane], E);  // tile bytes before this thread
+    const uint32_t local32 = wp32 * tb->t32[lane] + E32;
+
+    // 3. carry-in
+    if (wv == 0) {
+      const uint64_t ex = look_back<A61>(st61, tile, agg, tb->xt61);
+      if (lane == 0) s_ex61 = ex;
+    }
+    if (WH && wv == 1) {
+      const uint32_t ex = look_back<A32>(st32, tile, agg32, tb->xt32);
+      if (lane == 0) s_ex32 = ex;
+    }
+    __syncthreads();
+    const uint64_t C = mad61(s_ex61, tb->t61[t], local);  // P[pos]
+    const uint32_t C32 = s_ex32 * tb->t32[t] + local32;  // H[pos]
+
+    // 4. chain starts, then outputs.  Thread t of the contiguous layout holds
+    // P[pos + 16 c] = C x^(16 c) + F[c].  The outputs are written in rows of
+    // 4 KiB: in row r thread t runs the 16 Horner steps from tile offset
+    // 4096 r + 16 t, and each wave stages its 64 chains in LDS so that every
+    // store instruction covers whole 64-byte runs (lane-contiguous).
+    {
+      uint64_t v[4];
+      uint32_t u[4];
+      v[0] = C;
+      u[0] = C32;
+#pragma unroll
+      for (int c = 1; c < 4; ++c) {
+        v[c] = mad61(C, tb->c61[c], F61[c]);
+        u[c] = C32 * tb->c32[c] + F32[c];
+      }
+      if (SAMPLED) {
+        if (pos <= n) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (pos + 16 * c <= n) P[(pos >> 4) + c] = v[c];
+          if (pos + kPfBytes == n) P[n >> 4] = mad61(C, tb->t61[1], h61);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s_st61[4 * t + c] = v[c];
+      }
+      if (WH) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s_st32[4 * t + c] = u[c];
+      }
+    }
+    if (DENSE || WH) {
+      __syncthreads();
+      const bool tfull = tb0 + kPfTile < n;  // no output of the tile lies past n
+      uint64_t* so = s_out + wv * 64 * 9;
+      uint32_t* so32 = reinterpret_cast<uint32_t*>(so);
+#pragma unroll 1
+      for (int r = 0; r < 4; ++r) {
+        const uint64_t q = tb0 + 4096 * r + 16 * (uint64_t)t;  // this thread's 16 bytes
+        const uint64_t wbase = tb0 + 4096 * r + 1024 * (uint64_t)wv;  // the wave's 1024
+        uint32_t nx[4];  // the next row's bytes, requested one row ahead
+        if (r < 3) load_row(r + 1, nx);
+        const auto rb = [&](int k) { return (rw[k >> 2] >> (8 * (k & 3))) & 0xFFu; };
+        if (DENSE) {
+          // two halves of eight steps: P[q + 8 h + k] to row `lane`, then the
+          // wave stores 512 values, runs of eight (64 bytes) per lane group
+          uint64_t val = s_st61[256 * r + t];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              so[lane * 9 + k] = val;
+              val = mad61(val, x1, rb(8 * h + k));
+            }
+            wave_sync();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+              const int e = 64 * m + lane;  // row e / 8, step e % 8
+              const uint64_t j = wbase + 16 * (uint64_t)(e >> 3) + 8 * h + (e & 7);
+              if (tfull || j <= n) P[j] = so[(e >> 3) * 9 + (e & 7)];
+            }
+            wave_sync();
+          }
+          if (q + 16 == n) P[n] = val;
+        }
+        if (WH) {
+          uint32_t val = s_st32[256 * r + t];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            so32[lane * 17 + k] = val;
+            val = val * y1 + rb(k);
+          }
+          wave_sync();
+#pragma unroll
+          for (int m = 0; m < 16; ++m) {
+            const int e = 64 * m + lane;
+            const uint64_t j = wbase + e;
+            if (tfull || j <= n) H[j] = so32[(e >> 4) * 17 + (e & 15)];
+          }
+          wave_sync();
+          if (q + 16 == n) H[n] = val;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rw[e] = nx[e];
+      }
+    }
+    __syncthreads();  // s_tile, s_w*, s_ex* are rewritten by the next tile
   }
-  if (tile == 0 && t == 0) P[0] = 0;
 }
 
 template <typename V>
@@ -229,37 +389,31 @@ __global__ void k_zero(V* p, uint64_t n) {
     p[i] = 0;
 }
 
-template <class A, bool SAMPLED = false>
-static hipError_t launch_prefix(const uint8_t* T, uint64_t n, typename A::V* P,
-                                const typename A::Pow* pw, uint64_t* status, uint32_t* ctr,
-                                hipStream_t s) {
+}  // namespace
+
+hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled, uint32_t* H,
+                         const PfTab* tab, uint64_t* status, hipStream_t s) {
   const uint64_t tiles = (n + kPfTile - 1) / kPfTile;
-  if (tiles == 0) {
-    // P[0] = 0 only
-    k_zero<typename A::V><<<1, 64, 0, s>>>(P, 1);
+  if (tiles == 0) {  // P[0] = 0 (and H[0] = 0) only
+    k_zero<uint64_t><<<1, 64, 0, s>>>(P, 1);
+    if (H) k_zero<uint32_t><<<1, 64, 0, s>>>(H, 1);
     return hipGetLastError();
   }
-  // status words and the tile counter
-  const unsigned zb = (unsigned)((tiles + 255) / 256 < 4096 ? (tiles + 255) / 256 : 4096);
-  k_zero<uint64_t><<<zb, 256, 0, s>>>(status, tiles);
-  k_zero<uint32_t><<<1, 64, 0, s>>>(ctr, 1);
-  k_prefix<A, SAMPLED><<<(unsigned)tiles, kPfThreads, 0, s>>>(T, n, P, pw, status, ctr);
+  const uint64_t words = prefix_status_words(n);
+  const unsigned zb = (unsigned)((words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096);
+  k_zero<uint64_t><<<zb, 256, 0, s>>>(status, words);
+  uint64_t* st61 = status;
+  uint64_t* st32 = status + tiles + 1;
+  uint32_t* ctr = reinterpret_cast<uint32_t*>(status + 2 * (tiles + 1));
+  const unsigned grid = (unsigned)(tiles < kPfGrid ? tiles : kPfGrid);
+  if (sampled) {
+    if (H) k_prefix<true, true><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    else k_prefix<true, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+  } else {
+    if (H) k_prefix<false, true><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    else k_prefix<false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+  }
   return hipGetLastError();
-}
-
-hipError_t launch_prefix_fp(const uint8_t* T, uint64_t n, uint64_t* P, const PfPow* pw,
-                            uint64_t* status, uint32_t* ctr, hipStream_t s) {
-  return launch_prefix<Mod61>(T, n, P, pw, status, ctr, s);
-}
-
-hipError_t launch_prefix_fp_sampled(const uint8_t* T, uint64_t n, uint64_t* Ps, const PfPow* pw,
-                                    uint64_t* status, uint32_t* ctr, hipStream_t s) {
-  return launch_prefix<Mod61, true>(T, n, Ps, pw, status, ctr, s);
-}
-
-hipError_t launch_prefix_h32(const uint8_t* T, uint64_t n, uint32_t* H, const PfPow32* pw,
-                             uint64_t* status, uint32_t* ctr, hipStream_t s) {
-  return launch_prefix<Mod32>(T, n, H, pw, status, ctr, s);
 }
 
 }  // namespace bt

@@ -221,19 +221,47 @@ hipError_t launch_rank_empty(const uint64_t* pos, uint64_t m, uint64_t* out, hip
 
 // ---------------------------------------------------------------- auxiliary
 
-__global__ void k_histogram(const uint8_t* __restrict__ T, uint64_t n, uint64_t* hist) {
-  __shared__ uint32_t h[256];
-  for (int k = threadIdx.x; k < 256; k += blockDim.x) h[k] = 0;
+// Each thread keeps its own 256-bit set in LDS column t (word k of thread t at
+// s[k][t]: a wave's lanes touch 64 different banks); 16 bytes per load.  The
+// columns are then ORed and merged into the global set, which is read first so
+// that most workgroups skip the atomic.
+__global__ __launch_bounds__(256) void k_byte_presence(const uint8_t* __restrict__ T, uint64_t n,
+                                                       uint32_t* __restrict__ seen) {
+  __shared__ uint32_t s[8][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s[k][t] = 0;
+  const auto add = [&](uint32_t c) { atomicOr(&s[c >> 5][t], 1u << (c & 31)); };
+  const uint64_t mis = reinterpret_cast<uintptr_t>(T) & 15;
+  const uint64_t head = mis ? (16 - mis < n ? 16 - mis : n) : 0;
+  const uint64_t body = (n - head) / 16;
+  const uint4* __restrict__ B = reinterpret_cast<const uint4*>(T + head);
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + t; i < body; i += (uint64_t)gridDim.x * 256) {
+    const uint4 v = B[i];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) add((w[q] >> (8 * k)) & 0xFFu);
+  }
+  if (blockIdx.x == 0) {
+    for (uint64_t i = t; i < head; i += 256) add(T[i]);
+    for (uint64_t i = head + body * 16 + t; i < n; i += 256) add(T[i]);
+  }
   __syncthreads();
-  GRID_STRIDE(i, n) atomicAdd(&h[T[i]], 1u);
-  __syncthreads();
-  for (int k = threadIdx.x; k < 256; k += blockDim.x)
-    if (h[k]) atomicAdd((unsigned long long*)&hist[k], (unsigned long long)h[k]);
+  // word k = t / 32 over the 256 columns: eight per lane, then 32 lanes
+  const int k = t >> 5, part = t & 31;
+  uint32_t m = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) m |= s[k][part * 8 + e];
+#pragma unroll
+  for (int d = 16; d >= 1; d >>= 1) m |= __shfl_xor(m, d);
+  if (part == 0 && m && (seen[k] | m) != seen[k]) atomicOr(&seen[k], m);
 }
 
-hipError_t launch_histogram(const uint8_t* T, uint64_t n, uint64_t* hist, hipStream_t s) {
+hipError_t launch_byte_presence(const uint8_t* T, uint64_t n, uint32_t* seen, hipStream_t s) {
   if (!n) return hipSuccess;
-  k_histogram<<<grid_for(n, 256, 2048), 256, 0, s>>>(T, n, hist);
+  k_byte_presence<<<grid_for((n + 15) / 16, 256, 1024), 256, 0, s>>>(T, n, seen);
   return hipGetLastError();
 }
 

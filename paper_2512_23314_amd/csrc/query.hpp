@@ -68,7 +68,9 @@ hipError_t launch_select(QTree t, const uint8_t* cs, const uint64_t* ks, uint64_
 hipError_t launch_rank_empty(const uint64_t* pos, uint64_t m, uint64_t* out, hipStream_t s);
 
 // auxiliary kernels used by the build
-hipError_t launch_histogram(const uint8_t* T, uint64_t n, uint64_t* hist, hipStream_t s);
+// Which byte values occur in T[0..n): bit c of the 256-bit set `seen` (eight
+// words, zeroed by the caller) is set when byte value c occurs.
+hipError_t launch_byte_presence(const uint8_t* T, uint64_t n, uint32_t* seen, hipStream_t s);
 hipError_t launch_last_block_len(const LevelDev& lv, const TextsDev& tx, const uint64_t* tfirst,
                                  const uint64_t* tcount, uint64_t* out, hipStream_t s);
 hipError_t launch_text_deltas(const uint64_t* scanned, const uint64_t* tfirst,

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from tests import treecheck
+from tests import hashref, treecheck
 from tests.gpu_util import assert_same_tree, shape_of, to_device, torch_cuda
 
 pytestmark = pytest.mark.gpu
@@ -49,6 +49,43 @@ def test_prefix_fingerprints_unaligned_view(ctx):
         got = ctx.prefix_fingerprints(d[off:], x).cpu().numpy()
         assert np.array_equal(got, oracle.prefix_fp(T[off:], x))
     del torch
+
+
+def test_prefix_fingerprints_misaligned_output(ctx):
+    """An output view 8 bytes off a 16-byte boundary takes single-word stores."""
+    torch = torch_cuda()
+    T = np.random.default_rng(5).integers(0, 256, 40003).astype(np.uint8)
+    buf = torch.zeros(len(T) + 2, dtype=torch.uint64, device="cuda:0")
+    got = ctx.prefix_fingerprints(to_device(T), 987654321, out=buf[1:]).cpu().numpy()
+    assert np.array_equal(got, oracle.prefix_fp(T, 987654321))
+    assert int(buf[0]) == 0
+
+
+# both prefix arrays in one pass (the builds' form): dense or sampled
+# fingerprints, and the 32-bit hashes against their recurrence
+@pytest.mark.parametrize("sampled", [False, True], ids=["dense", "sampled"])
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 63, 64, 65, 4095, 16383, 16384, 16385, 32768,
+                               65536 * 3 + 7, (5 << 20) + 1])
+def test_prefix_scan(ctx, n, sampled):
+    rng = np.random.default_rng(n + 7)
+    T = rng.integers(0, 256, n).astype(np.uint8)
+    x = int(rng.integers(256, oracle.P61 - 1))
+    x32 = int(rng.integers(0, 1 << 31)) * 2 + 1
+    P, H = ctx.prefix_scan(to_device(T), x, x32, sampled=sampled)
+    want = oracle.prefix_fp(T, x)
+    assert np.array_equal(P.cpu().numpy(), want[::16] if sampled else want)
+    assert np.array_equal(H.cpu().numpy().view(np.uint32), hashref.h32(T, x32))
+
+
+def test_prefix_scan_unaligned_views(ctx):
+    T = np.random.default_rng(8).integers(0, 256, 70001).astype(np.uint8)
+    d = to_device(T)
+    for off in (1, 3, 8, 13):
+        for sampled in (False, True):
+            P, H = ctx.prefix_scan(d[off:], 1234567 + off, 0x9E3779B1, sampled=sampled)
+            want = oracle.prefix_fp(T[off:], 1234567 + off)
+            assert np.array_equal(P.cpu().numpy(), want[::16] if sampled else want)
+            assert np.array_equal(H.cpu().numpy().view(np.uint32), hashref.h32(T[off:], 0x9E3779B1))
 
 
 # ---- whole builds against the oracle
