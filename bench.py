@@ -92,6 +92,7 @@ def _csv_rows(path):
 def _short_name(name):
     """'void bt::k_probe_scan<2, false, false>(bt::PhaseArgs, ...)' -> 'k_probe_scan<2, false, false>'"""
     s = name[5:] if name.startswith("void ") else name
+    s = s.replace("(anonymous namespace)::", "")
     depth, cut = 0, len(s)
     for i, ch in enumerate(s):
         if ch == "<":

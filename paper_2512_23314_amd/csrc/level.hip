@@ -93,7 +93,8 @@ __global__ void k_keys(PhaseArgs a) {
     const uint64_t fp = finish_fp(win61_any(a, st, L, xp), a.tx.tsalt[t], a.fpmask);
     a.k.fp[j] = fp;
     a.k.len[j] = L;
-    a.odd.nkeys[t] = 1;
+    // (a flag: written once, not by every key of the text into one word)
+    if (!a.odd.nkeys[t]) a.odd.nkeys[t] = 1;
     if (L == a.Lmain) {
       uint64_t h = slot_of(fp, a.tab.mask);
       while (true) {
