@@ -64,11 +64,22 @@ def traffic_record(kernel):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2512_23314_amd", "csrc", rec.get("source", "level.hip"))
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if h != rec.get("source_sha256"):
+    if "sources" not in rec or _sources_sha(rec["sources"]) != rec.get("source_sha256"):
         return None
     return rec
+
+
+# the files the probe scan is compiled from; a change to any of them retires
+# the traffic record
+PROBE_SOURCES = ["level.hip", "common.hpp", "window.hpp", "internal.hpp"]
+
+
+def _sources_sha(names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2512_23314_amd", "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 # ---------------------------------------------------------------- profile summaries
@@ -153,7 +164,8 @@ def _counter_per_launch(d, needle):
 
 
 def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, bench_json, cmds,
-                      out_md, out_json, kernel="probe_scan", source="level.hip"):
+                      out_md, out_json, kernel="probe_scan", sources=None):
+    sources = sources or PROBE_SOURCES
     copy_bytes = copy_mib << 20
     cf, _ = _counter_per_launch(cfetch_dir, "copyBuffer")
     cw, _ = _counter_per_launch(cwrite_dir, "copyBuffer")
@@ -164,9 +176,7 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, be
     fetch, write = kf * 1024.0 * ff, kw * 1024.0 * fw
     b = _bench_line(bench_json)
     algo = b["roofline"].get("bytes_per_launch")
-    src = os.path.join(ROOT, "paper_2512_23314_amd", "csrc", source)
-    rec = {"kernel": kernel, "source": source,
-           "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+    rec = {"kernel": kernel, "sources": sources, "source_sha256": _sources_sha(sources),
            "workload": b["config"]["workload"], "launches": n,
            "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
            "bytes_per_launch": round(fetch + write), "algorithmic_bytes_per_launch": algo,
@@ -188,7 +198,8 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, be
         lines += ["| algorithmic (the two prefix values per window: 8 B pre-filtered, 16 B "
                   "otherwise) | %.4g |" % algo,
                   "| traffic / algorithmic | %.3f |" % ((fetch + write) / algo)]
-    lines += ["", "Source hash (%s): %s" % (source, rec["source_sha256"])]
+    lines += ["", "Source hash (SHA-256 of %s, in that order): %s" % (", ".join(sources),
+                                                                     rec["source_sha256"])]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", out_md, out_json)

@@ -19,14 +19,23 @@ constexpr uint32_t kOddKey = 0xFFFFFFFEu;   // key of non-standard length (text 
 constexpr uint32_t kCopyKey = 0xFFFFFFFDu;
 constexpr uint64_t kWeakMask = 0xFFFull;    // BT_DBG_WEAK_HASH truncation
 
-// a * b mod (2^61 - 1) for a, b < 2^61 - 1.  The 122-bit product is split at
-// bit 61 and folded once (2^61 = 1 mod q); the sum is below 2q.
-__device__ __forceinline__ uint64_t mul61(uint64_t a, uint64_t b) {
-  const uint64_t lo = a * b;
-  const uint64_t hi = __umul64hi(a, b);
-  const uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
-  return r >= kP61 ? r - kP61 : r;
+// (a b + c) mod (2^61 - 1) for a, b, c < 2^61.  The product is
+// p11 2^64 + mid 2^32 + p00 from four 32 x 32-bit products (no 64-bit high
+// multiply); with 2^64 = 8 and 2^61 = 1 (mod q) every part folds to a term
+// below 2^61, the sum stays below 2^63, and one more fold and one conditional
+// subtraction give the residue.
+__device__ __forceinline__ uint64_t mad61(uint64_t a, uint64_t b, uint64_t c) {
+  const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+  const uint64_t p00 = a0 * b0;
+  const uint64_t mid = a0 * b1 + a1 * b0;  // < 2^62
+  const uint64_t p11 = a1 * b1;            // < 2^58
+  uint64_t s = (p11 << 3) + (mid >> 29) + ((mid & ((1ull << 29) - 1)) << 32) + (p00 >> 61) +
+               (p00 & kP61) + c;
+  s = (s & kP61) + (s >> 61);
+  return s >= kP61 ? s - kP61 : s;
 }
+// a * b mod (2^61 - 1) for a, b < 2^61.
+__device__ __forceinline__ uint64_t mul61(uint64_t a, uint64_t b) { return mad61(a, b, 0); }
 __device__ __forceinline__ uint64_t add61(uint64_t a, uint64_t b) {
   const uint64_t r = a + b;
   return r >= kP61 ? r - kP61 : r;

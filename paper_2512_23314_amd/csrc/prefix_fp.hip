@@ -40,20 +40,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-constexpr uint64_t kM29 = (1ull << 29) - 1;
-
-// (a b + c) mod (2^61 - 1) for a, b, c < 2^61.  The product is
-// p11 2^64 + mid 2^32 + p00 from four 32 x 32-bit products; with 2^61 = 1
-// every part folds to a term below 2^61, and the sum stays below 2^63.
-__device__ __forceinline__ uint64_t mad61(uint64_t a, uint64_t b, uint64_t c) {
-  const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
-  const uint64_t p00 = a0 * b0;
-  const uint64_t mid = a0 * b1 + a1 * b0;  // < 2^62
-  const uint64_t p11 = a1 * b1;            // < 2^58
-  uint64_t s = (p11 << 3) + (mid >> 29) + ((mid & kM29) << 32) + (p00 >> 61) + (p00 & kP61) + c;
-  s = (s & kP61) + (s >> 61);
-  return s >= kP61 ? s - kP61 : s;
-}
 
 // s mod (2^61 - 1) for any 64-bit s.
 __device__ __forceinline__ uint64_t fold61(uint64_t s) {
