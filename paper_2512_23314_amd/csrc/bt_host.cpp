@@ -1121,11 +1121,16 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint64_t> d_ent = alloc<uint64_t>(ctx, T);
     upload(ctx, d_ent.p, ent.data(), T);
     Buf<uint64_t> ntcount = alloc<uint64_t>(ctx, T + 1), ntfirst = alloc<uint64_t>(ctx, T + 1);
-    HIPCHK(ctx, launch_text_counts(T, cs.p, d_tfirst.p, d_tcount.p, d_ent.p, ntcount.p, s));
-    HIPCHK(ctx, hipMemcpyAsync(ntfirst.p, ntcount.p, T * 8, hipMemcpyDeviceToDevice, s));
-    scan(ntfirst.p, T);
     Buf<uint64_t> tu = alloc<uint64_t>(ctx, T);
-    HIPCHK(ctx, launch_text_deltas(uoff.p, d_tfirst.p, d_tcount.p, T, tu.p, s));
+    if (T <= kTextStepMax) {  // counts, their prefix and the unmarked deltas in one launch
+      HIPCHK(ctx, launch_text_step(T, cs.p, d_tfirst.p, d_tcount.p, d_ent.p, uoff.p, ntcount.p,
+                                   ntfirst.p, tu.p, s));
+    } else {
+      HIPCHK(ctx, launch_text_counts(T, cs.p, d_tfirst.p, d_tcount.p, d_ent.p, ntcount.p, s));
+      HIPCHK(ctx, hipMemcpyAsync(ntfirst.p, ntcount.p, T * 8, hipMemcpyDeviceToDevice, s));
+      scan(ntfirst.p, T);
+      HIPCHK(ctx, launch_text_deltas(uoff.p, d_tfirst.p, d_tcount.p, T, tu.p, s));
+    }
     scan(nrun.p, c);
     std::vector<uint64_t> got;
     read_words(ctx, {{ntcount.p, T}, {tu.p, T}, {uoff.p + c, 1}, {nrun.p + c, 1}}, got);

@@ -179,6 +179,14 @@ hipError_t launch_fill_many(const FillList& f, hipStream_t s);
 // scan_tmp_words(n) words.
 uint64_t scan_tmp_words(uint64_t n);
 hipError_t scan_excl_u64(uint64_t* a, uint64_t n, uint64_t* tmp, hipStream_t s);
+// Per-text counts of the next level in one launch, for T <= kTextStepMax texts:
+// ncount[t] = cs[tfirst[t] + tcount[t]] - cs[tfirst[t]] + enter[t];
+// nfirst = exclusive prefix of ncount (T + 1 words);
+// tu[t] = uoff[tfirst[t] + tcount[t]] - uoff[tfirst[t]].
+constexpr uint32_t kTextStepMax = 2048;
+hipError_t launch_text_step(uint32_t T, const uint64_t* cs, const uint64_t* tfirst,
+                            const uint64_t* tcount, const uint64_t* enter, const uint64_t* uoff,
+                            uint64_t* ncount, uint64_t* nfirst, uint64_t* tu, hipStream_t s);
 
 // Phase kernels (steps a3-a7).
 hipError_t launch_keys(const PhaseArgs& a, hipStream_t s);

@@ -108,14 +108,12 @@ __device__ typename A::V look_back(uint64_t* status, uint64_t tile, typename A::
   return excl;
 }
 
+// Two waves per SIMD: the register budget of three spilled, and ran slower.
 template <bool SAMPLED, bool WH>
-__global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_prefix(const uint8_t* __restrict__ T, uint64_t n,
-                                                       uint64_t* __restrict__ P,
-                                                       uint32_t* __restrict__ H,
-                                                       const PfTab* __restrict__ tb,
-                                                       uint64_t* __restrict__ st61,
-                                                       uint64_t* __restrict__ st32,
-                                                       uint32_t* __restrict__ ctr, uint64_t tiles) {
+__global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_prefix(
+    const uint8_t* __restrict__ T, uint64_t n, uint64_t* __restrict__ P, uint32_t* __restrict__ H,
+    const PfTab* __restrict__ tb, uint64_t* __restrict__ st61, uint64_t* __restrict__ st32,
+    uint32_t* __restrict__ ctr, uint64_t tiles) {
   __shared__ uint64_t s_g61[7 * 256];
   __shared__ uint32_t s_g32[WH ? 7 * 256 : 1];
   __shared__ uint64_t s_w61[kPfThreads / 64];

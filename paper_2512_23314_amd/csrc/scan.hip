@@ -145,6 +145,49 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint64_t* __restrict
   }
 }
 
+__global__ __launch_bounds__(kScanThreads) void k_text_step(uint32_t T, const uint64_t* __restrict__ cs,
+                                                            const uint64_t* __restrict__ tfirst,
+                                                            const uint64_t* __restrict__ tcount,
+                                                            const uint64_t* __restrict__ enter,
+                                                            const uint64_t* __restrict__ uoff,
+                                                            uint64_t* __restrict__ ncount,
+                                                            uint64_t* __restrict__ nfirst,
+                                                            uint64_t* __restrict__ tu) {
+  __shared__ uint64_t s_w[kScanThreads / 64];
+  const uint64_t first = (uint64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t t = first + k;
+    v[k] = 0;
+    if (t < T) {
+      const uint64_t f = tfirst[t], e = f + tcount[t];
+      v[k] = cs[e] - cs[f] + enter[t];
+      ncount[t] = v[k];
+      tu[t] = uoff[e] - uoff[f];
+    }
+    sum += v[k];
+  }
+  uint64_t run = block_excl_scan(sum, s_w);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t t = first + k;
+    if (t < T) nfirst[t] = run;
+    run += v[k];
+    if (t + 1 == T || (T == 0 && t == 0)) nfirst[T] = run;
+  }
+}
+
+hipError_t launch_text_step(uint32_t T, const uint64_t* cs, const uint64_t* tfirst,
+                            const uint64_t* tcount, const uint64_t* enter, const uint64_t* uoff,
+                            uint64_t* ncount, uint64_t* nfirst, uint64_t* tu, hipStream_t s) {
+  if (T > kTextStepMax) return hipErrorInvalidValue;
+  static_assert(kTextStepMax == kScanTile, "one workgroup scans the texts");
+  k_text_step<<<1, kScanThreads, 0, s>>>(T, cs, tfirst, tcount, enter, uoff, ncount, nfirst, tu);
+  return hipGetLastError();
+}
+
 uint64_t scan_tmp_words(uint64_t n) {
   uint64_t w = 0;
   while (n > kScanTile) {

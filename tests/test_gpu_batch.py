@@ -133,3 +133,16 @@ def test_batch_unqueued_scan(ctx):
                             debug_flags=bt.BT_DBG_NO_QUEUE)
     for T, tr in zip(texts, trees):
         assert tr.serialize() == oracle.build_tree(T, 3, 4).canonical
+
+
+@pytest.mark.parametrize("count", [2048, 2500])
+def test_batch_many_small_texts(ctx, count):
+    """Per-text bookkeeping at the size where one workgroup scans the texts'
+    counts (2048) and past it (the multi-launch path)."""
+    rng = np.random.default_rng(count)
+    texts = [synth.random_text(int(rng.integers(0, 60)), int(rng.integers(1, 4)), int(rng.integers(1 << 30)))
+             for _ in range(count)]
+    concat, offs = _concat(texts)
+    trees = ctx.build_batch(to_device(concat), offs, tau=2, leaf_len=2)
+    for k, (T, tr) in enumerate(zip(texts, trees)):
+        assert tr.serialize() == oracle.build_tree(T, 2, 2).canonical, "text %d" % k
