@@ -321,7 +321,7 @@ uint32_t host_pow32(uint32_t x, uint64_t e) {
   return r;
 }
 
-// Tables of the prefix scan: g[j-1][b] = b x^j (j = 1..7), t[k] = x^(64 k),
+// Tables of the prefix scan: g61[j-1][b] = b x^j (j = 1..7), t[k] = x^(64 k),
 // xt[k] = x^(tile k), c[c] = x^(16 c), for both bases.
 void fill_tab(PfTab* tb, uint64_t x, uint32_t x32) {
   uint64_t xj = 1;
@@ -329,10 +329,7 @@ void fill_tab(PfTab* tb, uint64_t x, uint32_t x32) {
   for (int j = 1; j <= 7; ++j) {
     xj = host_mul61(xj, x);
     yj *= x32;
-    for (int b = 0; b < 256; ++b) {
-      tb->g61[j - 1][b] = host_mul61(xj, (uint64_t)b);
-      tb->g32[j - 1][b] = yj * (uint32_t)b;
-    }
+    for (int b = 0; b < 256; ++b) tb->g61[j - 1][b] = host_mul61(xj, (uint64_t)b);
   }
   tb->x1_61 = x;
   tb->x8_61 = host_mul61(xj, x);

@@ -8,19 +8,18 @@
 namespace bt {
 
 // ---- prefix fingerprints (step a2) ----
-constexpr int kPfThreads = 256;
+constexpr int kPfThreads = 512;
 constexpr int kPfBytes = 64;                            // consecutive bytes per thread
-constexpr uint64_t kPfTile = kPfThreads * kPfBytes;     // bytes per tile (16 KiB)
+constexpr uint64_t kPfTile = kPfThreads * kPfBytes;     // bytes per tile (32 KiB)
 
 // Tables of the prefix scan for one pair of bases, computed on the host: x mod
 // 2^61-1 (the fingerprints) and x32 mod 2^32 (the pre-filter hashes).
 struct PfTab {
-  uint64_t g61[7][256];          // b x^j, j = 1..7 (row j - 1), b = 0..255
+  uint64_t g61[7][256];          // b x^j mod 2^61 - 1, j = 1..7 (row j - 1), b = 0..255
   uint64_t t61[kPfThreads + 1];  // x^(64 k), k = 0..256
   uint64_t xt61[65];             // x^(tile k), k = 0..64
   uint64_t c61[4];               // x^(16 c), c = 0..3
   uint64_t x1_61, x8_61;         // x, x^8
-  uint32_t g32[7][256];
   uint32_t t32[kPfThreads + 1];
   uint32_t xt32[65];
   uint32_t c32[4];

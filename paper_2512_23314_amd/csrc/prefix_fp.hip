@@ -6,13 +6,13 @@
 //
 // The recurrence is a prefix operation under the associative combine
 // (h1, len1) o (h2, len2) = (h1 * x^len2 + h2, len1 + len2) (Section 2.2, the
-// all-prefix operation).  Workgroups of 256 threads stay resident and take
-// 16 KiB tiles in order from an atomic counter; in a tile each thread owns 64
+// all-prefix operation).  Workgroups of 512 threads stay resident and take
+// 32 KiB tiles in order from an atomic counter; in a tile each thread owns 64
 // consecutive bytes.
-//   1. Fold: the thread's bytes in groups of eight; a group's value
+//   1. Fold: the thread's bytes in groups of eight; a group's fingerprint
 //      sum_k b_k x^(7-k) is seven lookups in LDS tables of b x^j plus one
-//      reduction, and the eight groups join with x^8.  No multiplication per
-//      byte here.
+//      reduction (no multiplication mod 2^61 - 1 per byte), its 32-bit hash
+//      eight multiply-adds; the eight groups join with x^8.
 //   2. A wave64 shuffle scan and a 4-entry LDS pass give each thread the fold
 //      of the tile before it, and the tile aggregate.
 //   3. The tile's carry-in comes from a decoupled look-back over the tile
@@ -20,7 +20,7 @@
 //      prefix ready); wave 0 runs it for the fingerprints and wave 1 for the
 //      32-bit hashes, side by side.
 //   4. Outputs: every 16th value (the thread's prefix times x^(16 c) plus the
-//      folds of step 1) goes to LDS; then, row by row (4 KiB of the tile), each
+//      folds of step 1) goes to LDS; then, row by row (16 bytes per thread), each
 //      thread runs 16 Horner steps from one of them (one multiply-add per
 //      output), and each wave stages its outputs in LDS so that its stores are
 //      lane-contiguous.  The sampled form stores every 16th value only:
@@ -34,6 +34,7 @@ namespace bt {
 namespace {
 
 constexpr unsigned kPfGrid = 1024;  // resident workgroups
+constexpr uint64_t kPfRow = (uint64_t)kPfThreads * 16;  // step-4 row: 16 bytes per thread
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -115,7 +116,6 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
     const PfTab* __restrict__ tb, uint64_t* __restrict__ st61, uint64_t* __restrict__ st32,
     uint32_t* __restrict__ ctr, uint64_t tiles) {
   __shared__ uint64_t s_g61[7 * 256];
-  __shared__ uint32_t s_g32[WH ? 7 * 256 : 1];
   __shared__ uint64_t s_w61[kPfThreads / 64];
   __shared__ uint32_t s_w32[kPfThreads / 64];
   __shared__ uint64_t s_ex61;
@@ -130,10 +130,7 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ uint64_t s_out[(DENSE || WH) ? (kPfThreads / 64) * 64 * 9 : 1];
 
   const int t0 = threadIdx.x;
-  for (int k = t0; k < 7 * 256; k += kPfThreads) {
-    s_g61[k] = (&tb->g61[0][0])[k];
-    if (WH) s_g32[k] = (&tb->g32[0][0])[k];
-  }
+  for (int k = t0; k < 7 * 256; k += kPfThreads) s_g61[k] = (&tb->g61[0][0])[k];
   const uint64_t x1 = tb->x1_61, x8 = tb->x8_61;
   const uint32_t y1 = tb->x1_32, y8 = tb->x8_32;
   const bool t_al = (reinterpret_cast<uintptr_t>(T) & 15) == 0;
@@ -181,12 +178,15 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       uint64_t g = byte_at(8 * q + 7);
-      uint32_t g32 = byte_at(8 * q + 7);
 #pragma unroll
-      for (int j = 1; j < 8; ++j) {
-        const uint32_t b = byte_at(8 * q + 7 - j);
-        g += s_g61[(j - 1) * 256 + b];  // eight terms below 2^61: no overflow
-        if (WH) g32 += s_g32[(j - 1) * 256 + b];
+      for (int j = 1; j < 8; ++j)
+        g += s_g61[(j - 1) * 256 + byte_at(8 * q + 7 - j)];  // eight terms below 2^61
+      // the 32-bit hash by Horner's rule: a 32-bit multiply-add per byte is
+      // cheaper than a lookup in the one LDS pipe the workgroup shares
+      uint32_t g32 = 0;
+      if (WH) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g32 = g32 * y1 + byte_at(8 * q + k);
       }
       g = fold61(g);
       h61 = q ? mad61(h61, x8, g) : g;
@@ -199,10 +199,10 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
       __builtin_amdgcn_sched_barrier(0);
     }
 
-    // 16 bytes of a row of step 4 (row r: tile offset 4096 r + 16 t)
+    // 16 bytes of a row of step 4 (row r: tile offset kPfRow r + 16 t)
     const uint64_t tb0 = tile * kPfTile;
     const auto load_row = [&](int r, uint32_t* bw) {
-      const uint64_t q = tb0 + 4096 * r + 16 * (uint64_t)t;
+      const uint64_t q = tb0 + kPfRow * r + 16 * (uint64_t)t;
 #pragma unroll
       for (int e = 0; e < 4; ++e) bw[e] = 0;
       if (t_al && q + 16 <= n) {
@@ -278,8 +278,8 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
 
     // 4. chain starts, then outputs.  Thread t of the contiguous layout holds
     // P[pos + 16 c] = C x^(16 c) + F[c].  The outputs are written in rows of
-    // 4 KiB: in row r thread t runs the 16 Horner steps from tile offset
-    // 4096 r + 16 t, and each wave stages its 64 chains in LDS so that every
+    // 16 bytes per thread: in row r thread t runs the 16 Horner steps from tile offset
+    // kPfRow r + 16 t, and each wave stages its 64 chains in LDS so that every
     // store instruction covers whole 64-byte runs (lane-contiguous).
     {
       uint64_t v[4];
@@ -314,15 +314,15 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
       uint32_t* so32 = reinterpret_cast<uint32_t*>(so);
 #pragma unroll 1
       for (int r = 0; r < 4; ++r) {
-        const uint64_t q = tb0 + 4096 * r + 16 * (uint64_t)t;  // this thread's 16 bytes
-        const uint64_t wbase = tb0 + 4096 * r + 1024 * (uint64_t)wv;  // the wave's 1024
+        const uint64_t q = tb0 + kPfRow * r + 16 * (uint64_t)t;  // this thread's 16 bytes
+        const uint64_t wbase = tb0 + kPfRow * r + 1024 * (uint64_t)wv;  // the wave's 1024
         uint32_t nx[4];  // the next row's bytes, requested one row ahead
         if (r < 3) load_row(r + 1, nx);
         const auto rb = [&](int k) { return (rw[k >> 2] >> (8 * (k & 3))) & 0xFFu; };
         if (DENSE) {
           // two halves of eight steps: P[q + 8 h + k] to row `lane`, then the
           // wave stores 512 values, runs of eight (64 bytes) per lane group
-          uint64_t val = s_st61[256 * r + t];
+          uint64_t val = s_st61[kPfThreads * r + t];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
           if (q + 16 == n) P[n] = val;
         }
         if (WH) {
-          uint32_t val = s_st32[256 * r + t];
+          uint32_t val = s_st32[kPfThreads * r + t];
 #pragma unroll
           for (int k = 0; k < 16; ++k) {
             so32[lane * 17 + k] = val;
