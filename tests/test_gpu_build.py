@@ -28,10 +28,10 @@ def _build(ctx, T, tau, leaf, sigma=256, **kw):
 
 # ---- step a2: prefix fingerprints
 
-# sizes around a thread's 16 bytes, a 4 KiB row, a 16 KiB tile, and enough tiles
-# for the look-back to cross more than one window of 64 tiles
+# sizes around a thread's 64 bytes, a row of the output pass (8 KiB), a 32 KiB
+# tile, and enough tiles for the look-back to cross more than one window of 64
 @pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4095, 4096, 4097, 12289, 16383, 16384, 16385,
-                               65536 * 3 + 7, (1 << 20) + 13, (5 << 20) + 1])
+                               32767, 32768, 32769, 65536 * 3 + 7, (1 << 20) + 13, (5 << 20) + 1])
 def test_prefix_fingerprints(ctx, n):
     rng = np.random.default_rng(n + 1)
     T = rng.integers(0, 256, n).astype(np.uint8)
@@ -64,8 +64,8 @@ def test_prefix_fingerprints_misaligned_output(ctx):
 # both prefix arrays in one pass (the builds' form): dense or sampled
 # fingerprints, and the 32-bit hashes against their recurrence
 @pytest.mark.parametrize("sampled", [False, True], ids=["dense", "sampled"])
-@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 63, 64, 65, 4095, 16383, 16384, 16385, 32768,
-                               65536 * 3 + 7, (5 << 20) + 1])
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 63, 64, 65, 4095, 8191, 8192, 16385, 32767, 32768,
+                               32769, 65536 * 3 + 7, (5 << 20) + 1])
 def test_prefix_scan(ctx, n, sampled):
     rng = np.random.default_rng(n + 7)
     T = rng.integers(0, 256, n).astype(np.uint8)
