@@ -912,6 +912,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.P = P;
     a.Ps = lean ? d_P.p : nullptr;
     a.pbase = o0;
+    a.pend = offs[T];
     a.P32 = H32;
     a.tx = tx;
     a.lv = lv;

@@ -116,12 +116,35 @@ __device__ __forceinline__ uint32_t prefix8_bit(uint32_t lo, uint32_t hi, uint32
 
 // P[i] from prefix fingerprints sampled every 16 positions (Ps[q] = P[base +
 // 16 q]): the sample at or below i, then Horner's rule over the bytes between.
+// The up to 15 bytes come from three aligned 8-byte loads issued together (one
+// dependent byte load per step would wait a memory round trip each), when the
+// words lie inside the text [.., end); else byte by byte.
 __device__ __forceinline__ uint64_t prefix_at(const uint64_t* __restrict__ Ps,
                                               const uint8_t* __restrict__ T, uint64_t base,
-                                              uint64_t x, uint64_t i) {
+                                              uint64_t end, uint64_t x, uint64_t i) {
   const uint64_t r = i - base;
+  const uint32_t m = (uint32_t)(r & 15);
   uint64_t v = Ps[r >> 4];
-  for (uint64_t j = i - (r & 15); j < i; ++j) v = add61(mul61(v, x), T[j]);
+  if (!m) return v;
+  const uint64_t j0 = i - m;
+  if (j0 + 24 <= end) {
+    // the words at the 8-byte boundary at or below T + j0 cover its 16 bytes
+    // (and start no lower than the allocation, whose base is aligned)
+    const uintptr_t ad = reinterpret_cast<uintptr_t>(T + j0);
+    const uint64_t* wp = reinterpret_cast<const uint64_t*>(ad & ~(uintptr_t)7);
+    const uint32_t sh = (uint32_t)(ad & 7) * 8;
+    const uint64_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
+    const uint64_t lo = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;  // bytes j0 .. j0+7
+    const uint64_t hi = sh ? (w1 >> sh) | (w2 << (64 - sh)) : w1;  // bytes j0+8 .. j0+15
+#pragma unroll
+    for (uint32_t k = 0; k < 15; ++k) {
+      if (k >= m) break;
+      const uint64_t b = ((k < 8 ? lo : hi) >> (8 * (k & 7))) & 0xFF;
+      v = mad61(v, x, b);
+    }
+    return v;
+  }
+  for (uint64_t j = j0; j < i; ++j) v = mad61(v, x, T[j]);
   return v;
 }
 

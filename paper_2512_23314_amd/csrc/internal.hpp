@@ -100,6 +100,7 @@ struct PhaseArgs {
   const uint64_t* P;      // prefix fingerprints by text position, or null when sampled:
   const uint64_t* Ps;     // Ps[q] = P[pbase + 16 q] (memory-lean builds)
   uint64_t pbase;
+  uint64_t pend;          // end of the text bytes (offset), for the lean loads
   TextsDev tx;
   LevelDev lv;
   KeysDev k;

@@ -10,8 +10,8 @@ namespace bt {
 template <bool LEAN>
 __device__ __forceinline__ uint64_t win61(const PhaseArgs& a, uint64_t i, uint64_t L, uint64_t xL) {
   if (LEAN)
-    return sub61(prefix_at(a.Ps, a.T, a.pbase, a.x, i + L),
-                 mul61(prefix_at(a.Ps, a.T, a.pbase, a.x, i), xL));
+    return sub61(prefix_at(a.Ps, a.T, a.pbase, a.pend, a.x, i + L),
+                 mul61(prefix_at(a.Ps, a.T, a.pbase, a.pend, a.x, i), xL));
   return sub61(a.P[i + L], mul61(a.P[i], xL));
 }
 __device__ __forceinline__ uint64_t win61_any(const PhaseArgs& a, uint64_t i, uint64_t L,
