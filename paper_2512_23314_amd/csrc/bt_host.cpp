@@ -965,9 +965,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
                              !(prm.debug_flags & BT_DBG_NO_QUEUE);
       if (can_queue) {
         scan_mode = 1;
-        if (nkeys >= (1ull << 14)) {
-          f2words = 11;
-          while (f2words < 19 && (32ull << f2words) < 16 * nkeys) ++f2words;
+        if (nkeys >= (1ull << 14)) {  // 64-bit words, about 16 bits per key
+          f2words = 10;
+          while (f2words < 18 && (64ull << f2words) < 16 * nkeys) ++f2words;
         }
       } else {
         scan_mode = 2;
@@ -1006,7 +1006,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         f.add(oddb.p, 14 * (uint64_t)T, 0);
         f.add(vcnt.p, 4, 0);
         f.add(filt.p, (1ull << (byte_scan ? bbits : fbits)) / 32, 0);
-        if (f2words) f.add(filt2.p, 1ull << f2words, 0);
+        if (f2words) f.add(filt2.p, 2ull << f2words, 0);
         HIPCHK(ctx, launch_fill_many(f, s));
       }
       HIPCHK(ctx, launch_keys(a, s));

@@ -95,16 +95,16 @@ __device__ __forceinline__ uint32_t filter_bit32b(uint32_t h, uint32_t bits) {
   return (h * 0x9E3779B1u) >> (32 - bits);
 }
 
-// Second (global, L2-resident) filter of a 32-bit window hash: blocked, both
-// bits in one 32-bit word, so that a test is one load.  The word and the two
-// bit positions come from multiplicative hashes with their own odd constants,
-// unrelated to the bits the LDS filter takes.  words_log2 = log2(words).
+// Second (global, L2-resident) filter of a 32-bit window hash: blocked, three
+// bits in one 64-bit word, so that a test is one load.  The word and the bit
+// positions come from multiplicative hashes with their own odd constants,
+// unrelated to the bits the LDS filter takes.  words_log2 = log2(64-bit words).
 __device__ __forceinline__ uint32_t filter2_word(uint32_t h, uint32_t words_log2) {
   return (h * 0x6F4F2A35u) >> (32 - words_log2);
 }
-__device__ __forceinline__ uint32_t filter2_mask(uint32_t h) {
+__device__ __forceinline__ uint64_t filter2_mask(uint32_t h) {
   const uint32_t m = h * 0xD35A2D97u;
-  return (1u << (m >> 27)) | (1u << ((m >> 22) & 31));
+  return (1ull << (m >> 26)) | (1ull << ((m >> 20) & 63)) | (1ull << ((m >> 14) & 63));
 }
 
 // Filter bit of a string's first eight bytes (lo = bytes 0..3, hi = bytes

@@ -124,7 +124,7 @@ struct PhaseArgs {
   uint32_t x32;         // the 32-bit hash's base
   uint32_t pre32;
   // With pre32: a second, blocked bit filter of the keys' 32-bit hashes in
-  // global memory (2^filt2_words 32-bit words, two bits of one word per key;
+  // global memory (2^filt2_words 64-bit words, three bits of one word per key;
   // 0 = none), tested by the windows that pass the LDS filter before they are
   // queued.
   uint32_t* filt2;

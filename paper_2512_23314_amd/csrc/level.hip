@@ -113,7 +113,8 @@ __global__ void k_keys(PhaseArgs a) {
           f1 = filter_bit32(h, a.filt_bits);
           f2 = filter_bit32b(h, a.filt_bits);
           if (a.filt2_words)
-            atomicOr(&a.filt2[filter2_word(h, a.filt2_words)], filter2_mask(h));
+            atomicOr(reinterpret_cast<unsigned long long*>(a.filt2) + filter2_word(h, a.filt2_words),
+                     (unsigned long long)filter2_mask(h));
         } else {
           f1 = filter_bit(fp, a.filt_bits);
           f2 = filter_bit2(fp, a.filt_bits);
@@ -518,10 +519,10 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     const uint32_t b1 = filter_bit32(h, fbits);
     return filter_has(s_filt, b1, two ? filter_bit32b(h, fbits) : b1);
   };
-  const uint32_t* __restrict__ filt2 = a.filt2;
+  const uint64_t* __restrict__ filt2 = reinterpret_cast<const uint64_t*>(a.filt2);
   const uint32_t f2words = a.filt2_words;
   const auto pass2 = [&](uint32_t h) {
-    const uint32_t m = filter2_mask(h);
+    const uint64_t m = filter2_mask(h);
     return (filt2[filter2_word(h, f2words)] & m) == m;
   };
   const auto pass61 = [&](uint64_t f) {
@@ -624,12 +625,12 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
             for (int k = 0; k < 8; ++k) ok[k] = pass32(hv[k]);
             if (f2words) {
               // second filter: the eight steps' loads are issued together
-              uint32_t wv[8];
+              uint64_t wv[8];
 #pragma unroll
-              for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? filt2[filter2_word(hv[k], f2words)] : ~0u;
+              for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? filt2[filter2_word(hv[k], f2words)] : ~0ull;
 #pragma unroll
               for (int k = 0; k < 8; ++k) {
-                const uint32_t m = filter2_mask(hv[k]);
+                const uint64_t m = filter2_mask(hv[k]);
                 ok[k] = ok[k] && (wv[k] & m) == m;
               }
             }
