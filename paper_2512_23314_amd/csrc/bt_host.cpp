@@ -953,7 +953,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       // 32-bit pre-filter hash and queues its candidates (mode 1); from 2^14
       // keys on, where the LDS filter starts to pass a sizeable share of the
       // windows, those also test a blocked second filter in global memory of
-      // about 16 bits per key (at most 2^24 bits, L2-resident; beyond 2^20
+      // about 32 bits per key (at most 2^24 bits, L2-resident; beyond 2^19
       // keys it is what rejects most windows).  Queue entries pack a position
       // below 2^40 and a text below 2^24; past that, a 2^19-bit filter on
       // 61-bit fingerprints without queues (mode 2), where the table's tag
@@ -965,9 +965,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
                              !(prm.debug_flags & BT_DBG_NO_QUEUE);
       if (can_queue) {
         scan_mode = 1;
-        if (nkeys >= (1ull << 14)) {  // 64-bit words, about 16 bits per key
+        if (nkeys >= (1ull << 14)) {  // 64-bit words, about 32 bits per key
           f2words = 10;
-          while (f2words < 18 && (64ull << f2words) < 16 * nkeys) ++f2words;
+          while (f2words < 18 && (64ull << f2words) < 32 * nkeys) ++f2words;
         }
       } else {
         scan_mode = 2;
