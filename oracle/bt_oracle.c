@@ -43,22 +43,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORA_OK = 0, ORA_E_INVAL = -1, ORA_E_NOMEM = -2, ORA_E_LEMMA = -3 };
-
-typedef struct {
-  uint64_t b, c, u;     /* block length, #blocks, #unmarked */
-  uint64_t *st, *len;   /* block starts and lengths (c each) */
-  uint8_t *marked;      /* c bytes, 0/1 */
-  uint64_t *pb, *po;    /* pointers of unmarked blocks in block order (u each) */
-} olevel;
-
-typedef struct {
-  uint64_t n, b1;
-  uint32_t tau, leaf, h;
-  olevel *lv;           /* h levels; the last holds the leaves */
-  uint8_t *leaves;      /* concatenated leaf bytes */
-  uint64_t leaf_bytes;
-} otree;
+#include "ora_tree.h"
 
 /* ---- level plan (build parameters; see the header for the policy) ---- */
 
@@ -127,7 +112,7 @@ static uint64_t leftmost_in_runs(const uint8_t *T, uint64_t st, uint64_t L,
 
 /* ---- construction ---- */
 
-static void free_tree(otree *t) {
+void ora_free_tree(otree *t) {
   if (!t) return;
   if (t->lv) {
     for (uint32_t l = 0; l < t->h; ++l) {
@@ -164,7 +149,7 @@ void *ora_build(const uint8_t *T, uint64_t n, uint32_t tau, uint32_t leaf,
   uint64_t c = n ? (n + b1 - 1) / b1 : 0;
   uint64_t *st = malloc((c ? c : 1) * sizeof(uint64_t));
   uint64_t *len = malloc((c ? c : 1) * sizeof(uint64_t));
-  if (!st || !len) { free(st); free(len); free_tree(t); *err = ORA_E_NOMEM; return NULL; }
+  if (!st || !len) { free(st); free(len); ora_free_tree(t); *err = ORA_E_NOMEM; return NULL; }
   for (uint64_t j = 0; j < c; ++j) {
     st[j] = j * b1;
     len[j] = (n - st[j] < b1) ? n - st[j] : b1;
@@ -175,20 +160,20 @@ void *ora_build(const uint8_t *T, uint64_t n, uint32_t tau, uint32_t leaf,
     olevel *L = &t->lv[l];
     L->b = b; L->c = c; L->st = st; L->len = len;
     L->marked = calloc(c ? c : 1, 1);
-    if (!L->marked) { free_tree(t); *err = ORA_E_NOMEM; return NULL; }
+    if (!L->marked) { ora_free_tree(t); *err = ORA_E_NOMEM; return NULL; }
     if (l == hmax - 1) {
       /* leaves: every block of the last level, stored explicitly */
       uint64_t tot = 0;
       for (uint64_t j = 0; j < c; ++j) tot += len[j];
       t->leaves = malloc(tot ? tot : 1);
-      if (!t->leaves) { free_tree(t); *err = ORA_E_NOMEM; return NULL; }
+      if (!t->leaves) { ora_free_tree(t); *err = ORA_E_NOMEM; return NULL; }
       uint64_t o = 0;
       for (uint64_t j = 0; j < c; ++j) { memcpy(t->leaves + o, T + st[j], len[j]); o += len[j]; }
       t->leaf_bytes = tot;
       break;
     }
     uint8_t *adj = calloc(c ? c : 1, 1);
-    if (!adj) { free_tree(t); *err = ORA_E_NOMEM; return NULL; }
+    if (!adj) { ora_free_tree(t); *err = ORA_E_NOMEM; return NULL; }
     for (uint64_t j = 0; j + 1 < c; ++j) adj[j] = (st[j + 1] == st[j] + len[j]);
 
     /* runs of consecutive blocks, for the restricted search scope */
@@ -196,7 +181,7 @@ void *ora_build(const uint8_t *T, uint64_t n, uint32_t tau, uint32_t leaf,
     if (search == 2) {
       rs = malloc((c ? c : 1) * sizeof(uint64_t));
       re = malloc((c ? c : 1) * sizeof(uint64_t));
-      if (!rs || !re) { free(adj); free(rs); free(re); free_tree(t); *err = ORA_E_NOMEM; return NULL; }
+      if (!rs || !re) { free(adj); free(rs); free(re); ora_free_tree(t); *err = ORA_E_NOMEM; return NULL; }
       for (uint64_t j = 0; j < c; ++j) {
         if (j == 0 || !adj[j - 1]) { rs[R] = st[j]; re[R] = st[j] + len[j]; ++R; }
         else re[R - 1] = st[j] + len[j];
@@ -221,7 +206,7 @@ void *ora_build(const uint8_t *T, uint64_t n, uint32_t tau, uint32_t leaf,
     L->u = u;
     L->pb = malloc((u ? u : 1) * sizeof(uint64_t));
     L->po = malloc((u ? u : 1) * sizeof(uint64_t));
-    if (!L->pb || !L->po) { free(adj); free(rs); free(re); free_tree(t); *err = ORA_E_NOMEM; return NULL; }
+    if (!L->pb || !L->po) { free(adj); free(rs); free(re); ora_free_tree(t); *err = ORA_E_NOMEM; return NULL; }
     uint64_t k = 0;
     for (uint64_t j = 0; j < c; ++j) {
       if (L->marked[j]) continue;
@@ -254,7 +239,7 @@ void *ora_build(const uint8_t *T, uint64_t n, uint32_t tau, uint32_t leaf,
       if (L->marked[j]) nc += (len[j] + nb - 1) / nb;
     uint64_t *nst = malloc((nc ? nc : 1) * sizeof(uint64_t));
     uint64_t *nlen = malloc((nc ? nc : 1) * sizeof(uint64_t));
-    if (!nst || !nlen) { free(nst); free(nlen); free_tree(t); *err = ORA_E_NOMEM; return NULL; }
+    if (!nst || !nlen) { free(nst); free(nlen); ora_free_tree(t); *err = ORA_E_NOMEM; return NULL; }
     uint64_t q = 0;
     for (uint64_t j = 0; j < c; ++j) {
       if (!L->marked[j]) continue;
@@ -399,7 +384,7 @@ int ora_prune(void *hdl, const uint8_t *T) {
   return rc;
 }
 
-void ora_free(void *h) { free_tree((otree *)h); }
+void ora_free(void *h) { ora_free_tree((otree *)h); }
 
 int ora_tree_info(void *h, uint64_t *n, uint32_t *height, uint64_t *b1, uint64_t *leaf_bytes) {
   otree *t = h;

@@ -20,6 +20,8 @@ from .texts import (  # noqa: F401
     cfg3_text,
     batch_lengths,
     batch_texts,
+    batch_text,
+    batch_lengths_of,
     serving_sizes,
     random_text,
     periodic_text,

@@ -172,18 +172,34 @@ def batch_lengths(count=4096, median=1 << 18, sigma_ln=1.665, lo=1 << 12, hi=1 <
     return np.clip(np.round(x), lo, hi).astype(np.int64)
 
 
-def batch_texts(count=4096, seed=CFG_SEEDS[4], **kw):
-    """Independent texts of lognormal lengths, each generated like the 1 MiB DNA
-    text (base = len/16, 16 copies) with its own seed and a substitution rate
-    drawn from U[0.01%, 1%] (indel rate a tenth of it)."""
+def _batch_params(count, seed, **kw):
     lens = batch_lengths(count, seed=seed, **kw)
     rng = _rng(seed + 1)
     rates = rng.uniform(1e-4, 1e-2, count)
     seeds = rng.integers(0, 2**62, count)
+    return lens.tolist(), rates.tolist(), seeds.tolist()
+
+
+def batch_texts(count=4096, seed=CFG_SEEDS[4], **kw):
+    """Independent texts of lognormal lengths, each generated like the 1 MiB DNA
+    text (base = len/16, 16 copies) with its own seed and a substitution rate
+    drawn from U[0.01%, 1%] (indel rate a tenth of it)."""
     out = []
-    for n, r, s in zip(lens.tolist(), rates.tolist(), seeds.tolist()):
+    for n, r, s in zip(*_batch_params(count, seed, **kw)):
         out.append(dna_copies(n, max(1, n // 16), 16, r, r / 10, 8, int(s)))
     return out
+
+
+def batch_text(i, count=4096, seed=CFG_SEEDS[4], **kw):
+    """Text i of batch_texts(count, seed, ...), generated alone."""
+    lens, rates, seeds = _batch_params(count, seed, **kw)
+    n, r, s = lens[i], rates[i], seeds[i]
+    return dna_copies(n, max(1, n // 16), 16, r, r / 10, 8, int(s))
+
+
+def batch_lengths_of(count=4096, seed=CFG_SEEDS[4], **kw):
+    """The lengths of batch_texts(count, seed, ...), without generating them."""
+    return _batch_params(count, seed, **kw)[0]
 
 
 def serving_sizes(count, median=1 << 18, sigma_ln=2.0, lo=1 << 10, hi=1 << 28, seed=CFG_SEEDS[5]):

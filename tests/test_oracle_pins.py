@@ -431,3 +431,91 @@ def test_pruned_random_small():
         for tau, leaf in ((2, 1), (3, 1), (2, 2)):
             t = oracle.build_tree(T, tau, leaf, prune=True)
             treecheck.check_pruned(treecheck.from_oracle(t), T)
+
+
+def _decode_canonical(buf):
+    """Read canonical tree bytes field by field, following the layout the C ABI
+    documents for bt_serialize (little-endian):
+      "BTv1", u64 n, u32 tau, u32 leaf_len, u64 b1, u32 h, u32 0,
+      per level l < h: u64 b, u64 c, ceil(c/64) u64 mark words (bit j%64 of word
+        j/64 is block j, pad bits zero), u64 u, u64 ptr_block[u], u64 ptr_off[u];
+      level h: u64 b, u64 c, u64 leaf byte count, the leaf bytes, zeros to a
+        multiple of 8."""
+    import struct
+    at = 0
+
+    def take(fmt):
+        nonlocal at
+        v = struct.unpack_from("<" + fmt, buf, at)
+        at += struct.calcsize("<" + fmt)
+        return v
+
+    assert buf[:4] == b"BTv1"
+    at = 4
+    n, tau, leaf, b1, h, zero = take("QIIQII")
+    assert zero == 0
+    levels = []
+    for _ in range(h - 1):
+        b, c = take("QQ")
+        words = take("%dQ" % ((c + 63) // 64)) if c else ()
+        marked = [(words[j // 64] >> (j % 64)) & 1 for j in range(c)]
+        used = c - 64 * (len(words) - 1)          # bits used in the last word
+        if words and used < 64:
+            assert words[-1] >> used == 0, "pad bits set"
+        (u,) = take("Q")
+        pb = list(take("%dQ" % u)) if u else []
+        po = list(take("%dQ" % u)) if u else []
+        levels.append((b, c, marked, pb, po))
+    b, c, nb = take("QQQ")
+    leaves = bytes(buf[at:at + nb])
+    at += nb
+    pad = (8 - nb % 8) % 8
+    assert buf[at:at + pad] == b"\0" * pad
+    at += pad
+    assert at == len(buf), "trailing bytes"
+    return (n, tau, leaf, b1, h), levels, (b, c), leaves
+
+
+def test_canonical_layout_fig1():
+    """The canonical bytes of Figure 1's trees (Section 4), decoded field by field
+    against the documented layout, hold exactly the fixture's rows; the total
+    size is the sum of the documented field sizes."""
+    spec, rows, leaves = _load_fig1()
+    T = spec["text"].encode()
+    for kind, prune in (("unpruned", False), ("pruned", True)):
+        t = oracle.build_tree(T, int(spec["tau"]), int(spec["leaf"]), b1=int(spec["b1"]),
+                              exact_split=False, prune=prune)
+        head, levels, last, lv = _decode_canonical(t.canonical)
+        assert head == (12, 3, 1, 6, 3)
+        assert len(levels) == 2
+        for (b, c, marked, pb, po), (rb, rmarked, rptr) in zip(levels, rows[kind]):
+            assert b == rb and c == len(rmarked) and marked == rmarked
+            assert list(zip(pb, po)) == rptr
+        assert last == (1, len(leaves[kind])) and lv == leaves[kind]
+        # header 36, level 1: b c word u = 32, level 2: 24 + 8 + 8 + 16 u
+        size = 36 + 32 + (32 + 16 * len(rows[kind][1][2])) + 24 + len(lv) + (8 - len(lv) % 8) % 8
+        assert len(t.canonical) == size
+
+
+def test_canonical_layout_multiword():
+    """A tree with more than 64 blocks on a level: mark words split at bit 64,
+    pointer arrays in block order, pad bits zero."""
+    T = synth.cfg1_text(1 << 14)
+    t = oracle.build_tree(T, 2, 16, s_hint=100)
+    head, levels, last, lv = _decode_canonical(t.canonical)
+    assert head == (t.n, 2, 16, t.b1, t.h)
+    assert any(c > 64 for _, c, _, _, _ in levels)
+    for (b, c, marked, pb, po), L in zip(levels, t.levels):
+        assert (b, c) == (L.b, L.c) and marked == L.marked.tolist()
+        assert pb == L.ptr_block.tolist() and po == L.ptr_off.tolist()
+    assert lv == t.leaves.tobytes()
+
+
+@pytest.mark.parametrize("s_hint", [1, 64])
+def test_literal_double_loop_16k(s_hint):
+    """The literal double loop (no library search) on the first 16 KiB of the
+    1 MiB DNA text gives the same tree as memmem."""
+    T = synth.cfg1_text()[:1 << 14]
+    a = oracle.build_tree(T, 2, 16, s_hint=s_hint, search=oracle.SEARCH_NAIVE)
+    b = oracle.build_tree(T, 2, 16, s_hint=s_hint, search=oracle.SEARCH_MEMMEM)
+    assert a.canonical == b.canonical
