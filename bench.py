@@ -1,27 +1,40 @@
 """Benchmark: block-tree construction throughput on one MI355X.
 
-One step = one complete build (prefix fingerprints, every level's two phases,
-marks, pointers, split, leaves) of the 256 MiB versioned text (sigma = 96,
-tau = 4, leaf_len = 16, one root block), with the text already resident in
-HBM.  Prints one JSON line.
+Default workload (the largest configuration that fits one GPU): 4096
+independent DNA texts of lognormal length, about 3.9 GiB in total (tau = 4,
+leaf_len = 16, one root block per text), built by one bt_build_batch call.  One
+step = one complete batched build (prefix fingerprints, every level's two
+phases, marks, pointers, split, leaves) with the texts already resident in HBM.
+The plain per-text loop (bt_build_ex per text) is timed beside it.  Two legs
+follow, each with its own roofline and parity check: the 2 GiB haplotype
+collection (tau 4, leaf 16) and the 256 MiB versioned text (tau 4, leaf 16),
+the latter with its pruned, memory-lean and sort-phase builds.  Prints one
+JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-The roofline object covers the probe-scan kernel (the sliding-window
-fingerprint probe, the dominant kernel): its algorithmic bytes (the two prefix
-values each window reads: 8 bytes of 32-bit pre-filter hashes, or 16 bytes of
-61-bit prefix fingerprints where the scan does not pre-filter) over its
-HIP-event time on the library's stream.  The cpu_baseline object times the CPU oracle on a bounded
-prefix of the same text.  The pruned_build object times the same build with the
-optional pruning phase (--prune times that as the main step instead); the
-lean_build object times it with sampled prefix fingerprints (--lean) and gives
-both builds' peak device memory; the sort_phase_build object times it with the
-sort-based phases of Section 5.1 in place of the hash-table scan.
+Parity first: every tree a reported number rests on is serialized and its
+SHA-256 compared with the expected tree in tests/golden/ (written by the
+threaded oracle construction, tests/golden/make_fullsize.py).  A mismatch ends
+the run with an error and no JSON line.
+
+The roofline object covers the probe-scan kernel (the sliding-window probe,
+the dominant kernel): its algorithmic bytes over its HIP-event time on the
+library's stream.  Per window it reads two prefix values (4-byte 32-bit
+pre-filter hashes, or 8-byte 61-bit fingerprints where it does not
+pre-filter); a wave's tile of 1024 consecutive windows must fetch the union of
+[i0, i0 + 1024) and [i0 + L, i0 + L + 1024), so a window costs
+4 (1 + min(L, 1024) / 1024) bytes (twice that without the pre-filter).
+
+The cpu_baseline object times the threaded oracle construction (the paper's
+two-phase method, Section 4.1 over a domain decomposition, Section 5.2) on the
+host's cores, on a bounded sample of the same workload, and on one core.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -29,20 +42,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+METRIC = "block-tree build MB/s and KR-scan GB/s (% HBM peak) on 1 MI355X vs CPU oracle"
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 
 WORKLOADS = {
-    # name: (generator, sigma, tau, leaf_len, s_hint, description)
-    "versioned256m": ("cfg2", 96, 4, 16, 1,
+    # name: (generator, sigma, tau, leaf_len, s_hint, expected-tree entry, description)
+    "batch4096": ("cfg4", 4, 4, 16, 1, "batch4096",
+                  "4096 DNA texts, lognormal lengths (median 256 KiB, 4 KiB-64 MiB, ~3.9 GiB), "
+                  "each 16 mutated copies of a base: one batched build vs a loop of single builds"),
+    "dna2g": ("cfg3", 4, 4, 16, 1, "dna2g_t4_l16",
+              "2 GiB DNA collection, sigma 4: 256 haplotypes of an 8 MiB reference, 0.1% SNPs, "
+              "0.01% indels of length 1-20"),
+    "versioned256m": ("cfg2", 96, 4, 16, 1, "versioned256m",
                       "256 MiB versioned text, sigma 96: 1024 versions of a 256 KiB order-2 "
                       "Markov document, 0.05% edit runs per version"),
-    "versioned256m_s": ("cfg2", 96, 4, 16, 1 << 19,
+    "versioned256m_s": ("cfg2", 96, 4, 16, 1 << 19, "versioned256m_s",
                         "same text, about 2^19 root blocks (b1 = 256)"),
-    "dna1m": ("cfg1", 4, 2, 16, 1, "1 MiB DNA: 16 mutated copies of a 64 KiB base"),
-    "dna1m_s": ("cfg1", 4, 2, 16, 10000, "1 MiB DNA, s about 10^4 (b1 = 64)"),
-    "batch4096": ("cfg4", 4, 4, 16, 1,
-                  "4096 DNA texts, lognormal lengths (median 256 KiB, 4 KiB-64 MiB, ~3.9 GiB): "
-                  "one batched build vs a loop of single builds"),
-    "serve": ("cfg5", 4, 4, 16, 1,
+    "dna1m": ("cfg1", 4, 2, 16, 1, "dna1m", "1 MiB DNA: 16 mutated copies of a 64 KiB base"),
+    "dna1m_s": ("cfg1", 4, 2, 16, 10000, "dna1m_s", "1 MiB DNA, s about 10^4 (b1 = 64)"),
+    "serve": ("cfg5", 4, 4, 16, 1, None,
               "serving: Poisson build requests (lognormal sizes, median 256 KiB, 1 KiB-256 MiB, "
               "DNA texts) at 0.8x measured capacity, interleaved 1M-query batches"),
 }
@@ -54,24 +72,104 @@ def log(*a):
 
 def make_text(gen):
     import synth
-    return {"cfg1": synth.cfg1_text, "cfg2": synth.cfg2_text}[gen]()
+    return {"cfg1": synth.cfg1_text, "cfg2": synth.cfg2_text, "cfg3": synth.cfg3_text}[gen]()
 
 
-def traffic_record(kernel):
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def host_threads():
+    """CPUs this process may use, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+# ---------------------------------------------------------------- parity
+
+class ParityError(RuntimeError):
+    pass
+
+
+def golden_entry(name):
+    with open(os.path.join(GOLDEN_DIR, "fullsize_trees.json")) as f:
+        entries = json.load(f)["entries"]
+    if name not in entries:
+        raise ParityError("no expected tree recorded for %s (tests/golden/make_fullsize.py)" % name)
+    return entries[name]
+
+
+def _sha(b):
+    return hashlib.sha256(b).hexdigest()
+
+
+def check_single(tree, name, T):
+    """The GPU tree's canonical bytes against the expected tree of `name`."""
+    e = golden_entry(name)
+    if _sha(T.tobytes()) != e["input_sha256"]:
+        raise ParityError("%s: the generated input differs from the recorded one" % name)
+    got = _sha(tree.serialize())
+    if got != e["canonical_sha256"]:
+        raise ParityError("%s: GPU tree %s differs from the expected tree %s" % (
+            name, got[:16], e["canonical_sha256"][:16]))
+    return {"expected_tree": "tests/golden/fullsize_trees.json:" + name, "sha256": got,
+            "match": True}
+
+
+def check_batch(trees, name, insha_digest):
+    e = golden_entry(name)
+    if insha_digest != e["input_digest"]:
+        raise ParityError("%s: the generated inputs differ from the recorded ones" % name)
+    want = {}
+    with open(os.path.join(GOLDEN_DIR, e["per_text"])) as f:
+        for line in f:
+            if not line.startswith("#"):
+                i, _, h = line.split()
+                want[int(i)] = h
+    got, bad = [], []
+    for i, tr in enumerate(trees):
+        h = _sha(tr.serialize())
+        got.append(h)
+        if want.get(i) != h[:16]:
+            bad.append(i)
+    digest = _sha("".join(got).encode())
+    if bad or digest != e["tree_digest"]:
+        raise ParityError("%s: %d of %d trees differ from the expected ones (first %s)" % (
+            name, len(bad), len(trees), bad[:8]))
+    return {"expected_tree": "tests/golden/fullsize_trees.json:" + name, "trees": len(trees),
+            "tree_digest": digest, "match": True}
+
+
+# ---------------------------------------------------------------- roofline
+
+def traffic_record(kernel, workload):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "%s_traffic.json" % kernel)
+    it was taken on this workload and on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("workload") != workload:
+        return None
     if "sources" not in rec or _sources_sha(rec["sources"]) != rec.get("source_sha256"):
         return None
     return rec
 
 
-# the files the probe scan is compiled from; a change to any of them retires
-# the traffic record
-PROBE_SOURCES = ["level.hip", "common.hpp", "window.hpp", "internal.hpp"]
+# the files the probe scan is compiled from, and the host code that sizes its
+# launches; a change to any of them retires the traffic record
+PROBE_SOURCES = ["level.hip", "common.hpp", "window.hpp", "internal.hpp", "bt_host.cpp"]
 
 
 def _sources_sha(names):
@@ -80,6 +178,258 @@ def _sources_sha(names):
         with open(os.path.join(ROOT, "paper_2512_23314_amd", "csrc", nm), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def roofline(ctx, steps, workload):
+    ps = ctx.kernel_stats("probe_scan")
+    achieved = ps["bytes"] / ps["ms"] / 1e6 if ps["ms"] > 0 else 0.0
+    tr = traffic_record("probe_scan", workload)
+    traffic = tr.get("bytes_per_launch") if (tr is not None and ps["launches"]) else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "probe_scan",
+            "launches_per_step": ps["launches"] // max(steps, 1),
+            "bytes_per_launch": round(ps["bytes"] / max(ps["launches"], 1)),
+            "avg_launch_ms": round(ps["ms"] / max(ps["launches"], 1), 5)}
+
+
+def kernel_table(ctx, steps):
+    """Per-kernel figures of the timed steps (HIP events on the library stream)."""
+    out = {}
+    for k in ("probe_scan", "byte_scan", "prefix_fp", "verify"):
+        s = ctx.kernel_stats(k)
+        if s["launches"]:
+            out[k] = {"launches_per_step": s["launches"] // max(steps, 1),
+                      "ms_per_step": round(s["ms"] / max(steps, 1), 4),
+                      "algorithmic_GBps": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1)}
+    return out
+
+
+def probe_launches(ctx, steps):
+    """The probe-scan launches of the last timed step: [L, windows, us, bytes]."""
+    rows = [r for r in ctx.launches() if r[0] == "probe_scan"]
+    per = len(rows) // max(steps, 1)
+    return [[int(L), int(u), round(ms * 1e3, 1), int(by)] for _, L, u, ms, by in rows[-per:]] if per else []
+
+
+def base_line(workload, value, ms, steps, warmup, config):
+    return {"metric": METRIC, "value": round(value, 2), "unit": "MB/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": dict({"workload": workload}, **config)}
+
+
+# ---------------------------------------------------------------- CPU baseline
+
+def cpu_baseline_batch(sample_mib, cores):
+    """The threaded oracle construction on the first texts of the batch (in
+    index order) up to sample_mib MiB: texts spread over `cores` host threads,
+    one text per thread at a time; and the first texts up to 1/16 of that on
+    one thread."""
+    import concurrent.futures as cf
+    import oracle
+    import synth
+    lens = synth.batch_lengths_of()
+    pick, tot = [], 0
+    for i, n in enumerate(lens):
+        if tot >= (sample_mib << 20):
+            break
+        pick.append(i)
+        tot += n
+    texts = [synth.batch_text(i) for i in pick]
+
+    def one(T):
+        oracle.build_tree_par(T, 4, 16, threads=1, levels=False)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, sorted(texts, key=lambda t: -t.size)))
+    dt = time.perf_counter() - t0
+    small, stot = [], 0
+    for T in texts:
+        if stot >= tot // 16:
+            break
+        small.append(T)
+        stot += T.size
+    t1 = time.perf_counter()
+    for T in small:
+        one(T)
+    dt1 = time.perf_counter() - t1
+    return {"value": round(tot / dt / 1e6, 3), "unit": "MB/s", "cores": cores, "kind": "oracle",
+            "sample": "texts 0..%d of the batch (%d texts, %.1f MiB), tau 4, leaf 16: the threaded "
+                      "oracle construction, one text per host thread, %d threads, %.1f s"
+                      % (pick[-1], len(pick), tot / 2**20, cores, dt),
+            "one_core": {"value": round(stot / dt1 / 1e6, 3), "unit": "MB/s",
+                         "sample": "the first %d of those texts (%.1f MiB), one thread, %.1f s"
+                                   % (len(small), stot / 2**20, dt1)},
+            "host_cpu": host_cpu(), "host_cpus_visible": os.cpu_count()}
+
+
+def cpu_baseline_single(T, tau, leaf, s_hint, cores, sample_bytes):
+    """The threaded oracle construction on the first sample_bytes of T (all of
+    it when it is shorter) on `cores` threads."""
+    import oracle
+    S = T[:sample_bytes]
+    t0 = time.perf_counter()
+    oracle.build_tree_par(S, tau, leaf, s_hint=s_hint, threads=cores, levels=False)
+    dt = time.perf_counter() - t0
+    what = "the whole text" if S.size == T.size else "the first %d MiB of the text" % (S.size >> 20)
+    return {"value": round(S.size / dt / 1e6, 3), "unit": "MB/s", "cores": cores, "kind": "oracle",
+            "sample": "%s, tau %d, leaf %d, s_hint %d: the threaded oracle construction on %d "
+                      "threads, %.1f s" % (what, tau, leaf, s_hint, cores, dt),
+            "host_cpu": host_cpu(), "host_cpus_visible": os.cpu_count()}
+
+
+# ---------------------------------------------------------------- workloads
+
+def bench_batch(args, sigma, tau, leaf, golden, desc):
+    """Batched build of the 4096 texts (the headline), the plain per-text loop
+    over the same device buffer, parity of every tree, then the legs."""
+    import numpy as np
+    import torch
+    import paper_2512_23314_amd as bt
+    import synth
+    t0 = time.time()
+    texts = synth.batch_texts()
+    offs = np.zeros(len(texts) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(t) for t in texts])
+    insha = _sha("".join(_sha(t.tobytes()) for t in texts).encode())
+    concat = np.concatenate(texts)
+    del texts
+    n = int(offs[-1])
+    log("generated %d texts, %d bytes in %.1f s" % (len(offs) - 1, n, time.time() - t0))
+    d = torch.from_numpy(concat).to("cuda:0")
+    del concat
+    torch.cuda.synchronize()
+    ctx = bt.Context(0)
+
+    def batched():
+        return ctx.build_batch(d, offs, sigma=sigma, tau=tau, leaf_len=leaf)
+
+    for _ in range(args.warmup):
+        for tr in batched():
+            tr.free()
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        trees = batched()
+        if k + 1 < args.steps:
+            for tr in trees:
+                tr.free()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    ctx.profile(False)
+    rf = roofline(ctx, args.steps, "batch4096")
+    kt = kernel_table(ctx, args.steps)
+    pl = probe_launches(ctx, args.steps)
+    if args.launch_log:
+        with open(args.launch_log, "w") as f:
+            json.dump({"workload": "batch4096", "probe_scan": pl}, f)
+    parity = check_batch(trees, golden, insha)
+    for tr in trees:
+        tr.free()
+    log("batched %.1f ms (%.0f MB/s); parity: %d trees equal the expected ones" % (
+        dt * 1e3, n / 1e6 / dt, parity["trees"]))
+    plain = None
+    if not args.no_plain:
+        def loop():
+            for k in range(len(offs) - 1):
+                a, b = int(offs[k]), int(offs[k + 1])
+                ctx.build(d[a:b], sigma=sigma, tau=tau, leaf_len=leaf).free()
+        loop()  # the plain path's allocations
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loop()
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        plain = {"batched_mb_s": round(n / 1e6 / dt, 2), "plain_loop_mb_s": round(n / 1e6 / dtp, 2),
+                 "speedup": round(dtp / dt, 2), "plain_loop_ms": round(dtp * 1e3, 1)}
+        log("plain loop %.1f ms (%.0f MB/s)" % (dtp * 1e3, n / 1e6 / dtp))
+    ctx.close()
+    del d
+    torch.cuda.empty_cache()
+    out = base_line("batch4096", n / 1e6 / dt, dt * 1e3, args.steps, args.warmup,
+                    {"description": desc, "n": n, "texts": len(offs) - 1, "sigma": sigma,
+                     "tau": tau, "leaf_len": leaf, "s_hint": 1})
+    out["roofline"] = rf
+    out["cpu_baseline"] = None
+    out["parity"] = parity
+    if plain is not None:
+        out["batched_vs_plain"] = plain
+    out["kernels"] = kt
+    out["probe_scan_launches"] = {"columns": ["L", "windows", "us", "algorithmic_bytes"], "rows": pl}
+    return out
+
+
+def bench_single(args, workload, steps, warmup, sublegs=False):
+    import torch
+    import paper_2512_23314_amd as bt
+    gen, sigma, tau, leaf, s_hint, golden, desc = WORKLOADS[workload]
+    t0 = time.time()
+    T = make_text(gen)
+    log("generated %s (%d bytes) in %.1f s" % (workload, T.size, time.time() - t0))
+    n = int(T.size)
+    d = torch.from_numpy(T).to("cuda:0")
+    torch.cuda.synchronize()
+    ctx = bt.Context(0)
+
+    def step(prune=args.prune, lean=args.lean, keep=False):
+        tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, prune=prune, lean=lean)
+        if keep:
+            return tree
+        h = tree.height
+        tree.free()
+        return h
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        tree = step(keep=True)
+        if k + 1 < steps:
+            tree.free()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.profile(False)
+    ms = dt / max(steps, 1) * 1e3
+    h = tree.height
+    rf = roofline(ctx, steps, workload)
+    kt = kernel_table(ctx, steps)
+    pl = probe_launches(ctx, steps)
+    if args.launch_log and workload == args.workload:
+        with open(args.launch_log, "w") as f:
+            json.dump({"workload": workload, "probe_scan": pl}, f)
+    parity = None
+    if not args.prune:  # the expected trees are unpruned; lean builds give the same tree
+        parity = check_single(tree, golden, T)
+    tree.free()
+    for k, s in kt.items():
+        log("%-10s %s" % (k, s))
+    out = base_line(workload, n / 1e6 / (ms / 1e3), ms, steps, warmup,
+                    {"description": desc, "n": n, "sigma": sigma, "tau": tau, "leaf_len": leaf,
+                     "s_hint": s_hint, "levels": h, "prune": bool(args.prune),
+                     "lean": bool(args.lean)})
+    out["roofline"] = rf
+    out["parity"] = parity
+    out["kernels"] = kt
+    out["probe_scan_launches"] = {"columns": ["L", "windows", "us", "algorithmic_bytes"], "rows": pl}
+    if sublegs:
+        if not args.prune:
+            out["pruned_build"] = pruned_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
+            log("pruned build: %s" % out["pruned_build"])
+        if not args.lean:
+            out["lean_build"] = lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
+            log("lean build: %s" % out["lean_build"])
+        out["sort_phase_build"] = sort_leg(ctx, d, n, sigma, tau, leaf, s_hint, ms)
+        log("sort-phase build: %s" % out["sort_phase_build"])
+    ctx.close()
+    del d
+    torch.cuda.empty_cache()
+    return out, T
 
 
 # ---------------------------------------------------------------- profile summaries
@@ -205,75 +555,6 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, be
     print("wrote", out_md, out_json)
 
 
-def bench_batch(args, sigma, tau, leaf, desc):
-    """Batched build of 4096 texts vs a loop of single builds over the same
-    device buffer."""
-    import numpy as np
-    import torch
-    import paper_2512_23314_amd as bt
-    import synth
-    t0 = time.time()
-    texts = synth.batch_texts()
-    offs = np.zeros(len(texts) + 1, np.uint64)
-    offs[1:] = np.cumsum([len(t) for t in texts])
-    concat = np.concatenate(texts)
-    del texts
-    n = int(offs[-1])
-    log("generated %d texts, %d bytes in %.1f s" % (len(offs) - 1, n, time.time() - t0))
-    d = torch.from_numpy(concat).to("cuda:0")
-    del concat
-    ctx = bt.Context(0)
-
-    def batched():
-        trees = ctx.build_batch(d, offs, sigma=sigma, tau=tau, leaf_len=leaf)
-        for tr in trees:
-            tr.free()
-
-    def plain():
-        for k in range(len(offs) - 1):
-            a, b = int(offs[k]), int(offs[k + 1])
-            ctx.build(d[a:b], sigma=sigma, tau=tau, leaf_len=leaf).free()
-
-    for _ in range(args.warmup):
-        batched()
-    torch.cuda.synchronize()
-    ctx.reset_stats()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batched()
-    torch.cuda.synchronize()
-    dt_b = (time.perf_counter() - t0) / args.steps
-    ctx.profile(False)
-    ps = ctx.kernel_stats("probe_scan")
-    plain()  # warm the plain path's allocations
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain()
-    torch.cuda.synchronize()
-    dt_p = time.perf_counter() - t0
-    log("batched %.1f ms (%.0f MB/s), plain loop %.1f ms (%.0f MB/s)" % (
-        dt_b * 1e3, n / 1e6 / dt_b, dt_p * 1e3, n / 1e6 / dt_p))
-    achieved = ps["bytes"] / ps["ms"] / 1e6 if ps["ms"] > 0 else 0.0
-    out = {
-        "metric": "block-tree build MB/s and KR-scan GB/s (% HBM peak) on 1 MI355X vs CPU oracle",
-        "value": round(n / 1e6 / dt_b, 2), "unit": "MB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(dt_b * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "batch4096", "description": desc, "n": n, "texts": len(offs) - 1,
-                   "sigma": sigma, "tau": tau, "leaf_len": leaf},
-        "batched_vs_plain": {"batched_mb_s": round(n / 1e6 / dt_b, 2),
-                             "plain_loop_mb_s": round(n / 1e6 / dt_p, 2),
-                             "speedup": round(dt_p / dt_b, 2)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "probe_scan"},
-        "cpu_baseline": None,
-    }
-    print(json.dumps(out), flush=True)
-    ctx.close()
-
-
 def bench_serve(args, sigma, tau, leaf, desc, seconds=10.0):
     """Open-loop serving: Poisson build arrivals at 0.8x the capacity measured by a
     closed-loop burst, 1M-query batches (a third each of access, rank, select)
@@ -352,7 +633,7 @@ def bench_serve(args, sigma, tau, leaf, desc, seconds=10.0):
     served = st["built_bytes"] / wall
     log("served %s" % st)
     out = {
-        "metric": "block-tree build MB/s and KR-scan GB/s (% HBM peak) on 1 MI355X vs CPU oracle",
+        "metric": METRIC,
         "value": round(served / 1e6, 2), "unit": "MB/s", "n_gpus": 1, "steps": len(arrivals),
         "warmup": len(pool), "ms_per_step": round(wall / max(len(arrivals), 1) * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
@@ -447,15 +728,62 @@ def sort_leg(ctx, d, n, sigma, tau, leaf, s_hint, hash_ms, steps=2):
             "slowdown_vs_hashing": round(ms / hash_ms, 2)}
 
 
-def cpu_baseline(T, sigma, tau, leaf, s_hint, sample_bytes):
-    import oracle
-    S = T[:sample_bytes]
-    t0 = time.perf_counter()
-    oracle.build_tree(S, tau, leaf, s_hint=s_hint)
-    dt = time.perf_counter() - t0
-    return {"value": round(S.size / dt / 1e6, 4), "unit": "MB/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d MiB of the same text, same tau/leaf/s, single-threaded oracle "
-                      "(leftmost occurrences by memmem), %.1f s" % (S.size >> 20, dt)}
+def summarize_launches(launch_json, pmc_dirs, calib, cmds, out_md):
+    """Per-launch table of the probe scan for one build: the bench's launch log
+    (window length, windows, HIP-event time, algorithmic bytes) joined in
+    dispatch order with per-dispatch rocprofv3 counters from --pmc runs of the
+    same command.  calib: (copy MiB, fetch dir, write dir) of the copy
+    calibration, or None."""
+    import collections
+    with open(launch_json) as f:
+        rec = json.load(f)
+    rows = rec["probe_scan"]
+    per = collections.OrderedDict()
+    for d in pmc_dirs:
+        for r in _csv_rows(_find_csv(d, "counter_collection.csv")):
+            if "k_probe_scan<" not in r["Kernel_Name"]:
+                continue
+            key = int(r.get("Dispatch_Id", r.get("Correlation_Id", 0)))
+            per.setdefault(r["Counter_Name"], collections.OrderedDict())[key] = float(r["Counter_Value"])
+    counters = {k: [v[x] for x in sorted(v)] for k, v in per.items()}
+    ff = fw = None
+    if calib:
+        mib, cfd, cwd = calib
+        cf, _ = _counter_per_launch(cfd, "copyBuffer")
+        cw, _ = _counter_per_launch(cwd, "copyBuffer")
+        ff, fw = (mib << 20) / (cf * 1024.0), (mib << 20) / (cw * 1024.0)
+    names = sorted(counters)
+    lines = ["# Probe-scan launches, one %s build" % rec["workload"], "",
+             "Commands (repository root, one MI355X, each its own run):", ""]
+    lines += ["    " + c for c in cmds]
+    lines += ["", "Window length L, windows, HIP-event time and algorithmic bytes come from the "
+              "library's launch log (bt_ctx_launch_record); the counters are rocprofv3 --pmc values "
+              "per dispatch, joined in dispatch order."]
+    if ff:
+        lines += ["FETCH_SIZE and WRITE_SIZE are scaled to bytes with the copy calibration "
+                  "(x%.4f and x%.4f)." % (ff, fw)]
+    head = ["#", "L", "windows", "us", "algorithmic GB/s"] + names
+    lines += ["", "| " + " | ".join(head) + " |", "|" + "---:|" * len(head)]
+    for k, (L, w, us, by) in enumerate(rows):
+        cells = [str(k), str(L), str(w), "%.1f" % us, "%.0f" % (by / us / 1e3 if us else 0)]
+        for nm in names:
+            v = counters[nm][k] if k < len(counters[nm]) else float("nan")
+            if nm == "FETCH_SIZE" and ff:
+                cells.append("%.3g B" % (v * 1024 * ff))
+            elif nm == "WRITE_SIZE" and fw:
+                cells.append("%.3g B" % (v * 1024 * fw))
+            else:
+                cells.append("%.4g" % v)
+        lines.append("| " + " | ".join(cells) + " |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
+def leg_view(line):
+    """A leg's own figures, without the fields the main line already states."""
+    drop = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data")
+    return {k: v for k, v in line.items() if k not in drop}
 
 
 def main():
@@ -463,19 +791,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="versioned256m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batch4096", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="batch4096: skip the 2 GiB and 256 MiB legs; versioned256m: skip the "
+                         "pruned, lean and sort-phase builds")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batch4096: skip the plain per-text loop")
     ap.add_argument("--prune", action="store_true",
-                    help="time builds with the optional pruning phase (BT_PRUNE)")
-    ap.add_argument("--no-pruned-leg", action="store_true",
-                    help="skip the short pruned-build measurement beside the main line")
+                    help="single-text workloads: time builds with the optional pruning phase")
     ap.add_argument("--lean", action="store_true",
-                    help="time memory-lean builds (BT_LEAN: sampled prefix fingerprints)")
-    ap.add_argument("--no-lean-leg", action="store_true",
-                    help="skip the short memory-lean measurement beside the main line")
-    ap.add_argument("--no-sort-leg", action="store_true",
-                    help="skip the build with the sort-based phases of Section 5.1")
-    ap.add_argument("--cpu-sample-mib", type=int, default=8)
+                    help="single-text workloads: time memory-lean builds (sampled fingerprints)")
+    ap.add_argument("--cpu-sample-mib", type=int, default=512,
+                    help="bytes of the workload the CPU baseline builds")
+    ap.add_argument("--launch-log", metavar="FILE",
+                    help="write the probe-scan launches of the last timed step as JSON")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
                          "known-size reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -484,6 +814,9 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=4,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the probe_scan traffic record from four --pmc runs (no GPU)")
+    ap.add_argument("--summarize-launches", nargs="+", metavar="PATH",
+                    help="LAUNCH_JSON PMC_DIR...: the per-launch probe-scan table (no GPU)")
+    ap.add_argument("--calib-dirs", nargs=2, metavar=("COPY_FETCH_DIR", "COPY_WRITE_DIR"))
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--bench-json", help="stdout of the profiled bench run")
     ap.add_argument("--profile-cmd", action="append", default=[],
@@ -496,6 +829,10 @@ def main():
     if args.summarize_traffic:
         return summarize_traffic(*args.summarize_traffic, args.copy_mib, args.bench_json,
                                  args.profile_cmd, args.out[0], args.out[1])
+    if args.summarize_launches:
+        calib = (args.copy_mib,) + tuple(args.calib_dirs) if args.calib_dirs else None
+        return summarize_launches(args.summarize_launches[0], args.summarize_launches[1:], calib,
+                                  args.profile_cmd, args.out[0])
     if args.calibrate_copy:
         import torch
         nb = args.calibrate_copy << 20
@@ -511,103 +848,40 @@ def main():
               "(multi-GPU sharding is a design note, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-    import paper_2512_23314_amd as bt
-
-    gen, sigma, tau, leaf, s_hint, desc = WORKLOADS[args.workload]
-    if gen == "cfg4":
-        return bench_batch(args, sigma, tau, leaf, desc)
-    if gen == "cfg5":
-        return bench_serve(args, sigma, tau, leaf, desc)
-    t0 = time.time()
-    T = make_text(gen)
-    log("generated %s (%d bytes) in %.1f s" % (args.workload, T.size, time.time() - t0))
-    n = int(T.size)
-    d = torch.from_numpy(T).to("cuda:0")
-    torch.cuda.synchronize()
-    ctx = bt.Context(0)
-
-    def step(prune=args.prune, lean=args.lean):
-        tree = ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, prune=prune, lean=lean)
-        h = tree.height
-        tree.free()
-        return h
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.reset_stats()
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        h = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ctx.profile(False)
-    ms = dt / args.steps * 1e3
-    value = n / 1e6 / (ms / 1e3)
-
-    stats = {k: ctx.kernel_stats(k) for k in ("probe_scan", "byte_scan", "prefix_fp", "verify")}
-    for k, s in stats.items():
-        if s["launches"]:
-            log("%-10s launches %5d  total %8.3f ms  avg %.4f ms  units %.3e  GB/s %.1f" % (
-                k, s["launches"], s["ms"], s["ms"] / s["launches"], s["units"],
-                s["bytes"] / max(s["ms"], 1e-9) / 1e6))
-    ps = stats["probe_scan"]
-    achieved = ps["bytes"] / ps["ms"] / 1e6 if ps["ms"] > 0 else 0.0
-    tr = traffic_record("probe_scan")
-    traffic = None
-    if tr is not None and ps["launches"]:
-        traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "probe_scan", "launches_per_step": ps["launches"] // max(args.steps, 1),
-                "bytes_per_launch": round(ps["bytes"] / max(ps["launches"], 1)),
-                "avg_launch_ms": round(ps["ms"] / max(ps["launches"], 1), 5)}
-    pruned = None
-    if not args.prune and not args.no_pruned_leg:
-        pruned = pruned_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
-        log("pruned build: %s" % pruned)
-    leanr = None
-    if not args.lean and not args.no_lean_leg:
-        leanr = lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
-        log("lean build: %s" % leanr)
-    sortr = None
-    if not args.no_sort_leg:
-        sortr = sort_leg(ctx, d, n, sigma, tau, leaf, s_hint, ms)
-        log("sort-phase build: %s" % sortr)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(T, sigma, tau, leaf, s_hint, args.cpu_sample_mib << 20)
-        log("cpu baseline: %s" % cpu)
-    out = {
-        "metric": "block-tree build MB/s and KR-scan GB/s (% HBM peak) on 1 MI355X vs CPU oracle",
-        "value": round(value, 2), "unit": "MB/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "n": n, "sigma": sigma,
-                   "tau": tau, "leaf_len": leaf, "s_hint": s_hint, "levels": h,
-                   "prune": bool(args.prune), "lean": bool(args.lean)},
-        "roofline": roofline, "cpu_baseline": cpu,
-    }
-    # per-kernel figures of the timed steps (HIP events on the library stream;
-    # algorithmic bytes as in the roofline: 8 or 16 B per probe-scan window,
-    # 1 B per byte-scan window, 13 B per text byte for the prefix scan: 1 read,
-    # 8 + 4 written)
-    out["kernels"] = {k: {"launches_per_step": s["launches"] // max(args.steps, 1),
-                          "ms_per_step": round(s["ms"] / max(args.steps, 1), 4),
-                          "algorithmic_GBps": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1)}
-                      for k, s in stats.items() if s["launches"]}
-    if pruned is not None:
-        out["pruned_build"] = pruned
-    if leanr is not None:
-        out["lean_build"] = leanr
-    if sortr is not None:
-        out["sort_phase_build"] = sortr
+    gen, sigma, tau, leaf, s_hint, golden, desc = WORKLOADS[args.workload]
+    cores = host_threads()
+    try:
+        if gen == "cfg5":
+            return bench_serve(args, sigma, tau, leaf, desc)
+        if gen == "cfg4":
+            out = bench_batch(args, sigma, tau, leaf, golden, desc)
+            if not args.no_legs:
+                legs = {}
+                for w, steps in (("dna2g", 3), ("versioned256m", 5)):
+                    leg, T = bench_single(args, w, steps, 1, sublegs=(w == "versioned256m"))
+                    if w == "versioned256m" and not args.no_cpu_baseline:
+                        leg["cpu_baseline"] = cpu_baseline_single(T, 4, 16, 1, cores, T.size)
+                        log("cpu baseline (256 MiB): %s" % leg["cpu_baseline"])
+                    del T
+                    legs[w] = leg_view(leg)
+                    log("leg %s: %.0f MB/s, probe scan %.3f of peak" % (
+                        w, leg["value"], leg["roofline"]["frac"]))
+                out["legs"] = legs
+            if not args.no_cpu_baseline:
+                out["cpu_baseline"] = cpu_baseline_batch(args.cpu_sample_mib, cores)
+                log("cpu baseline: %s" % out["cpu_baseline"])
+        else:
+            out, T = bench_single(args, args.workload, args.steps, args.warmup,
+                                  sublegs=(gen == "cfg2" and s_hint == 1 and not args.no_legs))
+            out["cpu_baseline"] = None
+            if not args.no_cpu_baseline:
+                out["cpu_baseline"] = cpu_baseline_single(T, tau, leaf, s_hint, cores,
+                                                          args.cpu_sample_mib << 20)
+                log("cpu baseline: %s" % out["cpu_baseline"])
+    except ParityError as e:
+        log("bench.py: parity check failed, no result reported: %s" % e)
+        sys.exit(3)
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -151,6 +151,19 @@ BT_API int bt_ctx_profile(bt_ctx* ctx, int enable);
 BT_API int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches,
                         double* total_ms, double* bytes, double* units);
 BT_API int bt_ctx_reset_stats(bt_ctx* ctx);
+/* The same timed launches one by one, in launch order, since the last
+ * bt_ctx_reset_stats (at most 65536 are kept).  For launch idx < count: the
+ * kernel name (NUL-terminated, cut to name_cap - 1 characters), the window
+ * length L of a scan launch (0 for other kernels), its work units, HIP-event
+ * milliseconds and algorithmic bytes.  For "probe_scan" the algorithmic bytes
+ * are those of the prefix values its tiles must read: a tile of 1024
+ * consecutive windows reads values [i0, i0 + 1024) and [i0 + L, i0 + L + 1024),
+ * 4 bytes each (8 without the 32-bit pre-filter), and the union is counted,
+ * i.e. 4 (1 + min(L, 1024) / 1024) bytes per window.  Any output may be NULL.
+ * Errors: BT_E_INVAL (idx out of range). */
+BT_API int bt_ctx_launch_count(const bt_ctx* ctx, uint64_t* count);
+BT_API int bt_ctx_launch_record(const bt_ctx* ctx, uint64_t idx, char* name, uint64_t name_cap,
+                                uint64_t* window_len, double* units, double* ms, double* bytes);
 /* Device memory of the context's pool, in bytes: handed out and not yet
  * returned (scratch of a build in flight plus the storage of live trees), the
  * most of that since the last bt_ctx_reset_peak, and all that the pool holds

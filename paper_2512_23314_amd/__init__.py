@@ -54,6 +54,8 @@ SIGNATURES = {
     "bt_ctx_profile": (_i32, [_vp, _i32]),
     "bt_ctx_kernel_stats": (_i32, [_vp, ctypes.c_char_p, _pu64, _pd, _pd, _pd]),
     "bt_ctx_reset_stats": (_i32, [_vp]),
+    "bt_ctx_launch_count": (_i32, [_vp, _pu64]),
+    "bt_ctx_launch_record": (_i32, [_vp, _u64, ctypes.c_char_p, _u64, _pu64, _pd, _pd, _pd]),
     "bt_ctx_memory": (_i32, [_vp, _pu64, _pu64, _pu64]),
     "bt_ctx_reset_peak": (_i32, [_vp]),
     "bt_prefix_fingerprints": (_i32, [_vp, _vp, _u64, _u64, _vp]),
@@ -149,6 +151,21 @@ class Context:
         self._check(lib().bt_ctx_kernel_stats(self.h, name.encode(), ctypes.byref(n),
                                               ctypes.byref(ms), ctypes.byref(by), ctypes.byref(un)))
         return {"launches": n.value, "ms": ms.value, "bytes": by.value, "units": un.value}
+
+    def launches(self):
+        """Per-launch records since reset_stats(): (name, window length, units,
+        ms, algorithmic bytes), in launch order."""
+        n = ctypes.c_uint64()
+        self._check(lib().bt_ctx_launch_count(self.h, ctypes.byref(n)))
+        out = []
+        name = ctypes.create_string_buffer(64)
+        wl = ctypes.c_uint64()
+        un, ms, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        for k in range(n.value):
+            self._check(lib().bt_ctx_launch_record(self.h, k, name, 64, ctypes.byref(wl), ctypes.byref(un),
+                                                   ctypes.byref(ms), ctypes.byref(by)))
+            out.append((name.value.decode(), wl.value, un.value, ms.value, by.value))
+        return out
 
     def trim(self):
         self._check(lib().bt_ctx_trim(self.h))

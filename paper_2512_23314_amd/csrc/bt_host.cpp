@@ -178,7 +178,16 @@ struct PendingEv {
   double bytes, units;
   const uint64_t* d_units;
   double bytes_per_unit;
+  uint64_t wlen;  // window length of a scan launch (0 otherwise)
 };
+
+// One timed launch, in launch order.
+struct LaunchRec {
+  std::string name;
+  uint64_t wlen;
+  double units, ms, bytes;
+};
+constexpr size_t kLaunchLogMax = 1 << 16;
 
 struct bt_ctx {
   int dev = 0;
@@ -187,6 +196,7 @@ struct bt_ctx {
   std::string err = "no error";
   bool profile = false;
   std::map<std::string, KStat> stats;
+  std::vector<LaunchRec> launches;  // at most kLaunchLogMax, oldest first
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_free;
   uint64_t* h_small = nullptr;  // pinned host words for count read-back
@@ -374,7 +384,7 @@ hipEvent_t get_event(bt_ctx* ctx) {
 // synchronisation and bytes = units * bytes_per_unit.
 template <typename F>
 void timed(bt_ctx* ctx, const char* name, double bytes, double units, const uint64_t* d_units,
-           double bytes_per_unit, F&& f) {
+           double bytes_per_unit, F&& f, uint64_t wlen = 0) {
   if (!ctx->profile) {
     HIPCHK(ctx, f());
     return;
@@ -383,7 +393,7 @@ void timed(bt_ctx* ctx, const char* name, double bytes, double units, const uint
   HIPCHK(ctx, hipEventRecord(a, ctx->stream));
   HIPCHK(ctx, f());
   HIPCHK(ctx, hipEventRecord(b, ctx->stream));
-  ctx->pending.push_back({name, a, b, bytes, units, d_units, bytes_per_unit});
+  ctx->pending.push_back({name, a, b, bytes, units, d_units, bytes_per_unit, wlen});
 }
 
 // Folds finished timed launches into the statistics.  A launch whose unit
@@ -410,6 +420,8 @@ void collect_events(bt_ctx* ctx, const uint64_t* dbase = nullptr, const uint64_t
       s.ms += ms;
       s.bytes += bytes;
       s.units += units;
+      if (ctx->launches.size() < kLaunchLogMax)
+        ctx->launches.push_back({p.name, p.wlen, units, (double)ms, bytes});
     }
     ctx->ev_free.push_back(p.a);
     ctx->ev_free.push_back(p.b);
@@ -1067,11 +1079,17 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         // algorithmic bytes per window: the one text byte each window start adds
         timed(ctx, "byte_scan", 0, 0, wst, 1.0, [&] {
           return launch_byte_scan(as, swoff, has_odd, has_salt, c * b, s);
-        });
+        }, a.Lmain);
       } else {
-        timed(ctx, "probe_scan", 0, 0, wst, a.pre32 ? 8.0 : 16.0, [&] {
+        // A wave's tile is kProbeTile consecutive windows, whose two reads cover
+        // prefix values [i0, i0 + tile) and [i0 + L, i0 + L + tile): the bytes
+        // the tile must fetch are those of the union, so the partner read is
+        // counted only for the part beyond the tile.
+        const double per_value = a.pre32 ? 4.0 : 8.0;
+        const double partner = (double)std::min<uint64_t>(a.Lmain, kProbeTile) / (double)kProbeTile;
+        timed(ctx, "probe_scan", 0, 0, wst, per_value * (1.0 + partner), [&] {
           return launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
-        });
+        }, a.Lmain);
       }
       HIPCHK(ctx, launch_resolve(a, vb, s));
       timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });
@@ -1477,6 +1495,29 @@ int bt_ctx_kernel_stats(const bt_ctx* ctx, const char* name, uint64_t* launches,
 int bt_ctx_reset_stats(bt_ctx* ctx) {
   if (!ctx) return BT_E_INVAL;
   ctx->stats.clear();
+  ctx->launches.clear();
+  return BT_OK;
+}
+
+int bt_ctx_launch_count(const bt_ctx* ctx, uint64_t* count) {
+  if (!ctx || !count) return BT_E_INVAL;
+  *count = ctx->launches.size();
+  return BT_OK;
+}
+
+int bt_ctx_launch_record(const bt_ctx* ctx, uint64_t idx, char* name, uint64_t name_cap,
+                         uint64_t* window_len, double* units, double* ms, double* bytes) {
+  if (!ctx || idx >= ctx->launches.size()) return BT_E_INVAL;
+  const LaunchRec& r = ctx->launches[idx];
+  if (name && name_cap) {
+    const size_t k = std::min<size_t>(r.name.size(), name_cap - 1);
+    std::memcpy(name, r.name.data(), k);
+    name[k] = 0;
+  }
+  if (window_len) *window_len = r.wlen;
+  if (units) *units = r.units;
+  if (ms) *ms = r.ms;
+  if (bytes) *bytes = r.bytes;
   return BT_OK;
 }
 

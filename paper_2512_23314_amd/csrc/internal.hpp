@@ -188,6 +188,10 @@ hipError_t launch_text_step(uint32_t T, const uint64_t* cs, const uint64_t* tfir
                             const uint64_t* tcount, const uint64_t* enter, const uint64_t* uoff,
                             uint64_t* ncount, uint64_t* nfirst, uint64_t* tu, hipStream_t s);
 
+// The probe scan's tile: a wave takes this many consecutive window numbers at
+// a time (lanes step through them 64 apart).
+constexpr uint64_t kProbeTile = 1024;
+
 // Phase kernels (steps a3-a7).
 hipError_t launch_keys(const PhaseArgs& a, hipStream_t s);
 hipError_t launch_entries_from_runs(const LevelDev& lv, uint64_t* ea, uint64_t* ee, uint8_t* ef,

@@ -395,6 +395,7 @@ hipError_t launch_block_segments(const PhaseArgs& a, const uint64_t* wcs, const 
 
 constexpr int kScanK = 16;                      // windows per lane per chunk
 constexpr uint64_t kScanChunk = 64ull * kScanK;  // windows per wave per chunk
+static_assert(kScanChunk == kProbeTile, "the host counts algorithmic bytes per tile of kProbeTile windows");
 
 // Linear probing over the tag array, one aligned group of eight tags per load:
 // the slots from the home slot up to the first empty one are exactly those a

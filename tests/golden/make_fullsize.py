@@ -10,7 +10,8 @@ Outputs (merged into what is already there, so runs can be split):
                         hex digits of its tree's SHA-256
 
 Usage: python tests/golden/make_fullsize.py [--only NAME ...] [--threads K]
-Names: versioned256m, dna2g_t<tau>_l<leaf> (tau in 2,4,8,16; leaf in 8,16,32),
+Names: versioned256m, versioned256m_s (about 2^19 root blocks), dna1m and
+dna1m_s (s about 10^4), dna2g_t<tau>_l<leaf> (tau in 2,4,8,16; leaf in 8,16,32),
 batch4096.
 """
 import argparse
@@ -57,7 +58,10 @@ def _load():
                      "construction; inputs from synth (seeded)", "entries": {}}
 
 
-def _save(doc):
+def _save(name, entry):
+    """Merge one entry into the file as it is now on disk."""
+    doc = _load()
+    doc["entries"][name] = entry
     tmp = JSON_PATH + ".tmp"
     with open(tmp, "w") as f:
         json.dump(doc, f, indent=1, sort_keys=True)
@@ -65,15 +69,15 @@ def _save(doc):
     os.replace(tmp, JSON_PATH)
 
 
-def single(name, T, tau, leaf, threads, recipe):
+def single(name, T, tau, leaf, threads, recipe, s_hint=1):
     t0 = time.time()
-    tree = oracle.build_tree_par(T, tau, leaf, threads=threads, levels=False)
+    tree = oracle.build_tree_par(T, tau, leaf, s_hint=s_hint, threads=threads, levels=False)
     dt = time.time() - t0
     return {
         "recipe": recipe,
         "n": int(T.size),
         "input_sha256": hashlib.sha256(T.tobytes()).hexdigest(),
-        "tau": tau, "leaf_len": leaf, "s_hint": 1, "b1": int(tree.b1), "h": int(tree.h),
+        "tau": tau, "leaf_len": leaf, "s_hint": s_hint, "b1": int(tree.b1), "h": int(tree.h),
         "levels_b_c_u": [[int(L.b), int(L.c), int(L.u)] for L in tree.levels],
         "canonical_bytes": len(tree.canonical),
         "canonical_sha256": hashlib.sha256(tree.canonical).hexdigest(),
@@ -122,18 +126,25 @@ def main():
     ap.add_argument("--only", nargs="*", default=None)
     ap.add_argument("--threads", type=int, default=oracle.default_threads())
     a = ap.parse_args()
-    names = ["versioned256m", "dna2g_t4_l16", "batch4096"] + \
+    names = ["versioned256m", "dna2g_t4_l16", "batch4096", "dna1m", "dna1m_s", "versioned256m_s"] + \
         ["dna2g_t%d_l%d" % p for p in DNA2G_SWEEP if p != (4, 16)]
     if a.only:
         names = [x for x in names if x in a.only]
     oracle.build()
-    doc = _load()
     dna = None
     for name in names:
         print("%s ..." % name, flush=True)
         if name == "versioned256m":
             T = synth.cfg2_text()
             e = single(name, T, 4, 16, a.threads, "synth.cfg2_text(): 256 MiB versioned text, sigma 96")
+        elif name == "versioned256m_s":
+            T = synth.cfg2_text()
+            e = single(name, T, 4, 16, a.threads, "synth.cfg2_text(): 256 MiB versioned text, sigma 96",
+                       s_hint=1 << 19)
+        elif name in ("dna1m", "dna1m_s"):
+            T = synth.cfg1_text()
+            e = single(name, T, 2, 16, a.threads, "synth.cfg1_text(): 1 MiB DNA, 16 copies of 64 KiB",
+                       s_hint=1 if name == "dna1m" else 10000)
         elif name.startswith("dna2g"):
             if dna is None:
                 dna = synth.cfg3_text()
@@ -144,8 +155,7 @@ def main():
             e = batch(a.threads)
         else:
             raise SystemExit("unknown workload " + name)
-        doc["entries"][name] = e
-        _save(doc)
+        _save(name, e)
         print("%s: %s in %.0f s" % (name, e.get("canonical_sha256", e.get("tree_digest")),
                                     e["oracle_seconds"]), flush=True)
 
