@@ -67,6 +67,10 @@ extern "C" {
  * change.  Needs fewer than 2^31 windows per phase (else BT_E_INVAL) and about
  * 40 bytes of device memory per window. */
 #define BT_DBG_SORT_PHASES 8u
+/* Batches: scan with one key filter shared by all texts of a phase (the
+ * single-text path) instead of a filter per text; the output must not
+ * change. */
+#define BT_DBG_SHARED_FILTERS 16u
 
 /* ---- build flags (bt_params.flags) ---- */
 /* Also build the counters that bt_rank and bt_select need: per block and per

@@ -19,6 +19,7 @@ BT_DBG_WEAK_HASH = 1
 BT_DBG_NO_QUEUE = 2
 BT_DBG_NO_BYTE_SCAN = 4
 BT_DBG_SORT_PHASES = 8
+BT_DBG_SHARED_FILTERS = 16
 BT_WITH_RANK_SELECT = 1
 BT_PRUNE = 2
 BT_LEAN = 4

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbt.so")
 
-SOURCES = ["prefix_fp.hip", "scan.hip", "level.hip", "prune.hip", "sort_phase.hip", "query.hip", "rank.hip", "bt_host.cpp"]
+SOURCES = ["prefix_fp.hip", "scan.hip", "level.hip", "probe_text.hip", "prune.hip", "sort_phase.hip", "query.hip", "rank.hip", "bt_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

@@ -955,6 +955,45 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint64_t> bwoff = alloc<uint64_t>(ctx, c + 1);
     Buf<uint32_t> btext = alloc<uint32_t>(ctx, c);
 
+    // Text-local filters (batches): per text, 2^wl 32-bit words with wl the
+    // least >= 3 such that each of the text's blocks (a bound on its keys in
+    // either phase) has a word.  One layout serves both phases.
+    // A text whose filter is larger than LDS also gets a folded copy of LDS
+    // size (tf_fold), built after the keys.
+    Buf<uint64_t> tf_off, tf_fold_off, span_ctr;
+    Buf<uint32_t> tf_words, tf_wl, tf_fold, tf_big;
+    uint64_t tf_total = 0;
+    uint32_t nbig = 0;
+    if (has_salt && c && !(prm.debug_flags & (BT_DBG_SHARED_FILTERS | BT_DBG_SORT_PHASES))) {
+      std::vector<uint64_t> h_off(T), h_foff(T, 0);
+      std::vector<uint32_t> h_wl(T), h_big;
+      for (uint32_t t = 0; t < T; ++t) {
+        uint32_t wl = 3;
+        while ((1ull << wl) < h_tcount[t]) ++wl;
+        h_wl[t] = wl;
+        h_off[t] = tf_total;
+        tf_total += 1ull << wl;
+        if (wl > kTextFilterLdsLog2) {
+          h_foff[t] = (uint64_t)h_big.size() << kTextFilterLdsLog2;
+          h_big.push_back(t);
+        }
+      }
+      nbig = (uint32_t)h_big.size();
+      tf_words = alloc<uint32_t>(ctx, tf_total);
+      tf_off = alloc<uint64_t>(ctx, T);
+      tf_wl = alloc<uint32_t>(ctx, T);
+      span_ctr = alloc<uint64_t>(ctx, 1);
+      upload(ctx, tf_off.p, h_off.data(), T);
+      upload(ctx, tf_wl.p, h_wl.data(), T);
+      if (nbig) {
+        tf_fold = alloc<uint32_t>(ctx, (uint64_t)nbig << kTextFilterLdsLog2);
+        tf_fold_off = alloc<uint64_t>(ctx, T);
+        tf_big = alloc<uint32_t>(ctx, nbig);
+        upload(ctx, tf_fold_off.p, h_foff.data(), T);
+        upload(ctx, tf_big.p, h_big.data(), nbig);
+      }
+    }
+
     // nkeys: keys of the phase (pairs of consecutive blocks, or unmarked blocks)
     auto run_phase = [&](int phase, uint64_t nkeys) {
       a.phase = phase;
@@ -1004,6 +1043,17 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         f2words = 0;
         scan_mode = 1;
       }
+      // batches: each window against its own text's filter (probe_text.hip)
+      const bool text_local = tf_total && !byte_scan && scan_mode == 1;
+      if (text_local) {
+        fbits = 0;
+        f2words = 0;
+      }
+      a.tf_words = text_local ? tf_words.p : nullptr;
+      a.tf_off = text_local ? tf_off.p : nullptr;
+      a.tf_wl = text_local ? tf_wl.p : nullptr;
+      a.tf_fold = text_local ? tf_fold.p : nullptr;
+      a.tf_fold_off = text_local ? tf_fold_off.p : nullptr;
       a.filt_bits = fbits;
       a.filt_two = fbits && 8 * nkeys <= (1ull << fbits);
       a.pre32 = !byte_scan && scan_mode == 1;
@@ -1019,11 +1069,16 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         f.add(vcnt.p, 4, 0);
         f.add(filt.p, (1ull << (byte_scan ? bbits : fbits)) / 32, 0);
         if (f2words) f.add(filt2.p, 2ull << f2words, 0);
+        if (text_local) {
+          f.add(tf_words.p, tf_total, 0);
+          f.add(span_ctr.p, 2, 0);
+        }
         HIPCHK(ctx, launch_fill_many(f, s));
       }
       HIPCHK(ctx, launch_keys(a, s));
       // no keys: the slots say so (kNoKey), and there is nothing to scan for
       if (nkeys == 0) return;
+      if (text_local) HIPCHK(ctx, launch_fold_filters(a, tf_big.p, nbig, s));
       PhaseArgs as = a;  // the scan walks segments in place of runs
       uint64_t* swoff = woff.p;
       uint64_t* wst = wstats.p + 2 * step + (phase - 1);
@@ -1088,7 +1143,12 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         const double per_value = a.pre32 ? 4.0 : 8.0;
         const double partner = (double)std::min<uint64_t>(a.Lmain, kProbeTile) / (double)kProbeTile;
         timed(ctx, "probe_scan", 0, 0, wst, per_value * (1.0 + partner), [&] {
-          return launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
+          // spans: at least four per resident workgroup (512) for the level's
+          // window bound, 16 to 256 chunks, a multiple of the 16 waves
+          uint64_t span_chunks = (c * b) / kProbeTile / (4 * 512);
+          span_chunks = std::min<uint64_t>(256, std::max<uint64_t>(16, span_chunks & ~15ull));
+          return text_local ? launch_probe_text(as, swoff, has_odd, c * b, span_chunks, span_ctr.p, s)
+                            : launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
         }, a.Lmain);
       }
       HIPCHK(ctx, launch_resolve(a, vb, s));

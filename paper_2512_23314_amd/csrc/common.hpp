@@ -107,6 +107,18 @@ __device__ __forceinline__ uint64_t filter2_mask(uint32_t h) {
   return (1ull << (m >> 26)) | (1ull << ((m >> 20) & 63)) | (1ull << ((m >> 14) & 63));
 }
 
+// Text-local filter of a 32-bit window hash (batches): blocked, three bits in
+// one 32-bit word, so that a test is one 4-byte load.  words_log2 (>= 3) =
+// log2(32-bit words); word and bits come from multiplicative hashes with their
+// own odd constants.
+__device__ __forceinline__ uint32_t tfilter_word(uint32_t h, uint32_t words_log2) {
+  return (h * 0x7FEB352Du) >> (32 - words_log2);
+}
+__device__ __forceinline__ uint32_t tfilter_mask(uint32_t h) {
+  const uint32_t m = h * 0x846CA68Bu;
+  return (1u << (m >> 27)) | (1u << ((m >> 22) & 31)) | (1u << ((m >> 17) & 31));
+}
+
 // Filter bit of a string's first eight bytes (lo = bytes 0..3, hi = bytes
 // 4..7, little endian) in a filter of 2^bits bits: equal strings of length 8 or
 // more share it.  The top bits of each product depend on every bit of its word.

@@ -138,6 +138,18 @@ struct PhaseArgs {
   // first eight bytes (2^bfilt_bits bits, 0 = off), tested on the text itself.
   uint32_t* bfilt;
   uint32_t bfilt_bits;
+  // Text-local filters (batches, with pre32): per text t, a blocked filter of
+  // its keys' 32-bit hashes, 2^tf_wl[t] 32-bit words at tf_words + tf_off[t],
+  // three bits of one word per key (tfilter_word, tfilter_mask).  Null when off.
+  uint32_t* tf_words;
+  const uint64_t* tf_off;  // [T]
+  const uint32_t* tf_wl;   // [T], at least 3
+  // For a text whose filter is larger than LDS (tf_wl[t] > kTextFilterLdsLog2):
+  // the same filter folded to 2^kTextFilterLdsLog2 words at tf_fold +
+  // tf_fold_off[t] (word k = OR of the 2^(wl - kTextFilterLdsLog2) words
+  // k 2^d .., a superset test: a window failing it fails the full filter).
+  uint32_t* tf_fold;
+  const uint64_t* tf_fold_off;  // [T] (read only for such texts)
 };
 
 // Scan entries and segments (level.hip, "scan segments").
@@ -240,6 +252,21 @@ hipError_t launch_byte_scan(const PhaseArgs& a, const uint64_t* woff, bool has_o
 // 1: LDS key filter and per-wave candidate queues, 2: LDS key filter, inline probe.
 hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
                              bool has_salt, uint64_t max_windows, int mode, hipStream_t s);
+// The probe scan of a batch with text-local filters (probe_text.hip): resident
+// workgroups take spans of span_chunks * kProbeTile windows from *span_ctr
+// (zeroed by the caller); a window is tested against its own text's filter,
+// from LDS when the span lies in one text (its filter, or the folded filter of
+// a text whose filter does not fit, then the full one in global memory).
+// Needs pre32, text-local filters, salts.
+hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
+                             uint64_t max_windows, uint64_t span_chunks, uint64_t* span_ctr,
+                             hipStream_t s);
+// Folds the filters of the nbig texts listed in big (see PhaseArgs.tf_fold).
+hipError_t launch_fold_filters(const PhaseArgs& a, const uint32_t* big, uint32_t nbig,
+                               hipStream_t s);
+// log2 of the 32-bit words of the largest text-local filter a span loads into
+// LDS (64 KiB: with the queues, two 1024-thread workgroups fit one CU's LDS).
+constexpr uint32_t kTextFilterLdsLog2 = 14;
 
 struct VerifyBufs {
   uint32_t* vlist;  // [c]

@@ -19,6 +19,7 @@
 // present), so "leftmost on this level" and "leftmost in T" coincide.
 #include "common.hpp"
 #include "internal.hpp"
+#include "probe.hpp"
 #include "window.hpp"
 
 namespace bt {
@@ -106,6 +107,11 @@ __global__ void k_keys(PhaseArgs a) {
       a.k.slot[j] = (uint32_t)h;
       a.tab.tag[h] = (uint8_t)tag_of(fp);  // every key of the slot writes the same byte
       atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
+      if (a.tf_words) {
+        // text-local filter: this text's keys only
+        const uint32_t h = a.P32[st + L] - a.P32[st] * a.x32L + (uint32_t)a.tx.tsalt[t];
+        atomicOr(a.tf_words + a.tf_off[t] + tfilter_word(h, a.tf_wl[t]), tfilter_mask(h));
+      }
       if (a.filt_bits) {
         uint64_t f1, f2;
         if (a.pre32) {
@@ -397,38 +403,6 @@ constexpr int kScanK = 16;                      // windows per lane per chunk
 constexpr uint64_t kScanChunk = 64ull * kScanK;  // windows per wave per chunk
 static_assert(kScanChunk == kProbeTile, "the host counts algorithmic bytes per tile of kProbeTile windows");
 
-// Linear probing over the tag array, one aligned group of eight tags per load:
-// the slots from the home slot up to the first empty one are exactly those a
-// key with this fingerprint could occupy; only those whose tag matches are read.
-__device__ __forceinline__ void probe(Slot* __restrict__ slots, const uint8_t* __restrict__ tags,
-                                      uint64_t mask, uint64_t fp, uint64_t i) {
-  constexpr uint64_t kLo7 = 0x7F7F7F7F7F7F7F7Full;
-  const uint64_t h = slot_of(fp, mask);
-  const uint64_t tb = 0x0101010101010101ull * tag_of(fp);
-  uint64_t g = h >> 3;
-  uint64_t valid = ~0ull << (8 * (h & 7));  // bytes at or after the home slot
-  while (true) {
-    const uint64_t w = *reinterpret_cast<const uint64_t*>(tags + 8 * g);
-    // bit 8k+7 set exactly where byte k is zero (empty) / equals the tag
-    const uint64_t emp = ~(((w & kLo7) + kLo7) | w | kLo7) & valid;
-    const uint64_t x = w ^ tb;
-    uint64_t mat = ~(((x & kLo7) + kLo7) | x | kLo7) & valid;
-    if (emp) mat &= (emp & (0 - emp)) - 1;  // matches before the first empty slot
-    while (mat) {
-      const uint64_t j = 8 * g + (__builtin_ctzll(mat) >> 3);
-      const Slot s = slots[j];
-      if (s.fp == fp) {
-        if (i < s.best) atomicMin((unsigned long long*)&slots[j].best, (unsigned long long)i);
-        return;
-      }
-      mat &= mat - 1;
-    }
-    if (emp) return;
-    g = (g + 1) & (mask >> 3);
-    valid = ~0ull;
-  }
-}
-
 // Windows are numbered run after run (woff = exclusive prefix of per-run window
 // counts).  Each wave takes chunks of 64*kScanK consecutive window numbers;
 // in step k lane l handles window chunk + 64k + l, so consecutive lanes read
@@ -440,21 +414,11 @@ __device__ __forceinline__ void probe(Slot* __restrict__ slots, const uint8_t* _
 // hash.  The windows that pass are appended to a per-wave queue in LDS (ballot
 // + prefix popcount) and probed 64 at a time.
 constexpr int kProbeThreads = 1024;
-constexpr int kQueue = 128;  // entries per wave (< 64 pending + up to 64 new)
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ bool filter_has(const uint32_t* s_filt, uint64_t b1, uint64_t b2) {
   return ((s_filt[b1 >> 5] >> (b1 & 31)) & (s_filt[b2 >> 5] >> (b2 & 31)) & 1) != 0;
 }
 
-// Queue entries pack a window start (below 2^40) and its text (below 2^24).
-constexpr int kQPosBits = 40;
-constexpr uint64_t kQPosMask = (1ull << kQPosBits) - 1;
 
 // MODE 0 (kept in the template, not launched): no filter, every window probes
 // the table.  MODE 1: filter, and the

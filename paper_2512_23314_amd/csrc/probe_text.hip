@@ -1,0 +1,355 @@
+// The probe scan of a batch with text-local filters (Section 4.1, steps a4 and
+// a6, for many texts at once).
+//
+// A batch's keys only ever match windows of their own text: each text's
+// fingerprints carry their own salt, and a hit in another text counts as a
+// collision.  One filter shared by every text of a phase would hold millions of
+// keys and pass most windows; here each text has its own blocked filter of its
+// keys' 32-bit hashes (one 32-bit word per key, three bits per key, set by
+// k_keys), and a window is tested against its own text's filter only.
+//
+// Workgroups stay resident and take spans of span_chunks * kProbeTile
+// consecutive window numbers from an atomic counter.  When a span's windows all
+// belong to one text, the workgroup copies that text's filter into LDS (once
+// per text: the next span of the same text keeps it) and tests there; a text
+// whose filter is larger than LDS has a folded copy (each LDS word the OR of
+// the words it covers), and a window that passes it is tested again against
+// the full filter in global memory.  Spans that cross texts test each window
+// against its text's filter in global memory (such texts are small, and so are
+// their filters).  Inside a span, wave w takes chunks w, w + 16, ... of
+// kProbeTile windows, laid out as in the shared-filter probe scan: in step k,
+// lane l takes window chunk + 64 k + l, so consecutive lanes read consecutive
+// prefix hashes.  The windows that pass join the per-wave candidate queue and
+// probe the shared table 64 at a time with their 61-bit fingerprints.
+#include "common.hpp"
+#include "internal.hpp"
+#include "probe.hpp"
+#include "window.hpp"
+
+#include <type_traits>
+
+namespace bt {
+
+constexpr int kTlThreads = 1024;
+constexpr uint32_t kTlWaves = kTlThreads / 64;
+constexpr int kTlK = 16;  // windows per lane per chunk
+// Queue entries per wave: at most 63 wait between flushes and a step adds at
+// most 63 more (indices up to 126), so 127 suffice; the byte this saves per
+// wave leaves room for the workgroup's shared words beside a 64 KiB filter.
+constexpr int kTlQueue = 127;
+constexpr uint32_t kNoText = 0xFFFFFFFFu;
+static_assert(64ull * kTlK == kProbeTile, "a chunk is one probe tile");
+
+// Segment holding window number w: the last r with woff[r] <= w.
+__device__ __forceinline__ uint64_t segment_of(const uint64_t* __restrict__ woff, uint64_t R,
+                                               uint64_t w) {
+  uint64_t lo = 0, hi = R;
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (woff[mid] <= w) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <bool ODD, bool LEAN>
+__global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_chunks,
+                  uint64_t* __restrict__ span_ctr) {
+  extern __shared__ uint64_t s_lds[];
+  uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);  // up to 2^kTextFilterLdsLog2 words
+  uint64_t* q = s_lds + (1u << (kTextFilterLdsLog2 - 1)) + (uint64_t)(threadIdx.x >> 6) * kTlQueue;
+  const uint64_t span = span_chunks * kProbeTile;
+  __shared__ uint64_t s_span;
+  __shared__ uint32_t s_text;    // the span's text when its filter goes to LDS, else kNoText
+  __shared__ uint32_t s_loaded;  // the text whose filter LDS holds, or kNoText
+
+  const int lane = lane_id();
+  const uint32_t wave = threadIdx.x >> 6;
+  uint32_t qn = 0;  // wave-uniform queue length
+
+  const uint64_t R = a.lv.R;
+  const uint64_t W = woff[R];
+  const uint64_t* __restrict__ P = a.P;
+  const uint32_t* __restrict__ H = a.P32;
+  const uint64_t* __restrict__ rs_ = a.lv.rs;
+  const uint64_t* __restrict__ re_ = a.lv.re;
+  const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
+  const uint32_t x32L = a.x32L;
+  Slot* __restrict__ slots = a.tab.slots;
+  const uint8_t* __restrict__ tags = a.tab.tag;
+  const uint64_t mask = a.tab.mask;
+  const uint32_t* __restrict__ tfw = a.tf_words;
+  const uint64_t* __restrict__ tfo = a.tf_off;
+  const uint32_t* __restrict__ tfl = a.tf_wl;
+
+  const auto fp61 = [&](uint64_t i, uint64_t salt) {
+    const uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
+    return add61(f, salt) & fmask;
+  };
+  // the entry this lane holds: form its fingerprint and probe
+  const auto probe_entry = [&](uint64_t e) {
+    const uint64_t i = e & kQPosMask;
+    probe(slots, tags, mask, fp61(i, a.tx.tsalt[e >> kQPosBits]), i);
+  };
+  // whole wave: append the lanes' candidates; probe 64 once 64 are waiting
+  const auto push = [&](bool cand, uint64_t i, uint32_t t) {
+    const uint64_t bal = __ballot(cand);
+    if (!bal) return;
+    const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
+    if (cand) q[qn + my] = ((uint64_t)t << kQPosBits) | i;
+    qn += (uint32_t)__popcll(bal);
+    if (qn >= 64) {
+      wave_sync();
+      const uint64_t e = q[lane];
+      const bool mv = (uint32_t)lane < qn - 64;
+      const uint64_t e2 = mv ? q[64 + lane] : 0;
+      wave_sync();
+      if (mv) q[lane] = e2;
+      qn -= 64;
+      probe_entry(e);
+      wave_sync();
+    }
+  };
+
+  // One chunk of kProbeTile window numbers.  LDS (a compile-time tag): every
+  // window of the chunk belongs to text st, whose filter (2^lwl words, lwl =
+  // its word count or the folded one) is in LDS; when folded (big), a window
+  // that passes is tested again against the full filter.  Otherwise each lane
+  // reads its own text's filter in global memory.
+  const auto scan_chunk = [&](uint64_t ch, auto lds_tag, uint32_t st, uint32_t lwl, bool big) {
+    constexpr bool LDS = decltype(lds_tag)::value;
+    const uint64_t w0 = ch * kProbeTile + lane;
+    uint64_t r = segment_of(woff, R, w0);
+    uint64_t wo = woff[r], wn = woff[r + 1], rs = rs_[r], re = re_[r];
+    // lanes past the last window hold no segment: they read no text entry
+    uint32_t t = w0 < W ? a.lv.rtext[r] : 0;
+    uint64_t salt = a.tx.tsalt[t];
+    uint64_t toff = tfo[LDS ? st : t];
+    uint32_t twl = tfl[LDS ? st : t];
+    const auto pass_word = [&](uint32_t h) -> uint32_t {
+      return LDS ? s_filt[tfilter_word(h, lwl)] : tfw[toff + tfilter_word(h, twl)];
+    };
+    // the text's short final key, if any (kept in registers while t holds)
+    uint64_t oL = 0, opos = 0;
+    uint32_t oh = 0, ox = 0;
+    const auto load_odd = [&]() {
+      oL = a.odd.L[t];
+      if (oL) {
+        opos = a.odd.pos[t];
+        const uint64_t hx = a.odd.h32[t];
+        oh = (uint32_t)hx;
+        ox = (uint32_t)(hx >> 32);
+      }
+    };
+    if (ODD && w0 < W) load_odd();
+    // the short key's 61-bit fingerprint at i, against the key's (text t)
+    const auto odd61 = [&](uint64_t i, uint64_t sl) {
+      uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+      g = add61(g, sl);
+      if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
+        atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
+    };
+
+    // every lane's 16 windows inside its segment: eight steps' loads at once
+    {
+      const uint64_t wl = w0 + 64ull * (kTlK - 1);
+      const bool lane_ok = wl < wn && rs + (wl - wo) + L <= re;
+      if (__ballot(lane_ok) == ~0ull) {
+        const uint64_t i0 = rs + (w0 - wo);
+        const uint32_t s32 = (uint32_t)salt;
+#pragma unroll
+        for (int k0 = 0; k0 < kTlK; k0 += 8) {
+          uint32_t hv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint64_t i = i0 + 64ull * (k0 + k);
+            hv[k] = H[i + L] - H[i] * x32L + s32;
+          }
+          if (ODD && oL) {
+            // the short key's 32-bit hashes (H[i] again, from L1); the rare
+            // matches form their 61-bit fingerprints one at a time
+            uint32_t om = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint64_t i = i0 + 64ull * (k0 + k);
+              if (i < opos && H[i + oL] - H[i] * ox + s32 == oh) om |= 1u << k;
+            }
+            while (om) {
+              const int k = __builtin_ctz(om);
+              om &= om - 1;
+              odd61(i0 + 64ull * (k0 + k), salt);
+            }
+          }
+          uint32_t wv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) wv[k] = pass_word(hv[k]);
+          bool ok[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t m = tfilter_mask(hv[k]);
+            ok[k] = (wv[k] & m) == m;
+          }
+          if (LDS && big) {
+            // passed the folded filter: the full one, the loads issued together
+#pragma unroll
+            for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? tfw[toff + tfilter_word(hv[k], twl)] : 0u;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint32_t m = tfilter_mask(hv[k]);
+              ok[k] = ok[k] && (wv[k] & m) == m;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) push(ok[k], i0 + 64ull * (k0 + k), t);
+        }
+        return;
+      }
+    }
+
+    // per step, following each lane across segment (and text) boundaries
+    for (int k = 0; k < kTlK; ++k) {
+      const uint64_t w = w0 + (uint64_t)k * 64;
+      const bool live = w < W;  // every lane stays in the loop (the queue is wave-wide)
+      if (live && w >= wn) {
+        do {
+          ++r;
+          wo = wn;
+          wn = woff[r + 1];
+        } while (w >= wn);
+        rs = rs_[r];
+        re = re_[r];
+        t = a.lv.rtext[r];
+        salt = a.tx.tsalt[t];
+        if (!LDS) {
+          toff = tfo[t];
+          twl = tfl[t];
+        }
+        if (ODD) load_odd();
+      }
+      const uint64_t i = rs + (w - wo);
+      bool cand = false;
+      if (live && i + L <= re) {
+        const uint32_t h = H[i + L] - H[i] * x32L + (uint32_t)salt;
+        const uint32_t m = tfilter_mask(h);
+        cand = (pass_word(h) & m) == m;
+        if (LDS && big && cand) cand = (tfw[toff + tfilter_word(h, twl)] & m) == m;
+      }
+      push(cand, i, t);
+      // the short key: its 32-bit hash first (equal strings always agree),
+      // the 61-bit fingerprint only where that matches
+      if (ODD && live && oL && i + oL <= re && i < opos) {
+        const uint32_t ho = H[i + oL] - H[i] * ox + (uint32_t)salt;
+        if (ho == oh) odd61(i, salt);
+      }
+    }
+  };
+
+  if (threadIdx.x == 0) s_loaded = kNoText;
+  while (true) {
+    __syncthreads();  // the previous span is done with s_filt and s_span
+    if (threadIdx.x == 0) {
+      const uint64_t sp = atomicAdd((unsigned long long*)span_ctr, 1ull);
+      uint32_t tt = kNoText;
+      if (sp * span < W) {
+        const uint64_t w0 = sp * span;
+        const uint64_t w1 = (W - w0 < span ? W : w0 + span) - 1;
+        const uint32_t t0 = a.lv.rtext[segment_of(woff, R, w0)];
+        const uint32_t t1 = a.lv.rtext[segment_of(woff, R, w1)];
+        if (t0 == t1) tt = t0;
+      }
+      s_span = sp;
+      s_text = tt;
+    }
+    __syncthreads();
+    const uint64_t sp = s_span;
+    if (sp * span >= W) break;
+    const uint32_t st = s_text;
+    if (st != kNoText) {
+      const uint32_t wl = tfl[st];
+      const bool big = wl > kTextFilterLdsLog2;
+      const uint32_t lwl = big ? kTextFilterLdsLog2 : wl;
+      if (st != s_loaded) {
+        // 2^lwl >= 8 words: whole 16-byte groups
+        const uint64_t ng = (1ull << lwl) / 4;
+        const uint4* src = reinterpret_cast<const uint4*>(big ? a.tf_fold + a.tf_fold_off[st]
+                                                              : tfw + tfo[st]);
+        uint4* dst = reinterpret_cast<uint4*>(s_filt);
+        for (uint64_t k = threadIdx.x; k < ng; k += kTlThreads) dst[k] = src[k];
+        __syncthreads();
+        if (threadIdx.x == 0) s_loaded = st;
+      }
+      for (uint64_t c = wave; c < span_chunks; c += kTlWaves) {
+        const uint64_t ch = sp * span_chunks + c;
+        if (ch * kProbeTile >= W) break;
+        scan_chunk(ch, std::true_type{}, st, lwl, big);
+      }
+    } else {
+      for (uint64_t c = wave; c < span_chunks; c += kTlWaves) {
+        const uint64_t ch = sp * span_chunks + c;
+        if (ch * kProbeTile >= W) break;
+        scan_chunk(ch, std::false_type{}, 0u, 0u, false);
+      }
+    }
+  }
+  if (qn) {
+    wave_sync();
+    if ((uint32_t)lane < qn) probe_entry(q[lane]);
+  }
+}
+
+hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
+                             uint64_t max_windows, uint64_t span_chunks, uint64_t* span_ctr,
+                             hipStream_t s) {
+  if (a.lv.R == 0) return hipSuccess;
+  if (!a.tf_words || !a.pre32 || span_chunks == 0) return hipErrorInvalidValue;
+  const uint64_t span = span_chunks * kProbeTile;
+  const uint64_t spans = (max_windows + span - 1) / span;
+  // two resident 1024-thread workgroups per CU (256 CUs)
+  const unsigned grid = (unsigned)(spans < 512 ? (spans ? spans : 1) : 512);
+  const size_t lds = ((size_t)4 << kTextFilterLdsLog2) + (size_t)kTlWaves * kTlQueue * 8;
+  const bool lean = a.P == nullptr;
+#define BT_TL_LAUNCH(O, LN)                                                                 \
+  do {                                                                                      \
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_probe_text<O, LN>), \
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    if (e != hipSuccess) return e;                                                          \
+    k_probe_text<O, LN><<<grid, kTlThreads, lds, s>>>(a, woff, span_chunks, span_ctr);     \
+  } while (0)
+  if (has_odd) {
+    if (lean) BT_TL_LAUNCH(true, true); else BT_TL_LAUNCH(true, false);
+  } else {
+    if (lean) BT_TL_LAUNCH(false, true); else BT_TL_LAUNCH(false, false);
+  }
+#undef BT_TL_LAUNCH
+  return hipGetLastError();
+}
+
+// Word k of text big[b]'s folded filter: the OR of the 2^d full-filter words
+// k 2^d .. (k + 1) 2^d - 1, d = wl - kTextFilterLdsLog2.  A window's folded
+// word index is its full index shifted right by d (both take the top bits of
+// the same product), so the fold passes every window the full filter passes.
+__global__ void k_fold_filters(PhaseArgs a, const uint32_t* __restrict__ big, uint32_t nbig) {
+  const uint64_t per = 1ull << kTextFilterLdsLog2;
+  const uint64_t n = (uint64_t)nbig * per;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = big[i >> kTextFilterLdsLog2];
+    const uint64_t k = i & (per - 1);
+    const uint32_t d = a.tf_wl[t] - kTextFilterLdsLog2;
+    const uint32_t* src = a.tf_words + a.tf_off[t] + (k << d);
+    uint32_t v = 0;
+    for (uint64_t j = 0; j < (1ull << d); ++j) v |= src[j];
+    a.tf_fold[a.tf_fold_off[t] + k] = v;
+  }
+}
+
+hipError_t launch_fold_filters(const PhaseArgs& a, const uint32_t* big, uint32_t nbig,
+                               hipStream_t s) {
+  if (!nbig) return hipSuccess;
+  const uint64_t n = (uint64_t)nbig << kTextFilterLdsLog2;
+  const uint64_t g = (n + 255) / 256;
+  k_fold_filters<<<(unsigned)(g < 8192 ? g : 8192), 256, 0, s>>>(a, big, nbig);
+  return hipGetLastError();
+}
+
+}  // namespace bt

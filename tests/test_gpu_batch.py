@@ -146,3 +146,31 @@ def test_batch_many_small_texts(ctx, count):
     trees = ctx.build_batch(to_device(concat), offs, tau=2, leaf_len=2)
     for k, (T, tr) in enumerate(zip(texts, trees)):
         assert tr.serialize() == oracle.build_tree(T, 2, 2).canonical, "text %d" % k
+
+
+def test_batch_text_local_filters(ctx):
+    """Per-text key filters: texts small enough that a workgroup loads their
+    filter into LDS, texts whose filter stays in global memory (over 8192
+    blocks on a level), and runs of tiny texts whose windows share a span.
+    With dense and sampled prefix fingerprints and 12-bit fingerprints, every
+    tree equals the oracle's and the shared-filter build's."""
+    import paper_2512_23314_amd as bt
+    rng = np.random.default_rng(41)
+    texts = [synth.cfg1_text(1 << 20), synth.markov_versions(600000, 20000, 30, 3e-3, 16, 3)]
+    texts += [synth.dna_copies(int(n), max(1, int(n) // 16), 16, 2e-3, 2e-4, 8, int(rng.integers(1 << 30)))
+              for n in rng.integers(0, 3000, 300)]
+    texts += [synth.cfg1_text(1 << 17), synth.random_text(40000, 4, 8)]
+    concat, offs = _concat(texts)
+    d = to_device(concat)
+    want = [oracle.build_tree(T, 2, 16).canonical for T in texts]
+    for kw in ({}, {"lean": True}, {"debug_flags": bt.BT_DBG_WEAK_HASH}):
+        trees = ctx.build_batch(d, offs, tau=2, leaf_len=16, **kw)
+        shared = ctx.build_batch(d, offs, tau=2, leaf_len=16,
+                                 debug_flags=kw.get("debug_flags", 0) | bt.BT_DBG_SHARED_FILTERS,
+                                 lean=kw.get("lean", False))
+        for k, (w, tr, sh) in enumerate(zip(want, trees, shared)):
+            got = tr.serialize()
+            assert got == w, "text %d (length %d), %s" % (k, len(texts[k]), kw)
+            assert sh.serialize() == w
+            tr.free()
+            sh.free()
