@@ -196,6 +196,27 @@ BT_API int bt_prefix_fingerprints(bt_ctx* ctx, const uint8_t* d_text, uint64_t n
 BT_API int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
                           uint32_t x32, int sampled, uint64_t* d_P, uint32_t* d_H);
 
+/* ---- the same pass without allocating ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments,
+ * outputs and errors are those of bt_prefix_scan; the caller still provides
+ * d_text, d_P and d_H.  The scan's own scratch (its power tables and the
+ * look-back status words, which bt_prefix_scan takes from the context's pool)
+ * lives in a fixed device array of the library, BT_NOALLOC_SCRATCH_BYTES on
+ * each GPU the library runs on, held until the process ends.  That array
+ * bounds n: more than BT_NOALLOC_MAX_TEXT bytes -> BT_E_INVAL, before any
+ * device work.  The call allocates nothing (no hipMalloc or hipFree, no
+ * pooled buffer) and returns after its device work has completed.  Calls on
+ * one GPU share its array: calls that overlap on one GPU (from several host
+ * threads, or on several streams) race; calls ordered on one stream do not.
+ * Errors: BT_E_INVAL, BT_E_DEVICE (also when the array could not be located
+ * on this device when the context was created). */
+#define BT_NOALLOC_MAX_TEXT (1ull << 33)
+/* an upper bound on the array's size (4 MiB of status words plus the tables) */
+#define BT_NOALLOC_SCRATCH_BYTES ((4u << 20) + (128u << 10))
+BT_API int bt_prefix_scan_noalloc(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
+                                  uint32_t x32, int sampled, uint64_t* d_P, uint32_t* d_H);
+
 /* ---- builds ----
  * Build the block tree of the n bytes at d_text (device, caller-owned).
  * sigma is an upper bound on the number of distinct byte values (1..256); it

@@ -61,6 +61,7 @@ SIGNATURES = {
     "bt_ctx_reset_peak": (_i32, [_vp]),
     "bt_prefix_fingerprints": (_i32, [_vp, _vp, _u64, _u64, _vp]),
     "bt_prefix_scan": (_i32, [_vp, _vp, _u64, _u64, _u32, _i32, _vp, _vp]),
+    "bt_prefix_scan_noalloc": (_i32, [_vp, _vp, _u64, _u64, _u32, _i32, _vp, _vp]),
     "bt_build": (_i32, [_vp, _vp, _u64, _u32, _u32, _u32, ctypes.POINTER(_vp)]),
     "bt_build_ex": (_i32, [_vp, _vp, _u64, _u32, ctypes.POINTER(bt_params), ctypes.POINTER(_vp)]),
     "bt_build_batch": (_i32, [_vp, _vp, _vp, _u32, _u32, ctypes.POINTER(bt_params), _vp]),
@@ -198,6 +199,19 @@ class Context:
         H = torch.empty(n + 1, dtype=torch.int32, device=text.device)  # uint32 bits
         self._check(lib().bt_prefix_scan(self.h, _ptr(text), n, x, x32, 1 if sampled else 0,
                                          _ptr(P), _ptr(H)))
+        return P, H
+
+    def prefix_scan_noalloc(self, text, x, x32, sampled=False, P=None, H=None):
+        """prefix_scan through bt_prefix_scan_noalloc (the library allocates
+        nothing; P and H may be given to reuse caller buffers)."""
+        torch = _torch()
+        n = text.numel()
+        if P is None:
+            P = torch.empty(n // 16 + 1 if sampled else n + 1, dtype=torch.uint64, device=text.device)
+        if H is None:
+            H = torch.empty(n + 1, dtype=torch.int32, device=text.device)  # uint32 bits
+        self._check(lib().bt_prefix_scan_noalloc(self.h, _ptr(text), n, x, x32, 1 if sampled else 0,
+                                                 _ptr(P), _ptr(H)))
         return P, H
 
     # ---- builds

@@ -165,6 +165,48 @@ struct Buf {
 
 using namespace bt;
 
+// ------------------------------------------------------------------ fixed scratch
+//
+// bt_prefix_scan_noalloc keeps the prefix scan's scratch -- the power tables and
+// the look-back status words -- in this fixed device array instead of the
+// context's pool, so that the call allocates nothing.  Each GPU holds its own
+// copy until the process ends.  In host code the array's name is not a device
+// address: host code reaches the array only through the address
+// hipGetSymbolAddress gave for that device (scratch_base below).
+constexpr uint64_t kNoAllocMaxText = 1ull << 33;  // bytes of text (8 GiB)
+constexpr uint64_t kNoAllocTabWords = (sizeof(PfTab) + 255) / 256 * 32;  // whole 256-byte units
+constexpr uint64_t kNoAllocStatusWords = 2 * ((kNoAllocMaxText + kPfTile - 1) / kPfTile + 1) + 1;
+constexpr uint64_t kNoAllocWords = kNoAllocTabWords + kNoAllocStatusWords;
+static_assert(kNoAllocMaxText == BT_NOALLOC_MAX_TEXT, "the header states the text bound");
+static_assert(kNoAllocWords * 8 <= BT_NOALLOC_SCRATCH_BYTES, "the header states the size bound");
+static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch[kMaxDevices];  // per device: the array's address there, or null
+bool g_scratch_looked_up[kMaxDevices];
+
+// Look the array up on `device`, which must be current; once per device.
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_looked_up[device]) return;
+  g_scratch_looked_up[device] = true;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess)
+    g_scratch[device] = static_cast<uint64_t*>(p);
+  else
+    (void)hipGetLastError();  // reported by the entry point as BT_E_DEVICE
+}
+
+uint64_t* scratch_base(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch[device];
+}
+}  // namespace
+
 // ------------------------------------------------------------------ context
 
 struct KStat {
@@ -1494,6 +1536,7 @@ int bt_ctx_create(int device, void* hip_stream, bt_ctx** out) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BT_E_INVAL;
   if (hipSetDevice(device) != hipSuccess) return BT_E_DEVICE;
+  scratch_setup(device);
   bt_ctx* c = new (std::nothrow) bt_ctx;
   if (!c) return BT_E_NOMEM;
   c->dev = device;
@@ -1640,6 +1683,40 @@ int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x, u
     collect_events(ctx);
     return BT_OK;
   });
+}
+
+int bt_prefix_scan_noalloc(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
+                           uint32_t x32, int sampled, uint64_t* d_P, uint32_t* d_H) {
+  if (!ctx) return BT_E_INVAL;
+  if (x == 0 || x >= kP61Host || !d_P || !d_H || (!d_text && n)) {
+    ctx->err = "bt_prefix_scan_noalloc: need 1 <= x < 2^61-1 and valid pointers";
+    return BT_E_INVAL;
+  }
+  if (n > kNoAllocMaxText) {
+    ctx->err = "bt_prefix_scan_noalloc: texts of at most 2^33 bytes (the fixed scratch size)";
+    return BT_E_INVAL;
+  }
+  uint64_t* base = scratch_base(ctx->dev);
+  if (!base) {
+    ctx->err = "bt_prefix_scan_noalloc: the fixed scratch array of this device was not found";
+    return BT_E_DEVICE;
+  }
+  PfTab* tab = reinterpret_cast<PfTab*>(base);
+  uint64_t* status = base + kNoAllocTabWords;
+  hipError_t e = hipSetDevice(ctx->dev);
+  if (e == hipSuccess) {
+    fill_tab(ctx->h_tab, x, x32);
+    e = hipMemcpyAsync(tab, ctx->h_tab, sizeof(PfTab), hipMemcpyHostToDevice, ctx->stream);
+  }
+  if (e == hipSuccess) e = launch_prefix(d_text, n, d_P, sampled != 0, d_H, tab, status, ctx->stream);
+  // synchronous, like bt_prefix_scan: the pinned staging of the tables and the
+  // scratch are free again when the call returns
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    ctx->err = std::string("bt_prefix_scan_noalloc: ") + hipGetErrorString(e);
+    return BT_E_DEVICE;
+  }
+  return BT_OK;
 }
 
 int bt_build_ex(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
