@@ -132,12 +132,33 @@ typedef struct {
 
 /* ---- context ---- */
 
+/* Device memory supplier of a context (the benchmark spec's boundary: the caller's
+ * allocator, e.g. PyTorch's caching allocator, provides every device byte the
+ * library uses).  alloc returns `bytes` bytes of device memory of the
+ * context's device usable on `stream` (the context's stream), or NULL on
+ * failure; free returns a block alloc gave.  Both are called from the thread
+ * that calls into the library, never concurrently for one context.  The
+ * functions and `user` must stay valid until the context and every tree built
+ * on it have been released. */
+typedef struct {
+  void* (*alloc)(void* user, size_t bytes, void* stream);
+  void (*free)(void* user, void* ptr, void* stream);
+  void* user;
+} bt_allocator;
+
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
  * (a hipStream_t; NULL = the device's null stream).  The context owns a pool of
- * device scratch memory that grows on demand and is released by
- * bt_ctx_destroy.  Errors: BT_E_INVAL (bad device or out == NULL),
- * BT_E_DEVICE. */
+ * device memory that grows on demand: blocks come from `allocator` (or from
+ * hipMalloc when it is NULL; bt_ctx_create passes NULL), freed blocks are kept
+ * for reuse by size, and bt_ctx_trim and bt_ctx_destroy give the cached ones
+ * back (trees keep theirs until bt_tree_free).  When the allocator fails, the
+ * pool returns its cached blocks and asks once more; a second failure ends the
+ * call with BT_E_NOMEM, every block of that call back in the pool.  Errors:
+ * BT_E_INVAL (bad device, out == NULL, an allocator without both functions),
+ * BT_E_DEVICE, BT_E_NOMEM. */
 BT_API int bt_ctx_create(int device, void* hip_stream, bt_ctx** out);
+BT_API int bt_ctx_create_ex(int device, void* hip_stream, const bt_allocator* allocator,
+                            bt_ctx** out);
 BT_API void bt_ctx_destroy(bt_ctx* ctx);
 /* Message describing the last failure on this context (never NULL). */
 BT_API const char* bt_ctx_last_error(const bt_ctx* ctx);
@@ -259,6 +280,13 @@ BT_API int bt_level_info(const bt_tree* tree, uint32_t level, uint64_t* b, uint6
  * Errors: BT_E_INVAL for l outside 1..h-1. */
 BT_API int bt_level_copy(const bt_tree* tree, uint32_t level, uint64_t* marked_words,
                   uint64_t* ptr_block, uint64_t* ptr_off);
+/* The same copy enqueued on `stream` (a hipStream_t of the tree's device; NULL
+ * = the null stream) into host or device destinations, returning without
+ * waiting: the destinations hold the level once the stream reaches this point
+ * (pinned or device destinations; a pageable host destination makes the copy
+ * synchronous).  Errors: BT_E_INVAL, BT_E_DEVICE. */
+BT_API int bt_level_copy_async(const bt_tree* tree, uint32_t level, uint64_t* marked_words,
+                               uint64_t* ptr_block, uint64_t* ptr_off, void* stream);
 /* Number of leaf bytes (the sum of the level-h block lengths) and a copy of
  * them, block by block, into a host buffer. */
 BT_API int bt_leaves_size(const bt_tree* tree, uint64_t* bytes);

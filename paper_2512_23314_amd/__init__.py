@@ -37,6 +37,56 @@ _ERRNAMES = {BT_E_INVAL: "BT_E_INVAL", BT_E_NOMEM: "BT_E_NOMEM", BT_E_DEVICE: "B
              BT_E_INTERNAL: "BT_E_INTERNAL"}
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class bt_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class Allocator:
+    """A bt_allocator made of two Python callables: alloc(nbytes) -> device
+    address (int) or None, free(address).  The callbacks stay referenced for the
+    life of the process (the library may call them until the last tree of a
+    context is freed)."""
+
+    _keep = []
+
+    def __init__(self, alloc, free):
+        def _a(user, nbytes, stream):
+            try:
+                return alloc(int(nbytes))
+            except Exception:  # reported by the library as BT_E_NOMEM
+                return None
+
+        def _f(user, ptr, stream):
+            try:
+                free(int(ptr))
+            except Exception:
+                pass
+
+        self.c = bt_allocator(ALLOC_FN(_a), FREE_FN(_f), None)
+        Allocator._keep.append(self)
+
+
+_torch_allocators = {}
+
+
+def torch_allocator(device, stream):
+    """Device memory from PyTorch's caching allocator on `stream` (a
+    torch.cuda.Stream): the library's blocks count in torch's statistics and go
+    back to torch's cache when the context trims or is destroyed.  One per
+    (device, stream)."""
+    torch = _torch()
+    key = (device, stream.cuda_stream)
+    if key not in _torch_allocators:
+        _torch_allocators[key] = Allocator(
+            lambda n: torch.cuda.caching_allocator_alloc(n, device, stream),
+            torch.cuda.caching_allocator_delete)
+    return _torch_allocators[key]
+
+
 class bt_params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_uint32), ("leaf_len", ctypes.c_uint32),
                 ("root_block_len", ctypes.c_uint64), ("s_hint", ctypes.c_uint64),
@@ -49,6 +99,7 @@ _vp, _u64, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctype
 _pu64, _pu32, _pd = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "bt_ctx_create": (_i32, [_i32, _vp, ctypes.POINTER(_vp)]),
+    "bt_ctx_create_ex": (_i32, [_i32, _vp, ctypes.POINTER(bt_allocator), ctypes.POINTER(_vp)]),
     "bt_ctx_destroy": (None, [_vp]),
     "bt_ctx_last_error": (ctypes.c_char_p, [_vp]),
     "bt_ctx_trim": (_i32, [_vp]),
@@ -68,6 +119,7 @@ SIGNATURES = {
     "bt_tree_info": (_i32, [_vp, _pu64, _pu32, _pu64]),
     "bt_level_info": (_i32, [_vp, _u32, _pu64, _pu64, _pu64]),
     "bt_level_copy": (_i32, [_vp, _u32, _vp, _vp, _vp]),
+    "bt_level_copy_async": (_i32, [_vp, _u32, _vp, _vp, _vp, _vp]),
     "bt_leaves_size": (_i32, [_vp, _pu64]),
     "bt_leaves_copy": (_i32, [_vp, _vp]),
     "bt_serialize": (_i32, [_vp, _vp, _u64, _pu64]),
@@ -111,16 +163,26 @@ def _stream_handle(device):
 
 
 class Context:
-    """A bt_ctx bound to one device and the torch current stream at creation."""
+    """A bt_ctx bound to one device and the torch current stream at creation.
+    allocator: "torch" (default: PyTorch's caching allocator supplies the
+    library's device memory), None (the library's own hipMalloc), or an
+    Allocator."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, allocator="torch"):
         torch = _torch()
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
+        if allocator == "torch":
+            allocator = torch_allocator(device, stream)
+        self.allocator = allocator
         h = ctypes.c_void_p()
-        rc = lib().bt_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if allocator is None:
+            rc = lib().bt_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        else:
+            rc = lib().bt_ctx_create_ex(device, ctypes.c_void_p(stream.cuda_stream),
+                                        ctypes.byref(allocator.c), ctypes.byref(h))
         if rc != 0:
             raise BtError(rc, "bt_ctx_create failed")
         self.h = h

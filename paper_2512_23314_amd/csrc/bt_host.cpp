@@ -42,12 +42,20 @@ namespace bt {
 
 // ------------------------------------------------------------------ pool
 
+// Device memory of a context: blocks from the caller's allocator (bt_allocator)
+// or hipMalloc, kept on a free list when returned and reused by size; trim()
+// gives the cached ones back.
 class Pool {
  public:
-  explicit Pool(int dev) : dev_(dev) {}
+  Pool(int dev, const bt_allocator* a, hipStream_t s) : dev_(dev), stream_(s) {
+    if (a) {
+      ext_ = *a;
+      has_ext_ = true;
+    }
+  }
   ~Pool() {
     trim();
-    for (auto& kv : size_) (void)hipFree(kv.first);  // leaked buffers (trees outliving everything)
+    for (auto& kv : size_) release(kv.first);  // leaked buffers (trees outliving everything)
   }
   void* get(size_t bytes) {
     if (bytes == 0) bytes = 1;
@@ -61,27 +69,22 @@ class Pool {
       free_.erase(it);
       return p;
     }
-    void* p = nullptr;
     int old = -1;
     (void)hipGetDevice(&old);
     if (old != dev_) (void)hipSetDevice(dev_);
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
+    void* p = acquire(want);
+    if (!p) {
       // release cached blocks and try once more
       for (auto& kv : free_) {
-        (void)hipFree(kv.second);
+        release(kv.second);
         held_ -= size_[kv.second];
         size_.erase(kv.second);
       }
       free_.clear();
-      (void)hipGetLastError();
-      e = hipMalloc(&p, want);
+      p = acquire(want);
     }
     if (old != dev_ && old >= 0) (void)hipSetDevice(old);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return nullptr;
-    }
+    if (!p) return nullptr;
     size_[p] = want;
     held_ += want;
     in_use_ += want;
@@ -99,7 +102,7 @@ class Pool {
   void trim() {
     std::lock_guard<std::mutex> g(mu_);
     for (auto& kv : free_) {
-      (void)hipFree(kv.second);
+      release(kv.second);
       held_ -= size_[kv.second];
       size_.erase(kv.second);
     }
@@ -124,7 +127,24 @@ class Pool {
     const size_t g = 2u << 20;
     return (b + g - 1) / g * g;
   }
+  // one block from the caller's allocator or hipMalloc; null on failure
+  void* acquire(size_t bytes) {
+    if (has_ext_) return ext_.alloc(ext_.user, bytes, stream_);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void release(void* p) {
+    if (has_ext_) ext_.free(ext_.user, p, stream_);
+    else (void)hipFree(p);
+  }
   int dev_;
+  hipStream_t stream_;
+  bt_allocator ext_{};
+  bool has_ext_ = false;
   std::mutex mu_;
   std::multimap<size_t, void*> free_;
   std::unordered_map<void*, size_t> size_;
@@ -1532,7 +1552,12 @@ QTree qtree_of(const bt_tree* t) {
 extern "C" {
 
 int bt_ctx_create(int device, void* hip_stream, bt_ctx** out) {
+  return bt_ctx_create_ex(device, hip_stream, nullptr, out);
+}
+
+int bt_ctx_create_ex(int device, void* hip_stream, const bt_allocator* allocator, bt_ctx** out) {
   if (!out) return BT_E_INVAL;
+  if (allocator && (!allocator->alloc || !allocator->free)) return BT_E_INVAL;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BT_E_INVAL;
   if (hipSetDevice(device) != hipSuccess) return BT_E_DEVICE;
@@ -1541,7 +1566,7 @@ int bt_ctx_create(int device, void* hip_stream, bt_ctx** out) {
   if (!c) return BT_E_NOMEM;
   c->dev = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  c->pool = std::make_shared<Pool>(device);
+  c->pool = std::make_shared<Pool>(device, allocator, c->stream);
   if (hipHostMalloc((void**)&c->h_tab, sizeof(PfTab), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return BT_E_NOMEM;
@@ -1785,6 +1810,22 @@ int bt_level_copy(const bt_tree* t, uint32_t level, uint64_t* marked_words, uint
   if (ptr_off && L.u && hipMemcpy(ptr_off, L.po, L.u * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return BT_E_DEVICE;
   return BT_OK;
+}
+
+int bt_level_copy_async(const bt_tree* t, uint32_t level, uint64_t* marked_words,
+                        uint64_t* ptr_block, uint64_t* ptr_off, void* stream) {
+  if (!t || level < 1 || level >= t->h) return BT_E_INVAL;
+  const TreeLevel& L = t->lv[level - 1];
+  if (hipSetDevice(t->dev) != hipSuccess) return BT_E_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t nw = (L.c + 63) / 64;
+  hipError_t e = hipSuccess;
+  if (marked_words && nw) e = hipMemcpyAsync(marked_words, L.words, nw * 8, hipMemcpyDefault, s);
+  if (e == hipSuccess && ptr_block && L.u)
+    e = hipMemcpyAsync(ptr_block, L.pb, L.u * 8, hipMemcpyDefault, s);
+  if (e == hipSuccess && ptr_off && L.u)
+    e = hipMemcpyAsync(ptr_off, L.po, L.u * 8, hipMemcpyDefault, s);
+  return e == hipSuccess ? BT_OK : BT_E_DEVICE;
 }
 
 int bt_leaves_size(const bt_tree* t, uint64_t* bytes) {

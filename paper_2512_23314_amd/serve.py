@@ -10,6 +10,18 @@ next free slot; several slots build at once, so their kernels overlap on the
 device.  Finished trees stay resident (their bytes stay charged to the budget)
 until ``release``.  Query batches run on their own slot and stream.
 
+Memory.  Every context takes its device memory from PyTorch's caching
+allocator, so the library's bytes are torch's allocated bytes.  A request is
+charged its text, its copy in the batch, a fixed 16 MiB (a build's filters and
+smallest tables), and the library's measured peak per text byte beyond that
+(the most that any finished batch needed: bt_ctx_memory's peak less 16 MiB,
+over the batch's text bytes; before the first measurement, an upper bound
+computed from the sizes of the build's arrays).  The budget covers the resident
+trees, the charges of the builds in flight and the blocks the slots' pools keep
+cached; a slot trims its pool after a batch when that sum would exceed the
+budget, and a waiting slot trims its pool when its cached blocks keep the next
+request out.
+
 Every build is the library's exact construction, so a tree built in a mix is
 byte-identical to the same text built alone (tests/test_gpu_serve.py).
 """
@@ -40,6 +52,9 @@ def build_footprint(n, tau=4, leaf_len=16, sigma=256, rank_select=False):
     return foot
 
 
+_FIXED = 16 << 20  # per-request charge beyond the per-byte rate
+
+
 class _BuildReq:
     __slots__ = ("rid", "text", "t_arrive", "future", "foot")
 
@@ -58,7 +73,11 @@ class Server:
         import torch
         self.torch = torch
         self.budget = budget
-        self.used = 0
+        self.used = 0            # resident trees + charges of the builds in flight
+        self.cached = {}         # slot -> pooled bytes its context keeps for reuse
+        self.peak_per_byte = 0.0  # measured library peak beyond _FIXED, per text byte
+        self.measured = False
+        self.trims = 0
         self.params = dict(tau=tau, leaf_len=leaf_len, sigma=sigma, rank_select=rank_select)
         self.max_batch = max_batch
         self.device = device
@@ -84,12 +103,21 @@ class Server:
         self.qworker.start()
 
     # ---- client side
+    def footprint(self, n):
+        """Device bytes a build of an n-byte text is charged: the text on the
+        device and its copy in the batch, plus the library's peak (16 MiB and
+        the measured rate per text byte, or the computed bound before any build
+        finished)."""
+        if self.measured:
+            return 2 * n + int(self.peak_per_byte * n) + _FIXED
+        return n + build_footprint(n, self.params["tau"], self.params["leaf_len"],
+                                   self.params["sigma"], self.params["rank_select"])
+
     def submit_build(self, text):
         """text: uint8 numpy array (host) or uint8 CUDA tensor.  Returns a Future
         resolving to the request id once the tree is resident."""
         n = int(text.size if isinstance(text, np.ndarray) else text.numel())
-        foot = build_footprint(n, self.params["tau"], self.params["leaf_len"],
-                               self.params["sigma"], self.params["rank_select"])
+        foot = self.footprint(n)
         if foot > self.budget:
             raise BtError(-1, "request of %d bytes exceeds the memory budget" % n)
         with self.lock:
@@ -148,9 +176,10 @@ class Server:
         """Under the lock: the queued requests (in arrival order) that fit the
         free budget, at most max_batch of them."""
         batch, need = [], 0
+        cached = sum(self.cached.values())
         while self.pending and len(batch) < self.max_batch:
             r = self.pending[0]
-            if self.used + need + r.foot > self.budget:
+            if self.used + cached + need + r.foot > self.budget:
                 break
             batch.append(self.pending.popleft())
             need += r.foot
@@ -161,19 +190,38 @@ class Server:
         torch.cuda.set_device(self.device)
         stream = torch.cuda.Stream(self.device)
         ctx = Context(self.device, stream)
+        slot = threading.get_ident()
         while True:
+            trim = False
             with self.lock:
                 while not self.stop and not (self.pending and self._fits_head()):
+                    # the head request waits while this slot keeps cached blocks:
+                    # give them back
+                    if self.pending and self.cached.get(slot, 0):
+                        trim = True
+                        break
                     self.lock.wait(0.05)
-                if self.stop and not self.pending:
+                if trim:
+                    batch = None
+                elif self.stop and not self.pending:
                     break
-                batch, need = self._take_batch()
-                if not batch:
-                    continue
-                self.used += need
-                self.max_used = max(self.max_used, self.used)
-                self.inflight += 1
-                self.max_inflight = max(self.max_inflight, self.inflight)
+                else:
+                    batch, need = self._take_batch()
+                    if not batch:
+                        continue
+                if batch:
+                    self.used += need
+                    self.max_used = max(self.max_used, self.used)
+                    self.inflight += 1
+                    self.max_inflight = max(self.max_inflight, self.inflight)
+            if trim:
+                ctx.trim()
+                m = ctx.memory()
+                with self.lock:
+                    self.cached[slot] = m["held"] - m["in_use"]
+                    self.trims += 1
+                    self.lock.notify_all()
+                continue
             try:
                 with torch.cuda.stream(stream):
                     parts = [r.text if not isinstance(r.text, np.ndarray)
@@ -184,9 +232,18 @@ class Server:
                         offs.append(offs[-1] + int(p.numel()))
                     concat = torch.cat([p.reshape(-1) for p in parts]) if parts else None
                     stream.synchronize()
+                    base = ctx.memory()["in_use"]
+                    ctx.reset_peak()
                     trees = ctx.build_batch(concat, offs, **self.params)
+                    del concat, parts
                 t_done = time.perf_counter()
+                mem = ctx.memory()
+                nbytes = offs[-1]
                 with self.lock:
+                    if nbytes:
+                        over = max(0, mem["peak"] - base - _FIXED)
+                        self.peak_per_byte = max(self.peak_per_byte, over / nbytes)
+                        self.measured = True
                     self.batches += 1
                     for r, tr in zip(batch, trees):
                         nb = tr.device_bytes()
@@ -196,6 +253,17 @@ class Server:
                         self.built_bytes += int(r.text.size if isinstance(r.text, np.ndarray) else r.text.numel())
                     self.used -= need
                     self.inflight -= 1
+                    # this slot's cached blocks count against the budget: give
+                    # them back when the sum would not fit
+                    self.cached[slot] = mem["held"] - mem["in_use"]
+                    trim = self.used + sum(self.cached.values()) > self.budget
+                if trim:
+                    ctx.trim()
+                    m2 = ctx.memory()
+                    with self.lock:
+                        self.cached[slot] = m2["held"] - m2["in_use"]
+                        self.trims += 1
+                with self.lock:
                     self.lock.notify_all()
                 for r in batch:
                     r.future.set_result(r.rid)
@@ -209,7 +277,7 @@ class Server:
         ctx.close()
 
     def _fits_head(self):
-        return self.used + self.pending[0].foot <= self.budget
+        return self.used + sum(self.cached.values()) + self.pending[0].foot <= self.budget
 
     def _query_worker(self):
         torch = self.torch
@@ -261,4 +329,6 @@ class Server:
                 "query_p50_ms": pct(self.query_lat, 50) and pct(self.query_lat, 50) * 1e3,
                 "query_p99_ms": pct(self.query_lat, 99) and pct(self.query_lat, 99) * 1e3,
                 "built_bytes": self.built_bytes, "max_concurrent_builds": self.max_inflight,
-                "max_admitted_bytes": self.max_used}
+                "max_admitted_bytes": self.max_used, "peak_per_byte": self.peak_per_byte,
+                "measured": self.measured,
+                "trims": self.trims}

@@ -37,3 +37,12 @@ def test_status_strings():
 def test_params_layout():
     import ctypes
     assert ctypes.sizeof(bt.bt_params) == 40
+
+
+def test_ctx_create_ex_rejects_incomplete_allocator():
+    """An allocator without both functions is refused before any device call."""
+    import ctypes
+    al = bt.bt_allocator(bt.ALLOC_FN(), bt.FREE_FN(), None)
+    h = ctypes.c_void_p()
+    assert bt.lib().bt_ctx_create_ex(0, None, ctypes.byref(al), ctypes.byref(h)) == bt.BT_E_INVAL
+    assert not h.value

@@ -69,7 +69,7 @@ def test_admission_respects_budget():
     torch_cuda()
     from paper_2512_23314_amd.serve import Server, build_footprint
     texts = _requests(3, 12)
-    big = max(build_footprint(len(T), 4, 16, 4, True) for T in texts)
+    big = max(len(T) + build_footprint(len(T), 4, 16, 4, True) for T in texts)
     srv = Server(budget=big + (1 << 20), slots=3, max_batch=4, tau=4, leaf_len=16, sigma=4)
     futs = [srv.submit_build(T) for T in texts]
     rids = [f.result(timeout=120) for f in futs]
@@ -86,3 +86,36 @@ def test_admission_respects_budget():
     assert srv.used == 0
     srv.close()
     assert st["max_admitted_bytes"] <= srv.budget
+
+
+def test_device_bytes_within_budget():
+    """The device bytes the server really holds stay within its budget.  Every
+    context takes its memory from torch's caching allocator, so torch's exact
+    peak of allocated bytes over the run (the texts, uploaded by the client
+    beforehand, excluded) bounds the library's bytes, its pools' cached blocks
+    and the batches' text copies.  The budget is tight: a few requests at a
+    time, so slots wait, and trim their pools when the cached blocks would not
+    fit."""
+    torch = torch_cuda()
+    from paper_2512_23314_amd.serve import Server, build_footprint
+    texts = _requests(5, 40)
+    dev = [torch.from_numpy(T).to("cuda:0") for T in texts]
+    torch.cuda.synchronize()
+    biggest = max(len(T) + build_footprint(len(T), 4, 16, 4, True) for T in texts)
+    budget = 3 * biggest
+    base = torch.cuda.memory_allocated(0)
+    torch.cuda.reset_peak_memory_stats(0)
+    srv = Server(budget=budget, slots=3, max_batch=6, tau=4, leaf_len=16, sigma=4)
+    rids = [f.result(timeout=120) for f in [srv.submit_build(d) for d in dev]]
+    held = srv.used
+    peak = torch.cuda.max_memory_allocated(0) - base
+    st = srv.stats()
+    for T, rid in zip(texts, rids):
+        assert srv.tree(rid).n == len(T)
+    for rid in rids:
+        srv.release(rid)
+    srv.close()
+    assert peak <= budget, "device bytes %d over the budget %d" % (peak, budget)
+    assert st["max_admitted_bytes"] <= budget
+    assert 0 < held <= budget
+    assert st["measured"]
