@@ -482,7 +482,7 @@ def summarize_stats(stats_dir, bench_json, cmd, out, top=20):
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     b = _bench_line(bench_json)
-    probe = [r for r in rows if "k_probe_scan<" in r["Name"]]
+    probe = [r for r in rows if any(k in r["Name"] for k in PROBE_KERNELS)]
     calls = sum(int(r["Calls"]) for r in probe)
     pns = sum(float(r["TotalDurationNs"]) for r in probe)
     rf = b["roofline"]
@@ -492,7 +492,8 @@ def summarize_stats(stats_dir, bench_json, cmd, out, top=20):
              "launch %.4f ms (HIP events on the library stream), %d launches per step." % (
                  b["value"], b["unit"], b["ms_per_step"], rf["avg_launch_ms"], rf["launches_per_step"]),
              "",
-             "rocprofv3: k_probe_scan (all instantiations) %d calls, average %.4f ms "
+             "rocprofv3: the probe scan (k_probe_scan and k_probe_text, all instantiations) %d "
+             "calls, average %.4f ms "
              "(ratio to the HIP-event average %.3f); warmup and timed steps launch the same "
              "kernels, so the averages compare." % (calls, pns / max(calls, 1) / 1e6,
                                                      pns / max(calls, 1) / 1e6 / rf["avg_launch_ms"]),
@@ -507,10 +508,16 @@ def summarize_stats(stats_dir, bench_json, cmd, out, top=20):
     print("wrote", out)
 
 
-def _counter_per_launch(d, needle):
-    rows = [r for r in _csv_rows(_find_csv(d, "counter_collection.csv")) if needle in r["Kernel_Name"]]
+# the probe scan's kernels: the shared-filter scan and the per-text scan of batches
+PROBE_KERNELS = ("k_probe_scan<", "k_probe_text<")
+
+
+def _counter_per_launch(d, needles):
+    needles = (needles,) if isinstance(needles, str) else needles
+    rows = [r for r in _csv_rows(_find_csv(d, "counter_collection.csv"))
+            if any(nd in r["Kernel_Name"] for nd in needles)]
     if not rows:
-        raise ValueError("no %s dispatches in %s" % (needle, d))
+        raise ValueError("no %s dispatches in %s" % (needles, d))
     return sum(float(r["Counter_Value"]) for r in rows) / len(rows), len(rows)
 
 
@@ -522,8 +529,8 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, be
     cw, _ = _counter_per_launch(cwrite_dir, "copyBuffer")
     # a copy of B bytes reads B and writes B: scale each counter (KiB) to that
     ff, fw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
-    kf, n = _counter_per_launch(fetch_dir, "k_%s<" % kernel)
-    kw, _ = _counter_per_launch(write_dir, "k_%s<" % kernel)
+    kf, n = _counter_per_launch(fetch_dir, PROBE_KERNELS)
+    kw, _ = _counter_per_launch(write_dir, PROBE_KERNELS)
     fetch, write = kf * 1024.0 * ff, kw * 1024.0 * fw
     b = _bench_line(bench_json)
     algo = b["roofline"].get("bytes_per_launch")
@@ -742,7 +749,7 @@ def summarize_launches(launch_json, pmc_dirs, calib, cmds, out_md):
     per = collections.OrderedDict()
     for d in pmc_dirs:
         for r in _csv_rows(_find_csv(d, "counter_collection.csv")):
-            if "k_probe_scan<" not in r["Kernel_Name"]:
+            if not any(k in r["Kernel_Name"] for k in PROBE_KERNELS):
                 continue
             key = int(r.get("Dispatch_Id", r.get("Correlation_Id", 0)))
             per.setdefault(r["Counter_Name"], collections.OrderedDict())[key] = float(r["Counter_Value"])
