@@ -53,6 +53,9 @@ WORKLOADS = {
     "dna2g": ("cfg3", 4, 4, 16, 1, "dna2g_t4_l16",
               "2 GiB DNA collection, sigma 4: 256 haplotypes of an 8 MiB reference, 0.1% SNPs, "
               "0.01% indels of length 1-20"),
+    "dna2g_sweep": ("cfg3sweep", 4, 0, 0, 1, None,
+                    "the 2 GiB DNA collection built at every tau in {2,4,8,16} x leaf_len in "
+                    "{8,16,32}, one root block"),
     "versioned256m": ("cfg2", 96, 4, 16, 1, "versioned256m",
                       "256 MiB versioned text, sigma 96: 1024 versions of a 256 KiB order-2 "
                       "Markov document, 0.05% edit runs per version"),
@@ -360,6 +363,54 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
         out["batched_vs_plain"] = plain
     out["kernels"] = kt
     out["probe_scan_launches"] = {"columns": ["L", "windows", "us", "algorithmic_bytes"], "rows": pl}
+    return out
+
+
+def bench_sweep(args, desc):
+    """Every (tau, leaf) point of the 2 GiB DNA collection's sweep: each point's
+    tree is checked against its expected tree, then timed (1 warm-up, then
+    min(steps, 3) builds)."""
+    import torch
+    import paper_2512_23314_amd as bt
+    import synth
+    T = synth.cfg3_text()
+    n = int(T.size)
+    d = torch.from_numpy(T).to("cuda:0")
+    torch.cuda.synchronize()
+    ctx = bt.Context(0)
+    steps = max(1, min(args.steps, 3))
+    rows, tot_ms = [], 0.0
+    for tau in (2, 4, 8, 16):
+        for leaf in (8, 16, 32):
+            name = "dna2g_t%d_l%d" % (tau, leaf)
+            tree = ctx.build(d, sigma=4, tau=tau, leaf_len=leaf)
+            parity = check_single(tree, name, T)
+            h = tree.height
+            tree.free()
+            ctx.reset_stats()
+            ctx.profile(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.build(d, sigma=4, tau=tau, leaf_len=leaf).free()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            ctx.profile(False)
+            rf = roofline(ctx, steps, name)
+            tot_ms += ms
+            rows.append({"tau": tau, "leaf_len": leaf, "levels": h, "ms_per_build": round(ms, 3),
+                         "mb_s": round(n / 1e6 / (ms / 1e3), 1), "probe_scan_frac": rf["frac"],
+                         "probe_scan_ms": round(rf["avg_launch_ms"] * rf["launches_per_step"], 3),
+                         "tree_sha256": parity["sha256"][:16]})
+            log("%s: %.1f ms, %.0f MB/s, %d levels, probe scan %.3f of peak" % (
+                name, ms, n / 1e6 / (ms / 1e3), h, rf["frac"]))
+    ctx.close()
+    out = base_line("dna2g_sweep", 12 * n / 1e6 / (tot_ms / 1e3), tot_ms / 12, steps, 1,
+                    {"description": desc, "n": n, "sigma": 4, "points": 12})
+    out["roofline"] = None
+    out["cpu_baseline"] = None
+    out["parity"] = {"expected_trees": "tests/golden/fullsize_trees.json:dna2g_t*_l*", "match": True}
+    out["sweep"] = rows
     return out
 
 
@@ -861,6 +912,10 @@ def main():
     try:
         if gen == "cfg5":
             return bench_serve(args, sigma, tau, leaf, desc)
+        if gen == "cfg3sweep":
+            out = bench_sweep(args, desc)
+            print(json.dumps(out), flush=True)
+            return
         if gen == "cfg4":
             out = bench_batch(args, sigma, tau, leaf, golden, desc)
             if not args.no_legs:
