@@ -215,6 +215,21 @@ def probe_launches(ctx, steps):
     return [[int(L), int(u), round(ms * 1e3, 1), int(by)] for _, L, u, ms, by in rows[-per:]] if per else []
 
 
+def phase_totals(ctx, steps, path=None, workload=None):
+    """Per-step sums of the phase counters of the timed steps (and the last
+    step's phases as JSON lines to `path`)."""
+    ph = ctx.phases()
+    if not ph:
+        return None
+    per = len(ph) // max(steps, 1)
+    if path:
+        with open(path, "w") as f:
+            for r in ph[-per:]:
+                f.write(json.dumps(dict(r, workload=workload)) + "\n")
+    keys = ("keys", "windows", "candidates", "verified", "collisions")
+    return {k: sum(r[k] for r in ph) // max(steps, 1) for k in keys}
+
+
 def base_line(workload, value, ms, steps, warmup, config):
     return {"metric": METRIC, "value": round(value, 2), "unit": "MB/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
@@ -327,6 +342,7 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
     rf = roofline(ctx, args.steps, "batch4096")
     kt = kernel_table(ctx, args.steps)
     pl = probe_launches(ctx, args.steps)
+    pt = phase_totals(ctx, args.steps, args.phase_log, "batch4096")
     if args.launch_log:
         with open(args.launch_log, "w") as f:
             json.dump({"workload": "batch4096", "probe_scan": pl}, f)
@@ -363,6 +379,7 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
         out["batched_vs_plain"] = plain
     out["kernels"] = kt
     out["probe_scan_launches"] = {"columns": ["L", "windows", "us", "algorithmic_bytes"], "rows": pl}
+    out["phase_counters_per_step"] = pt
     return out
 
 
@@ -452,6 +469,7 @@ def bench_single(args, workload, steps, warmup, sublegs=False):
     rf = roofline(ctx, steps, workload)
     kt = kernel_table(ctx, steps)
     pl = probe_launches(ctx, steps)
+    pt = phase_totals(ctx, steps, args.phase_log if workload == args.workload else None, workload)
     if args.launch_log and workload == args.workload:
         with open(args.launch_log, "w") as f:
             json.dump({"workload": workload, "probe_scan": pl}, f)
@@ -469,6 +487,7 @@ def bench_single(args, workload, steps, warmup, sublegs=False):
     out["parity"] = parity
     out["kernels"] = kt
     out["probe_scan_launches"] = {"columns": ["L", "windows", "us", "algorithmic_bytes"], "rows": pl}
+    out["phase_counters_per_step"] = pt
     if sublegs:
         if not args.prune:
             out["pruned_build"] = pruned_leg(ctx, d, n, sigma, tau, leaf, s_hint, step)
@@ -865,6 +884,8 @@ def main():
                     help="bytes of the workload the CPU baseline builds")
     ap.add_argument("--launch-log", metavar="FILE",
                     help="write the probe-scan launches of the last timed step as JSON")
+    ap.add_argument("--phase-log", metavar="FILE",
+                    help="write the per-phase device counters of the last timed step as JSON lines")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
                          "known-size reference for the FETCH_SIZE/WRITE_SIZE counters)")

@@ -186,6 +186,21 @@ BT_API int bt_ctx_reset_stats(bt_ctx* ctx);
  * 4 bytes each (8 without the 32-bit pre-filter), and the union is counted,
  * i.e. 4 (1 + min(L, 1024) / 1024) bytes per window.  Any output may be NULL.
  * Errors: BT_E_INVAL (idx out of range). */
+/* Per-phase device counters of the builds run while profiling, since the last
+ * bt_ctx_reset_stats, in order (at most 65536 kept).  Record idx < count, nine
+ * words:
+ *   rec[0] level step (0-based; a batch's texts share steps by block length),
+ *   rec[1] block length b, rec[2] phase (1: pairs of blocks, 2: blocks),
+ *   rec[3] blocks of the level (all texts), rec[4] keys inserted into the table
+ *   (keys the level above proved to be copies stay out), rec[5] windows
+ *   scanned, rec[6] windows that passed the scan's filters and probed the
+ *   table, rec[7] keys verified against the text (their leftmost hit is not
+ *   their own start), rec[8] collisions: verifications that failed (a
+ *   fingerprint collision, or a hit in another text of the batch), each then
+ *   resolved by the exact retry walk.
+ * Errors: BT_E_INVAL (idx out of range). */
+BT_API int bt_ctx_phase_count(const bt_ctx* ctx, uint64_t* count);
+BT_API int bt_ctx_phase_record(const bt_ctx* ctx, uint64_t idx, uint64_t* rec);
 BT_API int bt_ctx_launch_count(const bt_ctx* ctx, uint64_t* count);
 BT_API int bt_ctx_launch_record(const bt_ctx* ctx, uint64_t idx, char* name, uint64_t name_cap,
                                 uint64_t* window_len, double* units, double* ms, double* bytes);

@@ -107,6 +107,8 @@ SIGNATURES = {
     "bt_ctx_kernel_stats": (_i32, [_vp, ctypes.c_char_p, _pu64, _pd, _pd, _pd]),
     "bt_ctx_reset_stats": (_i32, [_vp]),
     "bt_ctx_launch_count": (_i32, [_vp, _pu64]),
+    "bt_ctx_phase_count": (_i32, [_vp, _pu64]),
+    "bt_ctx_phase_record": (_i32, [_vp, _u64, _vp]),
     "bt_ctx_launch_record": (_i32, [_vp, _u64, ctypes.c_char_p, _u64, _pu64, _pd, _pd, _pd]),
     "bt_ctx_memory": (_i32, [_vp, _pu64, _pu64, _pu64]),
     "bt_ctx_reset_peak": (_i32, [_vp]),
@@ -229,6 +231,21 @@ class Context:
             self._check(lib().bt_ctx_launch_record(self.h, k, name, 64, ctypes.byref(wl), ctypes.byref(un),
                                                    ctypes.byref(ms), ctypes.byref(by)))
             out.append((name.value.decode(), wl.value, un.value, ms.value, by.value))
+        return out
+
+    PHASE_FIELDS = ("step", "b", "phase", "blocks", "keys", "windows", "candidates", "verified",
+                    "collisions")
+
+    def phases(self):
+        """Per-phase device counters of the profiled builds since reset_stats(),
+        as dicts with the fields PHASE_FIELDS (see bt_ctx_phase_record)."""
+        n = ctypes.c_uint64()
+        self._check(lib().bt_ctx_phase_count(self.h, ctypes.byref(n)))
+        out = []
+        rec = np.zeros(9, np.uint64)
+        for k in range(n.value):
+            self._check(lib().bt_ctx_phase_record(self.h, k, rec.ctypes.data_as(ctypes.c_void_p)))
+            out.append(dict(zip(self.PHASE_FIELDS, (int(v) for v in rec))))
         return out
 
     def trim(self):

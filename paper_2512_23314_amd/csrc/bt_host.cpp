@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -243,6 +244,12 @@ struct PendingEv {
   uint64_t wlen;  // window length of a scan launch (0 otherwise)
 };
 
+// One phase of a profiled build: step, block length, phase, blocks, then the
+// device counters (keys, candidates, windows, verified, collisions).
+struct PhaseRec {
+  uint64_t v[9];
+};
+
 // One timed launch, in launch order.
 struct LaunchRec {
   std::string name;
@@ -259,6 +266,7 @@ struct bt_ctx {
   bool profile = false;
   std::map<std::string, KStat> stats;
   std::vector<LaunchRec> launches;  // at most kLaunchLogMax, oldest first
+  std::vector<PhaseRec> phases;     // at most kLaunchLogMax
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_free;
   uint64_t* h_small = nullptr;  // pinned host words for count read-back
@@ -744,6 +752,13 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   Buf<uint64_t> d_err = alloc<uint64_t>(ctx, 1);
   HIPCHK(ctx, launch_fill_u64(d_err.p, 0, 1, s));
   Buf<uint64_t> wstats = alloc<uint64_t>(ctx, 2 * (uint64_t)H + 2);
+  // per (step, phase) device counters while profiling (PhaseArgs.pc)
+  Buf<uint64_t> pstats;
+  std::vector<std::array<uint64_t, 4>> phase_host;  // step, b, phase, blocks
+  if (ctx->profile) {
+    pstats = alloc<uint64_t>(ctx, 2 * (uint64_t)H * kPcWords);
+    HIPCHK(ctx, launch_fill_u64(pstats.p, 0, 2 * (uint64_t)H * kPcWords, s));
+  }
 
   // ---- level state
   uint64_t c = 0;
@@ -1059,6 +1074,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     // nkeys: keys of the phase (pairs of consecutive blocks, or unmarked blocks)
     auto run_phase = [&](int phase, uint64_t nkeys) {
       a.phase = phase;
+      a.pc = ctx->profile ? pstats.p + (2 * (uint64_t)step + (phase - 1)) * kPcWords : nullptr;
+      if (ctx->profile) phase_host.push_back({step, b, (uint64_t)phase, c});
       a.Lmain = phase == 1 ? 2 * b : b;
       a.xLmain = host_pow61(x, a.Lmain);
       // LDS filter: about 32 bits per key, at most 2^19 (64 KiB), two bits per
@@ -1217,6 +1234,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       timed(ctx, "verify", 0, 0, nullptr, 0, [&] { return launch_verify(a, vb, a.Lmain, s); });
       HIPCHK(ctx, launch_finish(a, vb, s));
       HIPCHK(ctx, launch_retry(a, vb, s));
+      if (a.pc) HIPCHK(ctx, launch_phase_record(a.pc, wst, vb, s));
     };
 
     // ---- phase 1: pairs (a3, a4) and marks (a5)
@@ -1442,8 +1460,19 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   }
 
   std::vector<uint64_t> fin;
-  read_words(ctx, {{d_err.p, 1}, {wstats.p, ctx->profile ? 2 * (uint64_t)H + 2 : 0}}, fin);
-  if (ctx->profile) collect_events(ctx, wstats.p, fin.data() + 1, 2 * (uint64_t)H + 2);
+  const uint64_t npw = ctx->profile ? 2 * (uint64_t)H * kPcWords : 0;
+  read_words(ctx, {{d_err.p, 1}, {wstats.p, ctx->profile ? 2 * (uint64_t)H + 2 : 0},
+                   {pstats.p, npw}}, fin);
+  if (ctx->profile) {
+    collect_events(ctx, wstats.p, fin.data() + 1, 2 * (uint64_t)H + 2);
+    const uint64_t* pw = fin.data() + 1 + 2 * (uint64_t)H + 2;
+    for (const auto& ph : phase_host) {
+      if (ctx->phases.size() >= kLaunchLogMax) break;
+      const uint64_t* r = pw + (2 * ph[0] + (ph[2] - 1)) * kPcWords;
+      ctx->phases.push_back({{ph[0], ph[1], ph[2], ph[3], r[kPcKeys], r[kPcWindows], r[kPcCand],
+                              r[kPcVerified], r[kPcCollisions]}});
+    }
+  }
   if (fin[0]) {
     ctx->err = "device check failed: a pointer does not target a marked block or pair";
     return BT_E_INTERNAL;
@@ -1624,6 +1653,19 @@ int bt_ctx_reset_stats(bt_ctx* ctx) {
   if (!ctx) return BT_E_INVAL;
   ctx->stats.clear();
   ctx->launches.clear();
+  ctx->phases.clear();
+  return BT_OK;
+}
+
+int bt_ctx_phase_count(const bt_ctx* ctx, uint64_t* count) {
+  if (!ctx || !count) return BT_E_INVAL;
+  *count = ctx->phases.size();
+  return BT_OK;
+}
+
+int bt_ctx_phase_record(const bt_ctx* ctx, uint64_t idx, uint64_t* rec) {
+  if (!ctx || !rec || idx >= ctx->phases.size()) return BT_E_INVAL;
+  std::memcpy(rec, ctx->phases[idx].v, sizeof(ctx->phases[idx].v));
   return BT_OK;
 }
 

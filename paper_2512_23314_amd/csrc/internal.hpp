@@ -150,7 +150,15 @@ struct PhaseArgs {
   // k 2^d .., a superset test: a window failing it fails the full filter).
   uint32_t* tf_fold;
   const uint64_t* tf_fold_off;  // [T] (read only for such texts)
+  // Counters of this phase (profiling only, else null): [kPcKeys] keys
+  // inserted by k_keys, [kPcCand] windows that passed the scan's filters.
+  uint64_t* pc;
 };
+// Words per phase record: keys inserted, candidates, windows scanned, keys
+// verified (hit elsewhere than at their own start), collisions (verification
+// failed: the exact retry ran).
+constexpr int kPcKeys = 0, kPcCand = 1, kPcWindows = 2, kPcVerified = 3, kPcCollisions = 4;
+constexpr int kPcWords = 8;
 
 // Scan entries and segments (level.hip, "scan segments").
 constexpr uint8_t kSkipInterior = 1;  // windows ending inside the entry are copies
@@ -277,6 +285,9 @@ struct VerifyBufs {
   uint64_t* counts; // [2]: verify count, retry count
 };
 hipError_t launch_resolve(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s);
+// Profiling: copy the phase's window count and verification counts into pc.
+hipError_t launch_phase_record(uint64_t* pc, const uint64_t* windows, const VerifyBufs& v,
+                               hipStream_t s);
 hipError_t launch_verify(const PhaseArgs& a, const VerifyBufs& v, uint64_t max_len,
                          hipStream_t s);
 hipError_t launch_finish(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s);

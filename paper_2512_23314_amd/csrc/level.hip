@@ -54,8 +54,16 @@ __device__ __forceinline__ void set_prefix_bit(const PhaseArgs& a, uint64_t st) 
   atomicOr(&a.bfilt[bit >> 5], 1u << (bit & 31));
 }
 
+// Profiling: add a per-thread count to *p, one atomic per wave.
+__device__ __forceinline__ void wave_count(uint64_t* p, uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long*)p, (unsigned long long)v);
+}
+
 __global__ void k_keys(PhaseArgs a) {
   const LevelDev lv = a.lv;
+  uint64_t inserted = 0;
   GRID_STRIDE(j, lv.c) {
     const uint32_t t = lv.text[j];
     const uint64_t st = lv.st[j];
@@ -90,6 +98,7 @@ __global__ void k_keys(PhaseArgs a) {
         continue;
       }
     }
+    ++inserted;
     const uint64_t xp = (L == a.Lmain) ? a.xLmain : pow61(a.x, L);
     const uint64_t fp = finish_fp(win61_any(a, st, L, xp), a.tx.tsalt[t], a.fpmask);
     a.k.fp[j] = fp;
@@ -147,6 +156,7 @@ __global__ void k_keys(PhaseArgs a) {
       if (a.bfilt_bits) set_prefix_bit(a, st);
     }
   }
+  if (a.pc) wave_count(a.pc + kPcKeys, inserted);
 }
 
 hipError_t launch_keys(const PhaseArgs& a, hipStream_t s) {
@@ -501,12 +511,14 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     probe(slots, tags, mask, fp61(i, salt), i);
   };
   // whole wave: append the lanes' candidates; probe 64 once 64 are waiting
+  uint64_t ncand = 0;  // wave-uniform: windows that passed the filters
   const auto push = [&](bool cand, uint64_t i, uint32_t t) {
     const uint64_t bal = __ballot(cand);
     if (!bal) return;
     const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
     if (cand) q[qn + my] = ((uint64_t)t << kQPosBits) | i;
     qn += (uint32_t)__popcll(bal);
+    ncand += (uint64_t)__popcll(bal);
     if (qn >= 64) {
       wave_sync();
       const uint64_t e = q[lane];
@@ -609,8 +621,12 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
             for (int k = 0; k < 8; ++k) {
               const uint64_t i = i0 + 64ull * (k0 + k);
               const bool cand = FILTER ? pass61(fv[k]) : true;
-              if (MODE == 1) push(cand, i, t);
-              else if (cand) probe(slots, tags, mask, fv[k], i);
+              if (MODE == 1) {
+                push(cand, i, t);
+              } else {
+                ncand += (uint64_t)__popcll(__ballot(cand));
+                if (cand) probe(slots, tags, mask, fv[k], i);
+              }
             }
           }
         }
@@ -646,6 +662,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         }
       }
       if (MODE == 1) push(cand, i, t);
+      else ncand += (uint64_t)__popcll(__ballot(cand));
       // the short key: its 32-bit hash first (equal strings always agree),
       // the 61-bit fingerprint only where that matches
       if (ODD && live && oL && i + oL <= re && i < opos) {
@@ -658,6 +675,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     wave_sync();
     if ((uint32_t)lane < qn) probe_entry(q[lane]);
   }
+  if (a.pc && lane == 0 && ncand) atomicAdd((unsigned long long*)(a.pc + kPcCand), (unsigned long long)ncand);
 }
 
 // Dynamic LDS beyond 64 KiB has to be allowed per kernel.
@@ -795,12 +813,14 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   };
   // whole wave: append the lanes' candidates; check 64 once 64 are waiting.
   // Bit 63 of an entry: the main-length window does not fit the run.
+  uint64_t ncand = 0;  // wave-uniform: windows that passed the filter
   const auto push = [&](bool cand, uint64_t e) {
     const uint64_t bal = __ballot(cand);
     if (!bal) return;
     const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
     if (cand) q[qn + my] = e;
     qn += (uint32_t)__popcll(bal);
+    ncand += (uint64_t)__popcll(bal);
     if (qn >= 64) {
       wave_sync();
       const uint64_t e0 = q[lane];
@@ -908,6 +928,7 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     wave_sync();
     if ((uint32_t)lane < qn) check(q[lane]);
   }
+  if (a.pc && lane == 0 && ncand) atomicAdd((unsigned long long*)(a.pc + kPcCand), (unsigned long long)ncand);
 }
 
 hipError_t launch_byte_scan(const PhaseArgs& a, const uint64_t* woff, bool has_odd, bool has_salt,
@@ -997,6 +1018,20 @@ __global__ __launch_bounds__(kResolveThreads) void k_resolve(PhaseArgs a, Verify
 
 hipError_t launch_resolve(const PhaseArgs& a, const VerifyBufs& v, hipStream_t s) {
   k_resolve<<<grid_for(a.lv.c, kResolveThreads, 2048), kResolveThreads, 0, s>>>(a, v);
+  return hipGetLastError();
+}
+
+__global__ void k_phase_record(uint64_t* pc, const uint64_t* windows, const uint64_t* counts) {
+  if (threadIdx.x == 0) {
+    pc[kPcWindows] = windows ? *windows : 0;
+    pc[kPcVerified] = counts[0];
+    pc[kPcCollisions] = counts[1];
+  }
+}
+
+hipError_t launch_phase_record(uint64_t* pc, const uint64_t* windows, const VerifyBufs& v,
+                               hipStream_t s) {
+  k_phase_record<<<1, 64, 0, s>>>(pc, windows, v.counts);
   return hipGetLastError();
 }
 

@@ -92,12 +92,14 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
     probe(slots, tags, mask, fp61(i, a.tx.tsalt[e >> kQPosBits]), i);
   };
   // whole wave: append the lanes' candidates; probe 64 once 64 are waiting
+  uint64_t ncand = 0;  // wave-uniform: windows that passed the filters
   const auto push = [&](bool cand, uint64_t i, uint32_t t) {
     const uint64_t bal = __ballot(cand);
     if (!bal) return;
     const uint32_t my = (uint32_t)__popcll(bal & ((1ull << lane) - 1));
     if (cand) q[qn + my] = ((uint64_t)t << kQPosBits) | i;
     qn += (uint32_t)__popcll(bal);
+    ncand += (uint64_t)__popcll(bal);
     if (qn >= 64) {
       wave_sync();
       const uint64_t e = q[lane];
@@ -295,6 +297,7 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
     wave_sync();
     if ((uint32_t)lane < qn) probe_entry(q[lane]);
   }
+  if (a.pc && lane == 0 && ncand) atomicAdd((unsigned long long*)(a.pc + kPcCand), (unsigned long long)ncand);
 }
 
 hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,

@@ -156,3 +156,41 @@ def test_level_copy_async():
     assert bt.lib().bt_level_copy_async(tree.h, tree.height, None, None, None, None) == bt.BT_E_INVAL
     tree.free()
     ctx.close()
+
+
+def test_phase_counters():
+    """Per-phase device counters of profiled builds: candidates never exceed
+    windows, verified keys never exceed keys, keys never exceed blocks; no
+    collisions with full fingerprints, some with 12-bit ones (every one then
+    resolved exactly: the tree still equals the oracle's); the windows of the
+    scanned phases equal the launch log's."""
+    torch = torch_cuda()
+    import paper_2512_23314_amd as bt
+    T = synth.cfg1_text(1 << 18)
+    want = oracle.build_tree(T, 2, 16).canonical
+    d = to_device(T)
+    ctx = bt.Context(0)
+    try:
+        for flags in (0, bt.BT_DBG_WEAK_HASH):
+            ctx.reset_stats()
+            ctx.profile(True)
+            tree = ctx.build(d, sigma=4, tau=2, leaf_len=16, debug_flags=flags)
+            ctx.profile(False)
+            assert tree.serialize() == want
+            ph = ctx.phases()
+            assert len(ph) >= 2 * (tree.height - 2)
+            for r in ph:
+                assert r["candidates"] <= r["windows"]
+                assert r["verified"] <= r["keys"] <= r["blocks"]
+                assert r["collisions"] <= r["verified"]
+            coll = sum(r["collisions"] for r in ph)
+            if flags:
+                assert coll > 0
+            else:
+                assert coll == 0
+            scans = [r for r in ctx.launches() if r[0] in ("probe_scan", "byte_scan")]
+            scanned = [r["windows"] for r in ph if r["keys"]]
+            assert sorted(int(x[2]) for x in scans) == sorted(scanned)
+            tree.free()
+    finally:
+        ctx.close()
