@@ -165,6 +165,29 @@ BT_API const char* bt_ctx_last_error(const bt_ctx* ctx);
 /* Release pooled scratch memory that is not in use. */
 BT_API int bt_ctx_trim(bt_ctx* ctx);
 
+/* Launch and sizing choices of a context's builds.  None of them changes a
+ * tree; they trade memory for speed, and their best values depend on the GPU
+ * and the shape of the work (paper_2512_23314_amd/autotune.py measures them
+ * and keeps the winners per GPU architecture and shape class).
+ *   table_load_log2       the key table has at least 2^this slots per key
+ *                         (1..3; default 1: load at most 1/2)
+ *   text_filter_bits_log2 batches: bits of a text's own key filter per block
+ *                         of the level, log2 (4..7; default 5: 32 bits)
+ *   span_chunks           batches: windows a workgroup takes at a time, in
+ *                         chunks of 1024 (a multiple of 16 up to 1024; 0, the
+ *                         default: chosen from the level's size)
+ *   filter2_max_log2      single texts: the largest second key filter, log2
+ *                         of its bits (16..28; default 24: 2 MiB, L2-sized)
+ * Errors: BT_E_INVAL (a value outside its range; the tuning is unchanged). */
+typedef struct {
+  uint32_t table_load_log2;
+  uint32_t text_filter_bits_log2;
+  uint32_t span_chunks;
+  uint32_t filter2_max_log2;
+} bt_tuning;
+BT_API int bt_ctx_set_tuning(bt_ctx* ctx, const bt_tuning* tuning);
+BT_API int bt_ctx_get_tuning(const bt_ctx* ctx, bt_tuning* tuning);
+
 /* Per-kernel timing, measured with HIP events on the context's stream around
  * each launch of the named kernel while enabled.  `bytes` accumulates the
  * kernel's algorithmic traffic (the bytes the method must move; defined with

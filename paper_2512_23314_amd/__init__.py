@@ -87,6 +87,15 @@ def torch_allocator(device, stream):
     return _torch_allocators[key]
 
 
+class bt_tuning(ctypes.Structure):
+    _fields_ = [("table_load_log2", ctypes.c_uint32), ("text_filter_bits_log2", ctypes.c_uint32),
+                ("span_chunks", ctypes.c_uint32), ("filter2_max_log2", ctypes.c_uint32)]
+
+
+DEFAULT_TUNING = {"table_load_log2": 1, "text_filter_bits_log2": 5, "span_chunks": 0,
+                  "filter2_max_log2": 24}
+
+
 class bt_params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_uint32), ("leaf_len", ctypes.c_uint32),
                 ("root_block_len", ctypes.c_uint64), ("s_hint", ctypes.c_uint64),
@@ -108,6 +117,8 @@ SIGNATURES = {
     "bt_ctx_reset_stats": (_i32, [_vp]),
     "bt_ctx_launch_count": (_i32, [_vp, _pu64]),
     "bt_ctx_phase_count": (_i32, [_vp, _pu64]),
+    "bt_ctx_set_tuning": (_i32, [_vp, ctypes.POINTER(bt_tuning)]),
+    "bt_ctx_get_tuning": (_i32, [_vp, ctypes.POINTER(bt_tuning)]),
     "bt_ctx_phase_record": (_i32, [_vp, _u64, _vp]),
     "bt_ctx_launch_record": (_i32, [_vp, _u64, ctypes.c_char_p, _u64, _pu64, _pd, _pd, _pd]),
     "bt_ctx_memory": (_i32, [_vp, _pu64, _pu64, _pu64]),
@@ -188,6 +199,8 @@ class Context:
         if rc != 0:
             raise BtError(rc, "bt_ctx_create failed")
         self.h = h
+        self._tcache = None    # tuning cache (autotune.py), loaded on the first build
+        self._applied = None   # the cached tuning last applied
 
     def close(self):
         if self.h:
@@ -232,6 +245,21 @@ class Context:
                                                    ctypes.byref(ms), ctypes.byref(by)))
             out.append((name.value.decode(), wl.value, un.value, ms.value, by.value))
         return out
+
+    def set_tuning(self, **kw):
+        """Set launch and sizing choices (bt_ctx_set_tuning); unnamed ones keep
+        their current values.  Returns the previous tuning as a dict."""
+        cur = bt_tuning()
+        self._check(lib().bt_ctx_get_tuning(self.h, ctypes.byref(cur)))
+        prev = {k: getattr(cur, k) for k, _ in bt_tuning._fields_}
+        new = bt_tuning(**dict(prev, **kw))
+        self._check(lib().bt_ctx_set_tuning(self.h, ctypes.byref(new)))
+        return prev
+
+    def tuning(self):
+        cur = bt_tuning()
+        self._check(lib().bt_ctx_get_tuning(self.h, ctypes.byref(cur)))
+        return {k: getattr(cur, k) for k, _ in bt_tuning._fields_}
 
     PHASE_FIELDS = ("step", "b", "phase", "blocks", "keys", "windows", "candidates", "verified",
                     "collisions")
@@ -301,19 +329,36 @@ class Context:
                          (BT_WITH_RANK_SELECT if rank_select else 0) | (BT_PRUNE if prune else 0) |
                          (BT_LEAN if lean else 0))
 
-    def build(self, text, sigma=256, tau=2, leaf_len=16, **kw):
-        """Build the tree of a uint8 CUDA tensor; returns a Tree."""
+    def _apply_tuning(self, ntexts, nbytes):
+        """Apply the autotuner's settings for this shape class, if the cache has them."""
+        from . import autotune
+        if self._tcache is None:
+            self._tcache = autotune.load_cache()
+            self._arch = autotune.arch_name(self.device) if self._tcache else ""
+        t = autotune.lookup(self._tcache, self._arch, autotune.shape_class(ntexts, nbytes))
+        if t and t != self._applied:
+            self.set_tuning(**t)
+            self._applied = t
+
+    def build(self, text, sigma=256, tau=2, leaf_len=16, tuned=True, **kw):
+        """Build the tree of a uint8 CUDA tensor; returns a Tree.  tuned: apply
+        the autotuner's settings for single texts of this size first (no tree
+        depends on them)."""
+        if tuned:
+            self._apply_tuning(1, text.numel())
         p = self.params(tau, leaf_len, **kw)
         h = ctypes.c_void_p()
         self._check(lib().bt_build_ex(self.h, _ptr(text), text.numel(), sigma, ctypes.byref(p),
                                       ctypes.byref(h)))
         return Tree(self, h)
 
-    def build_batch(self, concat, offsets, sigma=256, tau=2, leaf_len=16, **kw):
-        """Build one tree per text concat[offsets[i]:offsets[i+1]]."""
+    def build_batch(self, concat, offsets, sigma=256, tau=2, leaf_len=16, tuned=True, **kw):
+        """Build one tree per text concat[offsets[i]:offsets[i+1]] (tuned: as in build)."""
         p = self.params(tau, leaf_len, **kw)
         offs = np.ascontiguousarray(offsets, dtype=np.uint64)
         num = offs.size - 1
+        if tuned:
+            self._apply_tuning(num, int(offs[-1] - offs[0]) if num > 0 else 0)
         outs = (ctypes.c_void_p * max(num, 1))()
         self._check(lib().bt_build_batch(self.h, _ptr(concat), offs.ctypes.data_as(ctypes.c_void_p),
                                          num, sigma, ctypes.byref(p), outs))

@@ -267,6 +267,7 @@ struct bt_ctx {
   std::map<std::string, KStat> stats;
   std::vector<LaunchRec> launches;  // at most kLaunchLogMax, oldest first
   std::vector<PhaseRec> phases;     // at most kLaunchLogMax
+  bt_tuning tune{1, 5, 0, 24};      // see bt_ctx_set_tuning
   std::vector<PendingEv> pending;
   std::vector<hipEvent_t> ev_free;
   uint64_t* h_small = nullptr;  // pinned host words for count read-back
@@ -971,7 +972,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     for (uint32_t t = 0; t < T; ++t)
       if (h_tcount[t] && (h_n[t] % b) != 0) has_odd = true;
 
-    const uint64_t cap = std::max<uint64_t>(1024, pow2_at_least(2 * c));
+    const uint64_t cap = std::max<uint64_t>(1024, pow2_at_least(c << ctx->tune.table_load_log2));
     Buf<Slot> tab = alloc<Slot>(ctx, cap);
     Buf<uint64_t> tags = alloc<uint64_t>(ctx, cap / 8);
     Buf<uint64_t> kfp = alloc<uint64_t>(ctx, c), klen = alloc<uint64_t>(ctx, c),
@@ -991,7 +992,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     // LDS key filter of up to 2^19 bits, sized per phase from the key count
     Buf<uint32_t> filt = alloc<uint32_t>(ctx, (1ull << 19) / 32);
     // second key filter (global memory, at most 2^24 bits = 2 MiB: stays in L2)
-    Buf<uint32_t> filt2 = alloc<uint32_t>(ctx, (1ull << 24) / 32);
+    Buf<uint32_t> filt2 = alloc<uint32_t>(ctx, (1ull << ctx->tune.filter2_max_log2) / 32);
     int scan_mode = 1;
     uint32_t fbits = 12;
     VerifyBufs vb{vlist.p, vbest.p, vmis.p, rlist.p, rlb.p, vcnt.p};
@@ -1046,7 +1047,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       std::vector<uint32_t> h_wl(T), h_big;
       for (uint32_t t = 0; t < T; ++t) {
         uint32_t wl = 3;
-        while ((1ull << wl) < h_tcount[t]) ++wl;
+        // 2^(bits_log2 - 5) words of 32 bits per block
+        const uint32_t bl = ctx->tune.text_filter_bits_log2;
+        const uint64_t need = bl >= 5 ? h_tcount[t] << (bl - 5) : (h_tcount[t] + 1) >> (5 - bl);
+        while ((1ull << wl) < need) ++wl;
         h_wl[t] = wl;
         h_off[t] = tf_total;
         tf_total += 1ull << wl;
@@ -1097,7 +1101,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         scan_mode = 1;
         if (nkeys >= (1ull << 14)) {  // 64-bit words, about 32 bits per key
           f2words = 10;
-          while (f2words < 18 && (64ull << f2words) < 32 * nkeys) ++f2words;
+          while (f2words < ctx->tune.filter2_max_log2 - 6 && (64ull << f2words) < 32 * nkeys) ++f2words;
         }
       } else {
         scan_mode = 2;
@@ -1226,6 +1230,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
           // window bound, 16 to 256 chunks, a multiple of the 16 waves
           uint64_t span_chunks = (c * b) / kProbeTile / (4 * 512);
           span_chunks = std::min<uint64_t>(256, std::max<uint64_t>(16, span_chunks & ~15ull));
+          if (ctx->tune.span_chunks) span_chunks = ctx->tune.span_chunks;
           return text_local ? launch_probe_text(as, swoff, has_odd, c * b, span_chunks, span_ctr.p, s)
                             : launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
         }, a.Lmain);
@@ -1654,6 +1659,24 @@ int bt_ctx_reset_stats(bt_ctx* ctx) {
   ctx->stats.clear();
   ctx->launches.clear();
   ctx->phases.clear();
+  return BT_OK;
+}
+
+int bt_ctx_set_tuning(bt_ctx* ctx, const bt_tuning* t) {
+  if (!ctx || !t) return BT_E_INVAL;
+  if (t->table_load_log2 < 1 || t->table_load_log2 > 3 || t->text_filter_bits_log2 < 4 ||
+      t->text_filter_bits_log2 > 7 || t->span_chunks > 1024 || (t->span_chunks & 15) ||
+      t->filter2_max_log2 < 16 || t->filter2_max_log2 > 28) {
+    ctx->err = "bt_ctx_set_tuning: a value outside its documented range";
+    return BT_E_INVAL;
+  }
+  ctx->tune = *t;
+  return BT_OK;
+}
+
+int bt_ctx_get_tuning(const bt_ctx* ctx, bt_tuning* t) {
+  if (!ctx || !t) return BT_E_INVAL;
+  *t = ctx->tune;
   return BT_OK;
 }
 

@@ -194,3 +194,38 @@ def test_phase_counters():
             tree.free()
     finally:
         ctx.close()
+
+
+def test_tuning_never_changes_a_tree():
+    """Every setting of bt_tuning gives the same trees (single texts and a
+    batch); values outside their ranges are refused."""
+    torch = torch_cuda()
+    import paper_2512_23314_amd as bt
+    ctx = bt.Context(0)
+    try:
+        T = synth.markov_versions(300000, 20000, 15, 3e-3, 16, 11)
+        d = to_device(T)
+        # batch texts below 3 MiB (the expected trees come from the threaded
+        # oracle construction, which tests/test_oracle_par.py pins)
+        lens = synth.batch_lengths_of()
+        texts = [synth.batch_text(i) for i in range(60) if lens[i] < (3 << 20)][:40]
+        offs = np.zeros(len(texts) + 1, np.uint64)
+        offs[1:] = np.cumsum([t.size for t in texts])
+        db = to_device(np.concatenate(texts))
+        want_single = oracle.build_tree(T, 4, 16).canonical
+        want_batch = None
+        for tune in ({}, {"table_load_log2": 3}, {"text_filter_bits_log2": 4},
+                     {"text_filter_bits_log2": 7, "span_chunks": 16}, {"span_chunks": 1024},
+                     {"filter2_max_log2": 16}, {"filter2_max_log2": 28, "table_load_log2": 2}):
+            ctx.set_tuning(**dict(bt.DEFAULT_TUNING, **tune))
+            assert ctx.build(d, sigma=96, tau=4, leaf_len=16, tuned=False).serialize() == want_single
+            got = [tr.serialize() for tr in ctx.build_batch(db, offs, sigma=4, tau=4, leaf_len=16, tuned=False)]
+            if want_batch is None:
+                want_batch = [oracle.build_tree_par(t, 4, 16, levels=False).canonical for t in texts]
+            assert got == want_batch, tune
+        for bad in ({"table_load_log2": 0}, {"text_filter_bits_log2": 8}, {"span_chunks": 24},
+                    {"filter2_max_log2": 29}):
+            with pytest.raises(bt.BtError):
+                ctx.set_tuning(**bad)
+    finally:
+        ctx.close()
