@@ -366,6 +366,10 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
         plain = {"batched_mb_s": round(n / 1e6 / dt, 2), "plain_loop_mb_s": round(n / 1e6 / dtp, 2),
                  "speedup": round(dtp / dt, 2), "plain_loop_ms": round(dtp * 1e3, 1)}
         log("plain loop %.1f ms (%.0f MB/s)" % (dtp * 1e3, n / 1e6 / dtp))
+    lean = None
+    if not args.no_legs:
+        lean = batch_lean_leg(ctx, d, offs, n, sigma, tau, leaf, golden, insha)
+        log("lean batch: %s" % lean)
     ctx.close()
     del d
     torch.cuda.empty_cache()
@@ -377,6 +381,8 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
     out["parity"] = parity
     if plain is not None:
         out["batched_vs_plain"] = plain
+    if lean is not None:
+        out["lean_build"] = lean
     out["kernels"] = kt
     out["probe_scan_launches"] = {"columns": ["L", "windows", "us", "algorithmic_bytes"], "rows": pl}
     out["phase_counters_per_step"] = pt
@@ -761,6 +767,42 @@ def peak_build_bytes(ctx, d, sigma, tau, leaf, s_hint, lean):
     peak = ctx.memory()["peak"] - base
     tree.free()
     return peak
+
+
+def batch_lean_leg(ctx, d, offs, n, sigma, tau, leaf, golden, insha, steps=2):
+    """The batch built memory-lean (prefix fingerprints and 32-bit hashes kept
+    one in 16): parity of every tree, rate, and peak pool bytes of one build
+    against the dense build's."""
+    import torch
+
+    def build(lean):
+        return ctx.build_batch(d, offs, sigma=sigma, tau=tau, leaf_len=leaf, lean=lean)
+
+    def peak(lean):
+        torch.cuda.synchronize()
+        base = ctx.memory()["in_use"]
+        ctx.reset_peak()
+        trees = build(lean)
+        p = ctx.memory()["peak"] - base
+        for tr in trees:
+            tr.free()
+        return p
+    trees = build(True)
+    parity = check_batch(trees, golden, insha)
+    for tr in trees:
+        tr.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for tr in build(True):
+            tr.free()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    dense, lean = peak(False), peak(True)
+    return {"value": round(n / 1e6 / (ms / 1e3), 2), "unit": "MB/s", "ms_per_step": round(ms, 3),
+            "steps": steps, "parity_trees": parity["trees"], "peak_build_bytes": lean,
+            "peak_build_bytes_dense": dense, "peak_bytes_per_text_byte": round(lean / n, 3),
+            "peak_bytes_per_text_byte_dense": round(dense / n, 3)}
 
 
 def lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step, steps=3):

@@ -249,9 +249,12 @@ BT_API int bt_prefix_fingerprints(bt_ctx* ctx, const uint8_t* d_text, uint64_t n
  * before any fingerprint is formed, Section 4.1 step a4):
  *   d_H[0] = 0,  d_H[i+1] = (d_H[i] * x32 + d_text[i]) mod 2^32.
  * sampled = 0: d_P holds n+1 uint64 as in bt_prefix_fingerprints;
- * sampled = 1: d_P[q] = P[16 q] for 16 q <= n (n/16 + 1 uint64), the form a
- * memory-lean build keeps.  d_H: n+1 uint32.  All device, caller-owned.
- * x must be in [1, 2^61-1); any x32.  Errors: BT_E_INVAL. */
+ * sampled = 1: d_P[q] = P[16 q] for 16 q <= n (n/16 + 1 uint64), and d_H
+ * holds n+1 uint32;
+ * sampled = 2: both sampled, d_P as for 1 and d_H[q] = H[16 q] (n/16 + 1
+ * uint32), the form a memory-lean build keeps.  All device, caller-owned.
+ * x must be in [1, 2^61-1); any x32.  Errors: BT_E_INVAL (also for sampled
+ * outside 0..2). */
 BT_API int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
                           uint32_t x32, int sampled, uint64_t* d_P, uint32_t* d_H);
 

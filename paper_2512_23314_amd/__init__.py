@@ -299,13 +299,15 @@ class Context:
 
     def prefix_scan(self, text, x, x32, sampled=False):
         """Fingerprints (dense, or P[16 q] when sampled) and 32-bit hashes of one
-        pass; returns (P, H): uint64, and int32 holding the uint32 values."""
+        pass; returns (P, H): uint64, and int32 holding the uint32 values.
+        sampled=2 samples H too (H[16 q], the memory-lean build's form)."""
         torch = _torch()
         n = text.numel()
+        sampled = int(sampled)
         P = torch.empty(n // 16 + 1 if sampled else n + 1, dtype=torch.uint64, device=text.device)
-        H = torch.empty(n + 1, dtype=torch.int32, device=text.device)  # uint32 bits
-        self._check(lib().bt_prefix_scan(self.h, _ptr(text), n, x, x32, 1 if sampled else 0,
-                                         _ptr(P), _ptr(H)))
+        H = torch.empty(n // 16 + 1 if sampled == 2 else n + 1, dtype=torch.int32,
+                        device=text.device)  # uint32 bits
+        self._check(lib().bt_prefix_scan(self.h, _ptr(text), n, x, x32, sampled, _ptr(P), _ptr(H)))
         return P, H
 
     def prefix_scan_noalloc(self, text, x, x32, sampled=False, P=None, H=None):
@@ -313,11 +315,13 @@ class Context:
         nothing; P and H may be given to reuse caller buffers)."""
         torch = _torch()
         n = text.numel()
+        sampled = int(sampled)
         if P is None:
             P = torch.empty(n // 16 + 1 if sampled else n + 1, dtype=torch.uint64, device=text.device)
         if H is None:
-            H = torch.empty(n + 1, dtype=torch.int32, device=text.device)  # uint32 bits
-        self._check(lib().bt_prefix_scan_noalloc(self.h, _ptr(text), n, x, x32, 1 if sampled else 0,
+            H = torch.empty(n // 16 + 1 if sampled == 2 else n + 1, dtype=torch.int32,
+                            device=text.device)  # uint32 bits
+        self._check(lib().bt_prefix_scan_noalloc(self.h, _ptr(text), n, x, x32, sampled,
                                                  _ptr(P), _ptr(H)))
         return P, H
 

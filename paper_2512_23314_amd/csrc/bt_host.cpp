@@ -402,6 +402,14 @@ uint32_t host_pow32(uint32_t x, uint64_t e) {
   return r;
 }
 
+// x^-1 mod 2^32 for odd x: Newton's iteration y <- y (2 - x y) doubles the
+// number of correct low bits, and y = x is right to 3 bits (x x = 1 mod 8).
+uint32_t host_inv32(uint32_t x) {
+  uint32_t y = x;
+  for (int k = 0; k < 4; ++k) y *= 2u - x * y;
+  return y;
+}
+
 // Tables of the prefix scan: g61[j-1][b] = b x^j (j = 1..7), t[k] = x^(64 k),
 // xt[k] = x^(tile k), c[c] = x^(16 c), for both bases.
 void fill_tab(PfTab* tb, uint64_t x, uint32_t x32) {
@@ -672,18 +680,19 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   // build keeps one fingerprint in 16 (0.5 instead of 8 bytes per text byte)
   // and forms the others where a fingerprint is needed: keys, queued
   // candidates and retries.  Only the queued scan takes candidates that way.
+  // It samples the 32-bit hashes too (0.25 instead of 4 bytes per text byte):
+  // the scans roll them along consecutive windows.
   const bool lean = (prm.flags & BT_LEAN) && T <= (1u << 24) && offs[T] < (1ull << 40) &&
                     !(prm.debug_flags & BT_DBG_NO_QUEUE);
   const uint32_t x32 = base32_from_seed(prm.hash_seed);
   Buf<uint64_t> d_P = alloc<uint64_t>(ctx, lean ? N / 16 + 1 : N + 1);
-  Buf<uint32_t> d_H = alloc<uint32_t>(ctx, N + 1);
+  Buf<uint32_t> d_H = alloc<uint32_t>(ctx, lean ? N / 16 + 1 : N + 1);
   Buf<PfTab> d_tab = alloc<PfTab>(ctx, 1);
   fill_tab(ctx->h_tab, x, x32);
   HIPCHK(ctx, hipMemcpyAsync(d_tab.p, ctx->h_tab, sizeof(PfTab), hipMemcpyHostToDevice, s));
   Buf<uint64_t> d_status = alloc<uint64_t>(ctx, prefix_status_words(N));
-  timed(ctx, "prefix_fp", (double)N + 8.0 * (double)(lean ? N / 16 + 1 : N + 1) + 4.0 * (double)(N + 1),
-        (double)N, nullptr, 0,
-        [&] { return launch_prefix(d_base + o0, N, d_P.p, lean, d_H.p, d_tab.p, d_status.p, s); });
+  timed(ctx, "prefix_fp", (double)N + 12.0 * (double)(lean ? N / 16 + 1 : N + 1), (double)N, nullptr, 0,
+        [&] { return launch_prefix(d_base + o0, N, d_P.p, lean, d_H.p, d_tab.p, d_status.p, s, lean); });
   // P[i] belongs to text position i (never read below o0); null when sampled
   const uint64_t* P = lean ? nullptr : d_P.p - o0;
 
@@ -709,7 +718,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         ctx->err = "rank/select support needs texts shorter than 2^32 bytes";
         return BT_E_INVAL;
       }
-  const uint32_t* H32 = d_H.p - o0;
+  // H[i] belongs to text position i; null when sampled (Hs = d_H)
+  const uint32_t* H32 = lean ? nullptr : d_H.p - o0;
 
   auto store = std::make_shared<Storage>();
   store->pool = ctx->pool;
@@ -1004,6 +1014,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.pbase = o0;
     a.pend = offs[T];
     a.P32 = H32;
+    a.Hs = lean ? d_H.p : nullptr;
+    a.x32inv = host_inv32(x32);
     a.tx = tx;
     a.lv = lv;
     a.k = KeysDev{kfp.p, klen.p, kslot.p, klm.p};
@@ -1144,6 +1156,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       a.bfilt = byte_scan ? filt.p : nullptr;
       a.bfilt_bits = bbits;
       a.x32L = host_pow32(x32, a.Lmain);
+      a.x32Lm1 = host_pow32(x32, a.Lmain ? a.Lmain - 1 : 0);
       {
         FillList f;
         f.add(tab.p, 4 * cap, ~0u);  // empty slots: fp = best = ~0
@@ -1754,8 +1767,8 @@ int bt_prefix_fingerprints(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint6
 int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x, uint32_t x32,
                    int sampled, uint64_t* d_P, uint32_t* d_H) {
   if (!ctx) return BT_E_INVAL;
-  if (x == 0 || x >= kP61Host || !d_P || !d_H || (!d_text && n)) {
-    ctx->err = "bt_prefix_scan: need 1 <= x < 2^61-1 and valid pointers";
+  if (x == 0 || x >= kP61Host || !d_P || !d_H || (!d_text && n) || sampled < 0 || sampled > 2) {
+    ctx->err = "bt_prefix_scan: need 1 <= x < 2^61-1, sampled 0, 1 or 2 and valid pointers";
     return BT_E_INVAL;
   }
   return guarded(ctx, [&] {
@@ -1766,8 +1779,10 @@ int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x, u
                                ctx->stream));
     Buf<uint64_t> d_status = alloc<uint64_t>(ctx, prefix_status_words(n));
     const double pw = sampled ? 8.0 * (double)(n / 16 + 1) : 8.0 * (double)(n + 1);
-    timed(ctx, "prefix_fp", (double)n + pw + 4.0 * (double)(n + 1), (double)n, nullptr, 0, [&] {
-      return launch_prefix(d_text, n, d_P, sampled != 0, d_H, d_tab.p, d_status.p, ctx->stream);
+    const double hw = sampled == 2 ? 4.0 * (double)(n / 16 + 1) : 4.0 * (double)(n + 1);
+    timed(ctx, "prefix_fp", (double)n + pw + hw, (double)n, nullptr, 0, [&] {
+      return launch_prefix(d_text, n, d_P, sampled != 0, d_H, d_tab.p, d_status.p, ctx->stream,
+                           sampled == 2);
     });
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     collect_events(ctx);
@@ -1778,8 +1793,8 @@ int bt_prefix_scan(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x, u
 int bt_prefix_scan_noalloc(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint64_t x,
                            uint32_t x32, int sampled, uint64_t* d_P, uint32_t* d_H) {
   if (!ctx) return BT_E_INVAL;
-  if (x == 0 || x >= kP61Host || !d_P || !d_H || (!d_text && n)) {
-    ctx->err = "bt_prefix_scan_noalloc: need 1 <= x < 2^61-1 and valid pointers";
+  if (x == 0 || x >= kP61Host || !d_P || !d_H || (!d_text && n) || sampled < 0 || sampled > 2) {
+    ctx->err = "bt_prefix_scan_noalloc: need 1 <= x < 2^61-1, sampled 0, 1 or 2 and valid pointers";
     return BT_E_INVAL;
   }
   if (n > kNoAllocMaxText) {
@@ -1798,7 +1813,8 @@ int bt_prefix_scan_noalloc(bt_ctx* ctx, const uint8_t* d_text, uint64_t n, uint6
     fill_tab(ctx->h_tab, x, x32);
     e = hipMemcpyAsync(tab, ctx->h_tab, sizeof(PfTab), hipMemcpyHostToDevice, ctx->stream);
   }
-  if (e == hipSuccess) e = launch_prefix(d_text, n, d_P, sampled != 0, d_H, tab, status, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_prefix(d_text, n, d_P, sampled != 0, d_H, tab, status, ctx->stream, sampled == 2);
   // synchronous, like bt_prefix_scan: the pinned staging of the tables and the
   // scratch are free again when the call returns
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

@@ -160,6 +160,45 @@ __device__ __forceinline__ uint64_t prefix_at(const uint64_t* __restrict__ Ps,
   return v;
 }
 
+// The 15 bytes T[j0 .. j0 + 15) as two words (lo: bytes 0..7, hi: bytes 8..14
+// and one more), from three aligned 8-byte loads issued together when the words
+// lie inside [.., end); else byte by byte (bytes at or past end read as 0).
+__device__ __forceinline__ void bytes16_at(const uint8_t* __restrict__ T, uint64_t end, uint64_t j0,
+                                           uint64_t& lo, uint64_t& hi) {
+  if (j0 + 24 <= end) {
+    const uintptr_t ad = reinterpret_cast<uintptr_t>(T + j0);
+    const uint64_t* wp = reinterpret_cast<const uint64_t*>(ad & ~(uintptr_t)7);
+    const uint32_t sh = (uint32_t)(ad & 7) * 8;
+    const uint64_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
+    lo = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;
+    hi = sh ? (w1 >> sh) | (w2 << (64 - sh)) : w1;
+    return;
+  }
+  lo = hi = 0;
+  for (uint32_t k = 0; k < 16 && j0 + k < end; ++k)
+    (k < 8 ? lo : hi) |= (uint64_t)T[j0 + k] << (8 * (k & 7));
+}
+
+// H[i] from 32-bit prefix hashes sampled every 16 positions (Hs[q] = H[base +
+// 16 q], H[j+1] = H[j] x32 + T[j] mod 2^32): the sample at or below i, then
+// Horner's rule over the at most 15 bytes between (i < end).
+__device__ __forceinline__ uint32_t h32_at(const uint32_t* __restrict__ Hs,
+                                           const uint8_t* __restrict__ T, uint64_t base,
+                                           uint64_t end, uint32_t x32, uint64_t i) {
+  const uint64_t r = i - base;
+  const uint32_t m = (uint32_t)(r & 15);
+  uint32_t v = Hs[r >> 4];
+  if (!m) return v;
+  uint64_t lo, hi;
+  bytes16_at(T, end, i - m, lo, hi);
+#pragma unroll
+  for (uint32_t k = 0; k < 15; ++k) {
+    if (k >= m) break;
+    v = v * x32 + (uint32_t)(((k < 8 ? lo : hi) >> (8 * (k & 7))) & 0xFF);
+  }
+  return v;
+}
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -36,9 +36,10 @@ inline uint64_t prefix_status_words(uint64_t n) {
 // (n + 1 words) or, when sampled, as Ps[q] = P[16 q] for 16 q <= n (n / 16 + 1
 // words); and, when H is not null, H[0] = 0, H[i+1] = H[i] x32 + T[i] (mod
 // 2^32), the pre-filter hashes of the probe scan (n + 1 words), from the same
-// pass over the text.  status: prefix_status_words(n) words.
+// pass over the text; hsampled (with sampled): H holds H[16 q] for 16 q <= n
+// instead (n / 16 + 1 words).  status: prefix_status_words(n) words.
 hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled, uint32_t* H,
-                         const PfTab* tab, uint64_t* status, hipStream_t s);
+                         const PfTab* tab, uint64_t* status, hipStream_t s, bool hsampled = false);
 
 // ---- level data (device arrays; positions are offsets into the text base) ----
 struct TextsDev {
@@ -119,8 +120,11 @@ struct PhaseArgs {
   // 32-bit pre-filter hash: when pre32 is set the filter holds bits of the
   // keys' 32-bit window hashes, and the scan computes a window's fingerprint
   // only where its 32-bit hash passes the filter.
-  const uint32_t* P32;  // prefix hashes mod 2^32 (same indexing as P)
+  const uint32_t* P32;  // prefix hashes mod 2^32 (same indexing as P), or null when sampled:
+  const uint32_t* Hs;   // Hs[q] = H[pbase + 16 q] (memory-lean builds)
   uint32_t x32L;        // x32^Lmain mod 2^32
+  uint32_t x32Lm1;      // x32^(Lmain - 1): the weight of the byte that leaves a rolled window
+  uint32_t x32inv;      // x32^-1 mod 2^32 (x32 is odd)
   uint32_t x32;         // the 32-bit hash's base
   uint32_t pre32;
   // With pre32: a second, blocked bit filter of the keys' 32-bit hashes in

@@ -19,6 +19,7 @@
 // present), so "leftmost on this level" and "leftmost in T" coincide.
 #include "common.hpp"
 #include "internal.hpp"
+#include "lean.hpp"
 #include "probe.hpp"
 #include "window.hpp"
 
@@ -118,13 +119,13 @@ __global__ void k_keys(PhaseArgs a) {
       atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
       if (a.tf_words) {
         // text-local filter: this text's keys only
-        const uint32_t h = a.P32[st + L] - a.P32[st] * a.x32L + (uint32_t)a.tx.tsalt[t];
+        const uint32_t h = win32_any(a, st, L, a.x32L) + (uint32_t)a.tx.tsalt[t];
         atomicOr(a.tf_words + a.tf_off[t] + tfilter_word(h, a.tf_wl[t]), tfilter_mask(h));
       }
       if (a.filt_bits) {
         uint64_t f1, f2;
         if (a.pre32) {
-          const uint32_t h = a.P32[st + L] - a.P32[st] * a.x32L + (uint32_t)a.tx.tsalt[t];
+          const uint32_t h = win32_any(a, st, L, a.x32L) + (uint32_t)a.tx.tsalt[t];
           f1 = filter_bit32(h, a.filt_bits);
           f2 = filter_bit32b(h, a.filt_bits);
           if (a.filt2_words)
@@ -151,7 +152,7 @@ __global__ void k_keys(PhaseArgs a) {
         if (e & 1) x32p *= base;
         base *= base;
       }
-      const uint32_t h = a.P32[st + L] - a.P32[st] * x32p + (uint32_t)a.tx.tsalt[t];
+      const uint32_t h = win32_any(a, st, L, x32p) + (uint32_t)a.tx.tsalt[t];
       a.odd.h32[t] = (uint64_t)h | ((uint64_t)x32p << 32);
       if (a.bfilt_bits) set_prefix_bit(a, st);
     }
@@ -412,6 +413,7 @@ hipError_t launch_block_segments(const PhaseArgs& a, const uint64_t* wcs, const 
 constexpr int kScanK = 16;                      // windows per lane per chunk
 constexpr uint64_t kScanChunk = 64ull * kScanK;  // windows per wave per chunk
 static_assert(kScanChunk == kProbeTile, "the host counts algorithmic bytes per tile of kProbeTile windows");
+static_assert(kLeanK == kScanK, "lean scans take the same chunks");
 
 // Windows are numbered run after run (woff = exclusive prefix of per-run window
 // counts).  Each wave takes chunks of 64*kScanK consecutive window numbers;
@@ -451,7 +453,7 @@ __device__ __forceinline__ bool filter_has(const uint32_t* s_filt, uint64_t b1, 
 // Two 1024-thread workgroups per CU need 8 waves per SIMD: the register budget
 // (SGPRs included) is held to that.
 template <int MODE, bool ODD, bool SALT, bool PRE, bool LEAN>
-__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu((LEAN && ODD) ? 4 : 8)))
 void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   constexpr bool FILTER = MODE != 0;
   static_assert(!PRE || MODE == 1, "the 32-bit hash feeds the queued filter only");
@@ -533,6 +535,27 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   };
 
   for (uint64_t ch = gw; ch * kScanChunk < W; ch += nw) {
+    if constexpr (LEAN) {
+      // sampled hashes: consecutive windows per lane, rolled (lean.hpp)
+      const auto test8 = [&](const uint32_t* hv, bool* ok) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ok[k] = pass32(hv[k]);
+        if (f2words) {
+          uint64_t wv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? filt2[filter2_word(hv[k], f2words)] : ~0ull;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint64_t m = filter2_mask(hv[k]);
+            ok[k] = ok[k] && (wv[k] & m) == m;
+          }
+        }
+      };
+      const auto test1 = [&](uint32_t h) { return pass32(h) && (!f2words || pass2(h)); };
+      lean_chunk<ODD, ODD || SALT, SALT>(a, woff, R, W, ch * kScanChunk + (uint64_t)lane * kLeanK,
+                                         [](uint32_t) {}, test8, test1, push);
+      continue;
+    }
     const uint64_t w0 = ch * kScanChunk + lane;
     uint64_t lo = 0, hi = R;
     while (hi - lo > 1) {

@@ -24,7 +24,7 @@
 //      thread runs 16 Horner steps from one of them (one multiply-add per
 //      output), and each wave stages its outputs in LDS so that its stores are
 //      lane-contiguous.  The sampled form stores every 16th value only:
-//      P[16 q] for 16 q <= n.
+//      P[16 q] for 16 q <= n (and, with sampled hashes, H[16 q] likewise).
 // Tile order comes from the counter, so a tile waits only on tiles that
 // running workgroups hold.  The text is read once for both results.
 #include "common.hpp"
@@ -110,7 +110,7 @@ __device__ typename A::V look_back(uint64_t* status, uint64_t tile, typename A::
 }
 
 // Two waves per SIMD: the register budget of three spilled, and ran slower.
-template <bool SAMPLED, bool WH>
+template <bool SAMPLED, bool WH, bool HS>
 __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_prefix(
     const uint8_t* __restrict__ T, uint64_t n, uint64_t* __restrict__ P, uint32_t* __restrict__ H,
     const PfTab* __restrict__ tb, uint64_t* __restrict__ st61, uint64_t* __restrict__ st32,
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
   // and 17 words keep the lanes on different banks)
   constexpr bool DENSE = !SAMPLED;
   __shared__ uint64_t s_st61[DENSE ? kPfTile / 16 : 1];
-  __shared__ uint32_t s_st32[WH ? kPfTile / 16 : 1];
-  __shared__ uint64_t s_out[(DENSE || WH) ? (kPfThreads / 64) * 64 * 9 : 1];
+  __shared__ uint32_t s_st32[(WH && !HS) ? kPfTile / 16 : 1];
+  __shared__ uint64_t s_out[(DENSE || (WH && !HS)) ? (kPfThreads / 64) * 64 * 9 : 1];
 
   const int t0 = threadIdx.x;
   for (int k = t0; k < 7 * 256; k += kPfThreads) s_g61[k] = (&tb->g61[0][0])[k];
@@ -302,12 +302,19 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
         for (int c = 0; c < 4; ++c) s_st61[4 * t + c] = v[c];
       }
-      if (WH) {
+      if (HS) {
+        if (pos <= n) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (pos + 16 * c <= n) H[(pos >> 4) + c] = u[c];
+          if (pos + kPfBytes == n) H[n >> 4] = C32 * tb->t32[1] + h32;
+        }
+      } else if (WH) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) s_st32[4 * t + c] = u[c];
       }
     }
-    if (DENSE || WH) {
+    if (DENSE || (WH && !HS)) {
       __syncthreads();
       const bool tfull = tb0 + kPfTile < n;  // no output of the tile lies past n
       uint64_t* so = s_out + wv * 64 * 9;
@@ -341,7 +348,7 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
           }
           if (q + 16 == n) P[n] = val;
         }
-        if (WH) {
+        if (WH && !HS) {
           uint32_t val = s_st32[kPfThreads * r + t];
 #pragma unroll
           for (int k = 0; k < 16; ++k) {
@@ -376,7 +383,7 @@ __global__ void k_zero(V* p, uint64_t n) {
 }  // namespace
 
 hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled, uint32_t* H,
-                         const PfTab* tab, uint64_t* status, hipStream_t s) {
+                         const PfTab* tab, uint64_t* status, hipStream_t s, bool hsampled) {
   const uint64_t tiles = (n + kPfTile - 1) / kPfTile;
   if (tiles == 0) {  // P[0] = 0 (and H[0] = 0) only
     k_zero<uint64_t><<<1, 64, 0, s>>>(P, 1);
@@ -390,12 +397,16 @@ hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled
   uint64_t* st32 = status + tiles + 1;
   uint32_t* ctr = reinterpret_cast<uint32_t*>(status + 2 * (tiles + 1));
   const unsigned grid = (unsigned)(tiles < kPfGrid ? tiles : kPfGrid);
-  if (sampled) {
-    if (H) k_prefix<true, true><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
-    else k_prefix<true, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+  if (sampled && hsampled) {
+    if (!H) return hipErrorInvalidValue;
+    k_prefix<true, true, true><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+  } else if (sampled) {
+    if (H) k_prefix<true, true, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    else k_prefix<true, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
   } else {
-    if (H) k_prefix<false, true><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
-    else k_prefix<false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    if (hsampled) return hipErrorInvalidValue;
+    if (H) k_prefix<false, true, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    else k_prefix<false, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
   }
   return hipGetLastError();
 }

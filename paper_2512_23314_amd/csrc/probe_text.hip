@@ -23,6 +23,7 @@
 // probe the shared table 64 at a time with their 61-bit fingerprints.
 #include "common.hpp"
 #include "internal.hpp"
+#include "lean.hpp"
 #include "probe.hpp"
 #include "window.hpp"
 
@@ -39,20 +40,10 @@ constexpr int kTlK = 16;  // windows per lane per chunk
 constexpr int kTlQueue = 127;
 constexpr uint32_t kNoText = 0xFFFFFFFFu;
 static_assert(64ull * kTlK == kProbeTile, "a chunk is one probe tile");
-
-// Segment holding window number w: the last r with woff[r] <= w.
-__device__ __forceinline__ uint64_t segment_of(const uint64_t* __restrict__ woff, uint64_t R,
-                                               uint64_t w) {
-  uint64_t lo = 0, hi = R;
-  while (hi - lo > 1) {
-    const uint64_t mid = (lo + hi) >> 1;
-    if (woff[mid] <= w) lo = mid; else hi = mid;
-  }
-  return lo;
-}
+static_assert(kLeanK == kTlK, "lean chunks are probe tiles too");
 
 template <bool ODD, bool LEAN>
-__global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(LEAN ? 4 : 8)))
 void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_chunks,
                   uint64_t* __restrict__ span_ctr) {
   extern __shared__ uint64_t s_lds[];
@@ -113,6 +104,50 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
     }
   };
 
+  // Memory-lean builds: lane l takes the kLeanK consecutive windows from
+  // chunk + kLeanK l and rolls their hashes (lean.hpp).
+  const auto scan_chunk_lean = [&](uint64_t ch, auto lds_tag, uint32_t st, uint32_t lwl, bool big) {
+    constexpr bool LDS = decltype(lds_tag)::value;
+    uint64_t toff = LDS ? tfo[st] : 0;
+    uint32_t twl = LDS ? tfl[st] : 0;
+    const auto on_text = [&](uint32_t t) {
+      if (!LDS) {
+        toff = tfo[t];
+        twl = tfl[t];
+      }
+    };
+    const auto pass_word = [&](uint32_t h) -> uint32_t {
+      return LDS ? s_filt[tfilter_word(h, lwl)] : tfw[toff + tfilter_word(h, twl)];
+    };
+    const auto test8 = [&](const uint32_t* hv, bool* ok) {
+      uint32_t wv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) wv[k] = pass_word(hv[k]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t m = tfilter_mask(hv[k]);
+        ok[k] = (wv[k] & m) == m;
+      }
+      if (LDS && big) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? tfw[toff + tfilter_word(hv[k], twl)] : 0u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t m = tfilter_mask(hv[k]);
+          ok[k] = ok[k] && (wv[k] & m) == m;
+        }
+      }
+    };
+    const auto test1 = [&](uint32_t h) {
+      const uint32_t m = tfilter_mask(h);
+      bool c = (pass_word(h) & m) == m;
+      if (LDS && big && c) c = (tfw[toff + tfilter_word(h, twl)] & m) == m;
+      return c;
+    };
+    lean_chunk<ODD, true, true>(a, woff, R, W, ch * kProbeTile + (uint64_t)lane * kLeanK, on_text,
+                                test8, test1, push);
+  };
+
   // One chunk of kProbeTile window numbers.  LDS (a compile-time tag): every
   // window of the chunk belongs to text st, whose filter (2^lwl words, lwl =
   // its word count or the folded one) is in LDS; when folded (big), a window
@@ -120,6 +155,10 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
   // reads its own text's filter in global memory.
   const auto scan_chunk = [&](uint64_t ch, auto lds_tag, uint32_t st, uint32_t lwl, bool big) {
     constexpr bool LDS = decltype(lds_tag)::value;
+    if constexpr (LEAN) {
+      scan_chunk_lean(ch, lds_tag, st, lwl, big);
+      return;
+    }
     const uint64_t w0 = ch * kProbeTile + lane;
     uint64_t r = segment_of(woff, R, w0);
     uint64_t wo = woff[r], wn = woff[r + 1], rs = rs_[r], re = re_[r];

@@ -62,8 +62,9 @@ def test_prefix_fingerprints_misaligned_output(ctx):
 
 
 # both prefix arrays in one pass (the builds' form): dense or sampled
-# fingerprints, and the 32-bit hashes against their recurrence
-@pytest.mark.parametrize("sampled", [False, True], ids=["dense", "sampled"])
+# fingerprints, and the 32-bit hashes against their recurrence (sampled too
+# in the memory-lean form, sampled=2)
+@pytest.mark.parametrize("sampled", [0, 1, 2], ids=["dense", "sampled", "both_sampled"])
 @pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 63, 64, 65, 4095, 8191, 8192, 16385, 32767, 32768,
                                32769, 65536 * 3 + 7, (5 << 20) + 1])
 def test_prefix_scan(ctx, n, sampled):
@@ -74,18 +75,20 @@ def test_prefix_scan(ctx, n, sampled):
     P, H = ctx.prefix_scan(to_device(T), x, x32, sampled=sampled)
     want = oracle.prefix_fp(T, x)
     assert np.array_equal(P.cpu().numpy(), want[::16] if sampled else want)
-    assert np.array_equal(H.cpu().numpy().view(np.uint32), hashref.h32(T, x32))
+    h = hashref.h32(T, x32)
+    assert np.array_equal(H.cpu().numpy().view(np.uint32), h[::16] if sampled == 2 else h)
 
 
 def test_prefix_scan_unaligned_views(ctx):
     T = np.random.default_rng(8).integers(0, 256, 70001).astype(np.uint8)
     d = to_device(T)
     for off in (1, 3, 8, 13):
-        for sampled in (False, True):
+        for sampled in (0, 1, 2):
             P, H = ctx.prefix_scan(d[off:], 1234567 + off, 0x9E3779B1, sampled=sampled)
             want = oracle.prefix_fp(T[off:], 1234567 + off)
             assert np.array_equal(P.cpu().numpy(), want[::16] if sampled else want)
-            assert np.array_equal(H.cpu().numpy().view(np.uint32), hashref.h32(T[off:], 0x9E3779B1))
+            h = hashref.h32(T[off:], 0x9E3779B1)
+            assert np.array_equal(H.cpu().numpy().view(np.uint32), h[::16] if sampled == 2 else h)
 
 
 # ---- whole builds against the oracle

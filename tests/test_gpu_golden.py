@@ -77,6 +77,8 @@ def test_dna2g(name):
     e = _entry(name)
     T = _dna2g()
     _check_single(T, e, 4)
+    if name == "dna2g_t4_l16":
+        _check_single(T, e, 4, lean=True)
 
 
 _DNA = {}
