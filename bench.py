@@ -503,6 +503,8 @@ def bench_single(args, workload, steps, warmup, sublegs=False):
             log("lean build: %s" % out["lean_build"])
         out["sort_phase_build"] = sort_leg(ctx, d, n, sigma, tau, leaf, s_hint, ms)
         log("sort-phase build: %s" % out["sort_phase_build"])
+        out["rank_select_build"] = rank_leg(ctx, d, T, sigma, tau, leaf, s_hint, ms, golden)
+        log("rank/select build: %s" % out["rank_select_build"])
     ctx.close()
     del d
     torch.cuda.empty_cache()
@@ -821,6 +823,37 @@ def lean_leg(ctx, d, n, sigma, tau, leaf, s_hint, step, steps=3):
             "steps": steps, "peak_build_bytes": lean, "peak_build_bytes_dense": dense,
             "peak_bytes_per_text_byte": round(lean / n, 3),
             "peak_bytes_per_text_byte_dense": round(dense / n, 3)}
+
+
+def rank_leg(ctx, d, T, sigma, tau, leaf, s_hint, plain_ms, golden, steps=3):
+    """Builds with the rank/select support (bt_build's configuration): the same
+    tree (checked against the expected one), rate, the support's device bytes
+    per text byte, and what 32-bit counters for every block and pointer would
+    take on the same tree."""
+    import numpy as np
+    import torch
+    n = int(T.size)
+
+    def one():
+        return ctx.build(d, sigma=sigma, tau=tau, leaf_len=leaf, s_hint=s_hint, rank_select=True)
+    tree = one()
+    parity = check_single(tree, golden, T)
+    counts = [tree.level_info(l) for l in range(1, tree.height + 1)]
+    rb = tree.rank_bytes()
+    tree.free()
+    S = int(np.count_nonzero(np.bincount(T, minlength=256)))  # the support's alphabet
+    dense = sum(4 * S * (c + u) + 8 * c for _, c, u in counts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one().free()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return {"value": round(n / 1e6 / (ms / 1e3), 2), "unit": "MB/s", "ms_per_step": round(ms, 3),
+            "steps": steps, "support_ms": round(ms - plain_ms, 3), "symbols": S,
+            "support_bytes": rb, "support_bytes_per_text_byte": round(rb / n, 3),
+            "support_bytes_32bit_form": dense,
+            "support_bytes_per_text_byte_32bit_form": round(dense / n, 3), "parity": parity}
 
 
 def sort_leg(ctx, d, n, sigma, tau, leaf, s_hint, hash_ms, steps=2):

@@ -359,8 +359,16 @@ BT_API int bt_rank(bt_ctx* ctx, const bt_tree* tree, const uint8_t* d_c, const u
 BT_API int bt_select(bt_ctx* ctx, const bt_tree* tree, const uint8_t* d_c, const uint64_t* d_k,
               uint64_t m, uint64_t* d_out);
 
-/* Device bytes held by a tree. */
+/* Device bytes held by a tree (for a tree of a batch: the batch's storage
+ * divided by the number of trees). */
 BT_API int bt_tree_device_bytes(const bt_tree* tree, uint64_t* bytes);
+/* Of those, the bytes of the rank/select support (0 without
+ * BT_WITH_RANK_SELECT; same division for a batch).  The support keeps, per
+ * level and symbol, each block's count relative to its parent block in 8 or 16
+ * bits (absolute 32-bit counts on a tree's first level and where relative ones
+ * would need 32 bits), pointer counts in 8, 16 or 32 bits, the index of every
+ * marked block and the block starts. */
+BT_API int bt_tree_rank_bytes(const bt_tree* tree, uint64_t* bytes);
 BT_API void bt_tree_free(bt_tree* tree);
 BT_API const char* bt_strerror(int status);
 

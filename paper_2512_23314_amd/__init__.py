@@ -140,6 +140,7 @@ SIGNATURES = {
     "bt_rank": (_i32, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "bt_select": (_i32, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "bt_tree_device_bytes": (_i32, [_vp, _pu64]),
+    "bt_tree_rank_bytes": (_i32, [_vp, _pu64]),
     "bt_tree_free": (None, [_vp]),
     "bt_strerror": (ctypes.c_char_p, [_i32]),
 }
@@ -431,6 +432,12 @@ class Tree:
     def device_bytes(self):
         b = ctypes.c_uint64()
         lib().bt_tree_device_bytes(self.h, ctypes.byref(b))
+        return b.value
+
+    def rank_bytes(self):
+        """Device bytes of the rank/select support (0 when built without it)."""
+        b = ctypes.c_uint64()
+        lib().bt_tree_rank_bytes(self.h, ctypes.byref(b))
         return b.value
 
     # ---- queries (device tensors in, device tensors out)

@@ -302,9 +302,13 @@ struct TreeLevel {
   const uint64_t* wrank = nullptr;  // marks before each word
   const uint64_t* pb = nullptr;     // u
   const uint64_t* po = nullptr;     // u
-  const uint32_t* cnt = nullptr;    // c * S (rank/select support)
-  const uint32_t* pcnt = nullptr;   // u * S
+  // rank/select support (the forms are described in rank.hip)
+  const uint32_t* acnt = nullptr;   // c * S absolute counts, or null:
+  const uint8_t* qc = nullptr;      // c * S relative counts, qw bytes each
+  const uint8_t* pc = nullptr;      // u * S pointer counts, pw bytes each
+  const uint32_t* msel = nullptr;   // index of each marked block
   const uint64_t* st = nullptr;     // c
+  uint32_t qw = 0, pw = 0;
 };
 
 struct bt_tree {
@@ -317,6 +321,7 @@ struct bt_tree {
   uint64_t leaf_bytes = 0;
   QLevel* d_levels = nullptr;  // device copy of the level table for queries
   uint64_t dev_bytes = 0;
+  uint64_t rank_bytes = 0;  // of dev_bytes, the rank/select support's
   // rank/select support
   bool has_rank = false;
   const int16_t* sym = nullptr;   // 256 entries
@@ -609,13 +614,21 @@ struct TextLevelRec {
 };
 
 struct LevelBufs {
-  uint64_t* words;
-  uint64_t* wrank;
-  uint64_t* pb;
-  uint64_t* po;
-  uint32_t* cnt;
-  uint32_t* pcnt;
-  uint64_t* st;
+  uint64_t* words = nullptr;
+  uint64_t* wrank = nullptr;
+  uint64_t* pb = nullptr;
+  uint64_t* po = nullptr;
+  // rank/select support of the step: absolute counts of every block (acnt), or
+  // relative ones (qc) plus absolute rows for the texts whose tree starts here
+  // (aroot, text t's rows from root_row[t])
+  uint32_t* acnt = nullptr;
+  uint8_t* qc = nullptr;
+  uint32_t* aroot = nullptr;
+  std::vector<uint64_t> root_row;
+  uint8_t* pc = nullptr;
+  uint32_t* msel = nullptr;
+  uint64_t* st = nullptr;
+  uint32_t qw = 0, pw = 0;
 };
 
 int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& offs,
@@ -811,6 +824,47 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       throw Fail{BT_E_INTERNAL};
     }
   };
+  // ---- rank/select counts of a level from its absolute counts A: kept as they
+  // are where relative counts would need 32 bits, else narrowed to counts
+  // inside the parent (at most (tau - 1) b) with absolute rows for the texts
+  // whose tree starts at this step.  Also keeps the block starts (select).
+  uint64_t rank_bytes = 0;
+  auto rank_counts = [&](uint32_t step, uint64_t b, uint64_t c, const uint64_t* st,
+                         const uint32_t* text, const uint64_t* d_tf,
+                         const std::vector<uint64_t>& tcount, const std::vector<uint64_t>& tfirst,
+                         Buf<uint32_t>& A, LevelBufs& LB) {
+    Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
+    if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st, c * 8, hipMemcpyDeviceToDevice, s));
+    LB.st = store->add(std::move(stc), c);
+    rank_bytes += 8 * c;
+    LB.qw = counter_width((uint64_t)(prm.tau - 1) * b);
+    if (LB.qw == 4) {
+      LB.acnt = store->add(std::move(A), c * S);
+      rank_bytes += 4 * c * S;
+      return;
+    }
+    Buf<uint8_t> q = alloc<uint8_t>(ctx, c * S * LB.qw);
+    HIPCHK(ctx, launch_relative_counts(A.p, c, S, text, d_tf, prm.tau, q.p, LB.qw, s));
+    LB.qc = store->add(std::move(q), c * S * LB.qw);
+    rank_bytes += (uint64_t)LB.qw * c * S;
+    std::vector<uint64_t> ent;
+    uint64_t rows = 0;
+    LB.root_row.assign(T, ~0ull);
+    for (uint32_t t = 0; t < T; ++t)
+      if (H - plan[t].h == step && tcount[t]) {
+        ent.insert(ent.end(), {tfirst[t], tcount[t], rows});
+        LB.root_row[t] = rows;
+        rows += tcount[t];
+      }
+    if (!rows) return;
+    const uint32_t E = (uint32_t)(ent.size() / 3);
+    Buf<uint64_t> d_ent = alloc<uint64_t>(ctx, ent.size());
+    upload(ctx, d_ent.p, ent.data(), ent.size());
+    Buf<uint32_t> ar = alloc<uint32_t>(ctx, rows * S);
+    HIPCHK(ctx, launch_root_rows(A.p, S, d_ent.p, E, ar.p, s));
+    LB.aroot = store->add(std::move(ar), rows * S);
+    rank_bytes += 4 * rows * S;
+  };
   // ---- tree storage of an internal level: marks packed per text (with their
   // ranks), the pointers (by unmarked rank; the buffers move into the storage)
   // and the rank/select counters.  uoff: exclusive scan of the unmarked flags.
@@ -834,23 +888,27 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     HIPCHK(ctx, launch_word_pop(words.p, nwords, wtmp.p, s));
     scan(wtmp.p, nwords);
     HIPCHK(ctx, launch_word_rank(wtmp.p, T, d_woff.p, nwords, wrank.p, s));
-    LevelBufs LB{store->add(std::move(words), nwords), store->add(std::move(wrank), nwords + 1),
-                 store->add(std::move(spb), u), store->add(std::move(spo), u), nullptr, nullptr,
-                 nullptr};
+    LevelBufs LB;
+    LB.words = store->add(std::move(words), nwords);
+    LB.wrank = store->add(std::move(wrank), nwords + 1);
+    LB.pb = store->add(std::move(spb), u);
+    LB.po = store->add(std::move(spo), u);
     if (rank_on) {
-      Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
-      Buf<uint32_t> pcnt = alloc<uint32_t>(ctx, u * S);
-      Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
-      HIPCHK(ctx, launch_block_rank_counts(rc, st, text, c, d_Rt.p, cnt.p, s));
-      // the pointer arrays now belong to the storage (spb/spo were released)
+      Buf<uint32_t> A = alloc<uint32_t>(ctx, c * S);
+      HIPCHK(ctx, launch_block_rank_counts(rc, st, text, c, d_Rt.p, A.p, s));
+      // pointer counts: below b (the pointer arrays now belong to the storage)
+      LB.pw = counter_width(b ? b - 1 : 0);
+      Buf<uint8_t> pc = alloc<uint8_t>(ctx, u * S * LB.pw);
       HIPCHK(ctx, launch_pointer_rank_counts(rc, st, text, marked, c, uoff, d_tf, LB.pb, LB.po,
-                                             d_Rt.p, cnt.p, pcnt.p, s));
-      if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st, c * 8, hipMemcpyDeviceToDevice, s));
-      LB.cnt = store->add(std::move(cnt), c * S);
-      LB.pcnt = store->add(std::move(pcnt), u * S);
-      LB.st = store->add(std::move(stc), c);
+                                             d_Rt.p, A.p, pc.p, LB.pw, s));
+      LB.pc = store->add(std::move(pc), u * S * LB.pw);
+      Buf<uint32_t> msel = alloc<uint32_t>(ctx, c - u);
+      HIPCHK(ctx, launch_marked_index(marked, uoff, c, text, d_tf, msel.p, s));
+      LB.msel = store->add(std::move(msel), c - u);
+      rank_bytes += (uint64_t)LB.pw * u * S + 4 * (c - u);
+      rank_counts(step, b, c, st, text, d_tf, tcount, tfirst, A, LB);
     }
-    lbufs[step] = LB;
+    lbufs[step] = std::move(LB);
     for (uint32_t t = 0; t < T; ++t)
       if (H - plan[t].h <= step)
         rec[t][step - (H - plan[t].h)] = {b, tcount[t], tu[t], h_woff[t], h_poff[t], tfirst[t]};
@@ -866,16 +924,13 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     Buf<uint8_t> lb = alloc<uint8_t>(ctx, c * b);
     HIPCHK(ctx, launch_leaves(d_base, lvl, tx, lb.p, s));
     leaves = store->add(std::move(lb), c * b);
-    LevelBufs LL{};
+    LevelBufs LL;
     if (rank_on) {
-      Buf<uint32_t> cnt = alloc<uint32_t>(ctx, c * S);
-      HIPCHK(ctx, launch_block_rank_counts(rc, st, text, c, d_Rt.p, cnt.p, s));
-      Buf<uint64_t> stc = alloc<uint64_t>(ctx, c);
-      if (c) HIPCHK(ctx, hipMemcpyAsync(stc.p, st, c * 8, hipMemcpyDeviceToDevice, s));
-      LL.cnt = store->add(std::move(cnt), c * S);
-      LL.st = store->add(std::move(stc), c);
+      Buf<uint32_t> A = alloc<uint32_t>(ctx, c * S);
+      HIPCHK(ctx, launch_block_rank_counts(rc, st, text, c, d_Rt.p, A.p, s));
+      rank_counts(step, b, c, st, text, d_tf, tcount, tfirst, A, LL);
     }
-    lbufs[step] = LL;
+    lbufs[step] = std::move(LL);
     Buf<uint64_t> d_last = alloc<uint64_t>(ctx, T);
     HIPCHK(ctx, launch_last_block_len(lvl, tx, d_tf, d_tc, d_last.p, s));
     std::vector<uint64_t> last;
@@ -1497,6 +1552,15 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   }
 
   // ---- trees
+  // a tree's counts on one level: absolute for the whole step, absolute rows of
+  // its first level, or relative
+  auto rank_level = [&](TreeLevel& tl, const LevelBufs& L, uint32_t t, uint32_t l, uint64_t first) {
+    if (L.acnt) tl.acnt = L.acnt + first * S;
+    else if (l == 0) tl.acnt = L.aroot + L.root_row[t] * S;
+    else tl.qc = L.qc + first * S * L.qw;
+    tl.qw = L.qw;
+    tl.st = L.st + first;
+  };
   for (uint32_t t = 0; t < T; ++t) {
     bt_tree* tr = new bt_tree;
     tr->store = store;
@@ -1519,19 +1583,18 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       tl.pb = L.pb + r.ptr_off;
       tl.po = L.po + r.ptr_off;
       if (rank_on) {
-        tl.cnt = L.cnt + r.first * S;
-        tl.pcnt = L.pcnt + r.ptr_off * S;
-        tl.st = L.st + r.first;
+        rank_level(tl, L, t, l, r.first);
+        tl.pc = L.pc + r.ptr_off * S * L.pw;
+        tl.pw = L.pw;
+        // marked blocks before this text's: its blocks before, less its unmarked ones
+        tl.msel = L.msel + (r.first - r.ptr_off);
       }
       tr->lv.push_back(tl);
     }
     TreeLevel leafl;
     leafl.b = rec[t].back().b;
     leafl.c = rec[t].back().c;
-    if (rank_on) {
-      leafl.cnt = lbufs.back().cnt + rec[t].back().first * S;
-      leafl.st = lbufs.back().st + rec[t].back().first;
-    }
+    if (rank_on) rank_level(leafl, lbufs.back(), t, plan[t].h - 1, rec[t].back().first);
     tr->lv.push_back(leafl);
     tr->has_rank = with_rank;
     tr->sym = d_sym;
@@ -1549,7 +1612,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     for (uint32_t t = 0; t < T; ++t) {
       at[t] = ql.size();
       for (const TreeLevel& L : outs[t]->lv)
-        ql.push_back(QLevel{L.b, L.c, L.words, L.wrank, L.pb, L.po, L.cnt, L.pcnt, L.st});
+        ql.push_back(QLevel{L.b, L.c, L.words, L.wrank, L.pb, L.po, L.acnt, L.qc, L.pc, L.msel,
+                            L.st, L.qw, L.pw});
     }
     Buf<QLevel> d = alloc<QLevel>(ctx, ql.size());
     const uint64_t words = (ql.size() * sizeof(QLevel) + 7) / 8;
@@ -1561,6 +1625,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     for (uint32_t t = 0; t < T; ++t) {
       outs[t]->d_levels = base + at[t];
       outs[t]->dev_bytes = store->bytes / T;
+      outs[t]->rank_bytes = rank_bytes / T;
     }
   }
   return BT_OK;
@@ -2032,6 +2097,12 @@ int bt_select(bt_ctx* ctx, const bt_tree* t, const uint8_t* d_c, const uint64_t*
 int bt_tree_device_bytes(const bt_tree* t, uint64_t* bytes) {
   if (!t || !bytes) return BT_E_INVAL;
   *bytes = t->dev_bytes;
+  return BT_OK;
+}
+
+int bt_tree_rank_bytes(const bt_tree* t, uint64_t* bytes) {
+  if (!t || !bytes) return BT_E_INVAL;
+  *bytes = t->rank_bytes;
   return BT_OK;
 }
 

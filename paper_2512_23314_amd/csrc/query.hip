@@ -90,10 +90,37 @@ hipError_t launch_access(QTree t, const uint64_t* pos, uint64_t m, uint8_t* out,
   return hipGetLastError();
 }
 
-// rank(c, i): the same walk as access; every pointer followed from block j
-// (unmarked number u, target t) adds cnt[j] - cnt[t] - pcnt[u], i.e. the count
-// before block j minus the count before the source position; at the leaf the
-// leaf's own count and the bytes before the offset are added.
+// Counter of width w at index idx.
+__device__ __forceinline__ uint64_t narrow_at(const uint8_t* p, uint32_t w, uint64_t idx) {
+  return w == 1 ? p[idx]
+                : w == 2 ? reinterpret_cast<const uint16_t*>(p)[idx]
+                         : reinterpret_cast<const uint32_t*>(p)[idx];
+}
+
+// R (occurrences of symbol s before block x of level l, from the text's
+// start): relative counts up the parents to the nearest absolute level.
+__device__ uint64_t block_count(const QTree& q, uint32_t l, uint64_t x, uint32_t s) {
+  uint64_t r = 0;
+  while (!q.lv[l].acnt) {
+    const QLevel& L = q.lv[l];
+    r += narrow_at(L.qc, L.qw, x * q.S + s);
+    x = q.lv[l - 1].msel[x / q.tau];
+    --l;
+  }
+  return r + q.lv[l].acnt[x * q.S + s];
+}
+
+// R of block jc of level l1 whose parent has R = rp.
+__device__ __forceinline__ uint64_t child_count(const QTree& q, uint32_t l1, uint64_t jc, uint32_t s,
+                                                uint64_t rp) {
+  const QLevel& N = q.lv[l1];
+  return N.acnt ? N.acnt[jc * q.S + s] : rp + narrow_at(N.qc, N.qw, jc * q.S + s);
+}
+
+// rank(c, i): the walk of access, carrying R of the current block.  Every
+// pointer followed from block j (unmarked number u, target t) adds
+// R[j] - (R[t] + P[u]), the count before block j minus the count before the
+// source position; at the leaf, R of the leaf and the bytes before the offset.
 __global__ void k_rank(QTree q, const uint8_t* __restrict__ cs, const uint64_t* __restrict__ pos,
                        uint64_t m, uint64_t* __restrict__ out) {
   const uint32_t S = q.S;
@@ -113,16 +140,41 @@ __global__ void k_rank(QTree q, const uint8_t* __restrict__ cs, const uint64_t* 
       out[k] = q.total[s];
       continue;
     }
+    const QLevel* lv = q.lv;
+    uint64_t j = i / lv[0].b;
+    uint64_t o = i - j * lv[0].b;
+    uint64_t R = lv[0].acnt[j * S + s];
     int64_t acc = 0;
-    uint64_t leaf, o;
-    descend(q, i, leaf, o,
-            [&](uint32_t l, uint64_t j, uint64_t u, uint64_t t, uint64_t, uint64_t) {
-              const QLevel& L = q.lv[l];
-              acc += (int64_t)L.cnt[j * S + s] - (int64_t)L.cnt[t * S + s] -
-                     (int64_t)L.pcnt[u * S + s];
-            });
-    acc += q.lv[q.h - 1].cnt[leaf * S + s];
-    const uint8_t* lb = q.leaves + leaf * q.leaf_len;
+    uint32_t l = 0;
+    while (l + 1 < q.h) {
+      const QLevel& L = lv[l];
+      const uint64_t r1 = marks_before(L, j);
+      if (is_marked(L, j)) {
+        const uint64_t bn = lv[l + 1].b;
+        const uint64_t x = o / bn;
+        j = r1 * q.tau + x;
+        o -= x * bn;
+        ++l;
+        R = child_count(q, l, j, s, R);
+      } else {
+        const uint64_t u = j - r1;
+        uint64_t t = L.pb[u];
+        uint64_t o2 = L.po[u] + o;
+        const uint64_t Rt = block_count(q, l, t, s);
+        acc += (int64_t)R - (int64_t)(Rt + narrow_at(L.pc, L.pw, u * S + s));
+        if (o2 >= L.b) {
+          o2 -= L.b;
+          ++t;
+          R = block_count(q, l, t, s);
+        } else {
+          R = Rt;
+        }
+        j = t;
+        o = o2;
+      }
+    }
+    acc += (int64_t)R;
+    const uint8_t* lb = q.leaves + j * q.leaf_len;
     for (uint64_t r = 0; r < o; ++r) acc += lb[r] == ch;
     out[k] = (uint64_t)acc;
   }
@@ -135,13 +187,13 @@ hipError_t launch_rank(QTree t, const uint8_t* cs, const uint64_t* pos, uint64_t
   return hipGetLastError();
 }
 
-// select(c, k): keep the invariant cnt[j] < k <= cnt[j] + (occurrences in
-// block j).  Level 1: binary search over the blocks.  Marked block: the last
-// child whose count is below k.  Unmarked block j with pointer (t, off): the
-// wanted occurrence is the (k - cnt[j])-th inside the block, i.e. occurrence
-// k' = cnt[t] + pcnt[u] + (k - cnt[j]) of the source, which lies in block t or
-// t+1; the answer moves by (start of j) - (source position).  At the leaf,
-// scan its bytes.
+// select(c, k): keep the invariant R[j] < k <= R[j] + (occurrences in block
+// j), carrying R of the current block.  Level 1: binary search over the blocks.
+// Marked block: the last child whose count is below k.  Unmarked block j with
+// pointer (t, off): the wanted occurrence is the (k - R[j])-th inside the block,
+// i.e. occurrence k' = R[t] + P[u] + (k - R[j]) of the source, which lies in
+// block t or t+1; the answer moves by (start of j) - (source position).  At the
+// leaf, scan its bytes.
 __global__ void k_select(QTree q, const uint8_t* __restrict__ cs, const uint64_t* __restrict__ ks,
                          uint64_t m, uint64_t* __restrict__ out) {
   const uint32_t S = q.S;
@@ -157,9 +209,10 @@ __global__ void k_select(QTree q, const uint8_t* __restrict__ cs, const uint64_t
     uint64_t lo = 0, hi = lv[0].c;
     while (hi - lo > 1) {
       const uint64_t mid = (lo + hi) >> 1;
-      if (lv[0].cnt[mid * S + s] < k) lo = mid; else hi = mid;
+      if (lv[0].acnt[mid * S + s] < k) lo = mid; else hi = mid;
     }
     uint64_t j = lo;
+    uint64_t R = lv[0].acnt[j * S + s];
     uint32_t l = 0;
     uint64_t shift = 0;
     while (l + 1 < q.h) {
@@ -170,24 +223,39 @@ __global__ void k_select(QTree q, const uint8_t* __restrict__ cs, const uint64_t
         const uint64_t j0 = r1 * q.tau;
         uint64_t nch = N.c - j0;
         if (nch > q.tau) nch = q.tau;
-        uint64_t x = 1;
-        while (x < nch && N.cnt[(j0 + x) * S + s] < k) ++x;
+        // the first child starts where its parent does: its R is the parent's
+        uint64_t x = 1, Rx = R;
+        while (x < nch) {
+          const uint64_t Rn = child_count(q, l + 1, j0 + x, s, R);
+          if (Rn >= k) break;
+          Rx = Rn;
+          ++x;
+        }
         j = j0 + x - 1;
+        R = Rx;
         ++l;
       } else {
         const uint64_t u = j - r1;
         const uint64_t t = L.pb[u];
         const uint64_t src = L.st[t] + L.po[u];
-        const uint64_t k2 = (uint64_t)L.cnt[t * S + s] + L.pcnt[u * S + s] + (k - L.cnt[j * S + s]);
+        const uint64_t Rt = block_count(q, l, t, s);
+        const uint64_t k2 = Rt + narrow_at(L.pc, L.pw, u * S + s) + (k - R);
         shift += L.st[j] - src;
-        uint64_t nt = t;
-        if (t + 1 < L.c && L.st[t + 1] == L.st[t] + L.b && L.cnt[(t + 1) * S + s] < k2) nt = t + 1;
+        uint64_t nt = t, Rn = Rt;
+        if (t + 1 < L.c && L.st[t + 1] == L.st[t] + L.b) {
+          const uint64_t R1 = block_count(q, l, t + 1, s);
+          if (R1 < k2) {
+            nt = t + 1;
+            Rn = R1;
+          }
+        }
         j = nt;
         k = k2;
+        R = Rn;
       }
     }
     const QLevel& LH = lv[q.h - 1];
-    uint64_t need = k - LH.cnt[j * S + s];
+    uint64_t need = k - R;
     const uint8_t* lb = q.leaves + j * q.leaf_len;
     uint64_t res = ~0ull;
     const uint64_t rest = q.tstart + q.n - LH.st[j];

@@ -17,11 +17,18 @@ struct QLevel {
   const uint64_t* wrank;   // marks before each word (within this tree)
   const uint64_t* pb;      // pointer block (level-local), one per unmarked block
   const uint64_t* po;      // pointer offset
-  // rank/select support (rank.hip); null when the tree was built without it
-  const uint32_t* cnt;     // [c * S]: occurrences of each symbol before the block
-  const uint32_t* pcnt;    // [u * S]: occurrences between the target block's start
-                           //          and the source position
+  // rank/select support (rank.hip); all null when the tree was built without it
+  const uint32_t* acnt;    // [c * S]: occurrences of each symbol before the block
+                           //          (from the text's start), or null on a
+                           //          relative level:
+  const uint8_t* qc;       // [c * S]: occurrences inside the parent before the
+                           //          block, qw bytes each
+  const uint8_t* pc;       // [u * S]: occurrences between the target block's start
+                           //          and the source position, pw bytes each
+  const uint32_t* msel;    // [marked blocks]: index of each marked block (internal
+                           //          levels; the parent of child j is msel[j / tau])
   const uint64_t* st;      // [c] block starts (positions in the build's buffer)
+  uint32_t qw, pw;         // widths in bytes (1, 2 or 4)
 };
 
 struct QTree {
@@ -56,7 +63,20 @@ hipError_t launch_pointer_rank_counts(const RankCtx& rc, const uint64_t* st, con
                                       const uint8_t* marked, uint64_t c, const uint64_t* uoff,
                                       const uint64_t* tfirst, const uint64_t* pb,
                                       const uint64_t* po, const uint64_t* Rt, const uint32_t* cnt,
-                                      uint32_t* pcnt, hipStream_t s);
+                                      uint8_t* pcnt, uint32_t pw, hipStream_t s);
+// Relative counts of a level from its absolute ones A (u32, from the text's
+// start), qw bytes each.
+hipError_t launch_relative_counts(const uint32_t* A, uint64_t c, uint32_t S, const uint32_t* text,
+                                  const uint64_t* tfirst, uint32_t tau, uint8_t* q, uint32_t qw,
+                                  hipStream_t s);
+// Copies of absolute rows: ent holds E triples (first row, rows, destination row).
+hipError_t launch_root_rows(const uint32_t* A, uint32_t S, const uint64_t* ent, uint32_t E,
+                            uint32_t* out, hipStream_t s);
+hipError_t launch_marked_index(const uint8_t* marked, const uint64_t* uoff, uint64_t c,
+                               const uint32_t* text, const uint64_t* tfirst, uint32_t* msel,
+                               hipStream_t s);
+// Bytes of a counter that holds values up to vmax: 1, 2 or 4.
+inline uint32_t counter_width(uint64_t vmax) { return vmax <= 0xFF ? 1u : vmax <= 0xFFFF ? 2u : 4u; }
 
 hipError_t launch_access(QTree t, const uint64_t* pos, uint64_t m, uint8_t* out, uint32_t* bad,
                          hipStream_t s);

@@ -1,21 +1,35 @@
 // Rank/select support of a block tree (Section 1 defines the queries; the
 // counters follow the usual block-tree scheme of storing, per block, how often
-// each symbol occurs before it).  Built from the text during construction,
-// only when requested:
-//   cnt[l][j][s]  occurrences of symbol s in T[text start, start of block j)
-//                 for every block j of every level l (leaves included);
-//   pcnt[l][u][s] occurrences of s in T[start of target block t, source
-//                 position) for the u-th unmarked block of level l.
+// each symbol occurs before it, made compact).  Built from the text during
+// construction, only when requested.  Per level l with block length b:
+//   R[l][j][s]  occurrences of symbol s in T[text start, start of block j),
+//               for every block j (leaves included), stored in one of two forms:
+//     absolute  (u32) on a tree's first level, and on levels whose relative
+//               counts would need 32 bits anyway;
+//     relative  Q[l][j][s] = R[l][j][s] - R[l-1][parent][s], the occurrences
+//               inside the parent before the block: at most (tau - 1) b, so 8
+//               or 16 bits.  A query recovers R by walking up the parents
+//               (msel: the index of each marked block of a level) to the
+//               nearest absolute level.
+//   P[l][u][s]  occurrences of s in T[start of target block t, source
+//               position) for the u-th unmarked block: below b, so 8, 16 or
+//               32 bits.
 // Symbols are the text's distinct byte values, densely renumbered.
 //
-// Both come from a sampled count table G: G[k][s] = occurrences of s in the
+// All come from a sampled count table G: G[k][s] = occurrences of s in the
 // first k*Q bytes of the concatenation (Q = 1024), so that the count before any
-// position p is G[p / Q] plus a histogram of at most Q bytes.
+// position p is G[p / Q] plus a histogram of at most Q bytes.  A level's
+// absolute counts are formed first (a temporary of 4 B per block and symbol),
+// then narrowed.
 #include "common.hpp"
 #include "internal.hpp"
 #include "query.hpp"
 
 namespace bt {
+
+#define GRID_STRIDE(i, n)                                                        \
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+       i += (uint64_t)gridDim.x * blockDim.x)
 
 static unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 8192) {
   uint64_t g = (n + threads - 1) / threads;
@@ -145,6 +159,49 @@ __global__ __launch_bounds__(256) void k_block_counts(RankCtx rc, const uint64_t
   }
 }
 
+__device__ __forceinline__ void put_narrow(uint8_t* p, uint32_t w, uint64_t idx, uint32_t v) {
+  if (w == 1) p[idx] = (uint8_t)v;
+  else if (w == 2) reinterpret_cast<uint16_t*>(p)[idx] = (uint16_t)v;
+  else reinterpret_cast<uint32_t*>(p)[idx] = v;
+}
+
+// Q[j][s] = R[j][s] - R[f][s], f = the first child of block j's parent (the
+// block j - (jl mod tau), jl = j's index within its text's level): the parent
+// and its first child start at the same position, so R[f] = R[parent].  Rows
+// of a text's first level (no parent) are never read and are left as computed.
+__global__ void k_relative_counts(const uint32_t* __restrict__ A, uint64_t c, uint32_t S,
+                                  const uint32_t* __restrict__ text,
+                                  const uint64_t* __restrict__ tfirst, uint32_t tau,
+                                  uint8_t* __restrict__ q, uint32_t qw) {
+  GRID_STRIDE(idx, c * S) {
+    const uint64_t j = idx / S, sy = idx - j * S;
+    const uint64_t jl = j - tfirst[text[j]];
+    const uint64_t f = j - jl % tau;
+    put_narrow(q, qw, idx, A[idx] - A[f * S + sy]);
+  }
+}
+
+// Absolute rows of the texts that start at this level: entry e copies rows
+// [src[e], src[e] + rows[e]) of A to [dst[e], ...) of out.
+__global__ void k_root_rows(const uint32_t* __restrict__ A, uint32_t S,
+                            const uint64_t* __restrict__ ent, uint32_t E,
+                            uint32_t* __restrict__ out) {
+  for (uint32_t e = blockIdx.x; e < E; e += gridDim.x) {
+    const uint64_t src = ent[3 * e], rows = ent[3 * e + 1], dst = ent[3 * e + 2];
+    for (uint64_t k = threadIdx.x; k < rows * S; k += blockDim.x) out[dst * S + k] = A[src * S + k];
+  }
+}
+
+// msel[m] = index within its text's level of the m-th marked block of the
+// level (m counted over the whole level; a text's marked blocks are contiguous).
+__global__ void k_marked_index(const uint8_t* __restrict__ marked, const uint64_t* __restrict__ uoff,
+                               uint64_t c, const uint32_t* __restrict__ text,
+                               const uint64_t* __restrict__ tfirst, uint32_t* __restrict__ msel) {
+  GRID_STRIDE(j, c) {
+    if (marked[j]) msel[j - uoff[j]] = (uint32_t)(j - tfirst[text[j]]);
+  }
+}
+
 // pcnt[u][s] for every unmarked block of a level (target t = tfirst + ptr_block).
 __global__ __launch_bounds__(256) void k_pointer_counts(RankCtx rc, const uint64_t* st,
                                                         const uint32_t* text,
@@ -153,7 +210,7 @@ __global__ __launch_bounds__(256) void k_pointer_counts(RankCtx rc, const uint64
                                                         const uint64_t* tfirst,
                                                         const uint64_t* pb, const uint64_t* po,
                                                         const uint64_t* Rt, const uint32_t* cnt,
-                                                        uint32_t* pcnt) {
+                                                        uint8_t* pcnt, uint32_t pw) {
   __shared__ uint32_t s_part[4][256];
   uint32_t* part = s_part[threadIdx.x >> 6];
   const int lane = lane_id();
@@ -167,8 +224,8 @@ __global__ __launch_bounds__(256) void k_pointer_counts(RankCtx rc, const uint64
     const uint64_t p = st[t] + po[u];
     wave_counts_before(rc, p, part);
     for (uint32_t s = lane; s < rc.S; s += 64)
-      pcnt[u * rc.S + s] =
-          (uint32_t)(count_of(rc, p, part, s) - Rt[tx * rc.S + s] - cnt[t * rc.S + s]);
+      put_narrow(pcnt, pw, u * rc.S + s,
+                 (uint32_t)(count_of(rc, p, part, s) - Rt[tx * rc.S + s] - cnt[t * rc.S + s]));
   }
 }
 
@@ -206,10 +263,33 @@ hipError_t launch_pointer_rank_counts(const RankCtx& rc, const uint64_t* st, con
                                       const uint8_t* marked, uint64_t c, const uint64_t* uoff,
                                       const uint64_t* tfirst, const uint64_t* pb,
                                       const uint64_t* po, const uint64_t* Rt, const uint32_t* cnt,
-                                      uint32_t* pcnt, hipStream_t s) {
+                                      uint8_t* pcnt, uint32_t pw, hipStream_t s) {
   if (!c) return hipSuccess;
   k_pointer_counts<<<grid_for(c * 64, 256, 4096), 256, 0, s>>>(rc, st, text, marked, c, uoff,
-                                                                tfirst, pb, po, Rt, cnt, pcnt);
+                                                                tfirst, pb, po, Rt, cnt, pcnt, pw);
+  return hipGetLastError();
+}
+
+hipError_t launch_relative_counts(const uint32_t* A, uint64_t c, uint32_t S, const uint32_t* text,
+                                  const uint64_t* tfirst, uint32_t tau, uint8_t* q, uint32_t qw,
+                                  hipStream_t s) {
+  if (!c) return hipSuccess;
+  k_relative_counts<<<grid_for(c * S, 256), 256, 0, s>>>(A, c, S, text, tfirst, tau, q, qw);
+  return hipGetLastError();
+}
+
+hipError_t launch_root_rows(const uint32_t* A, uint32_t S, const uint64_t* ent, uint32_t E,
+                            uint32_t* out, hipStream_t s) {
+  if (!E) return hipSuccess;
+  k_root_rows<<<E < 4096 ? E : 4096, 256, 0, s>>>(A, S, ent, E, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_marked_index(const uint8_t* marked, const uint64_t* uoff, uint64_t c,
+                               const uint32_t* text, const uint64_t* tfirst, uint32_t* msel,
+                               hipStream_t s) {
+  if (!c) return hipSuccess;
+  k_marked_index<<<grid_for(c, 256), 256, 0, s>>>(marked, uoff, c, text, tfirst, msel);
   return hipGetLastError();
 }
 

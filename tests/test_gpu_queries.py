@@ -103,3 +103,30 @@ def test_rank_needs_support(ctx):
     tree = ctx.build(to_device(T), tau=2, leaf_len=16)
     with pytest.raises(bt.BtError):
         tree.rank(to_device(np.array([65], np.uint8)), _dev_u64([3]))
+
+
+def _dense_support_bytes(tree, S):
+    """What 32-bit counters for every block and every pointer would take (the
+    uncompacted form), plus the same block starts."""
+    tot = 0
+    for l in range(1, tree.height + 1):
+        _, c, u = tree.level_info(l)
+        tot += 4 * S * (c + u) + 8 * c
+    return tot
+
+
+@pytest.mark.parametrize("tau,leaf", [(4, 16), (2, 8), (8, 4)])
+def test_queries_counter_widths(ctx, tau, leaf):
+    """A 3 MiB versioned text (sigma 96): its levels span 32-bit absolute
+    counters (long blocks), 16-bit and 8-bit relative ones, and 8/16/32-bit
+    pointer counts; queries walk up the parents through all of them.  The
+    support takes well under half of the 32-bit form."""
+    T = synth.cfg2_text()[: 3 << 20].copy()
+    tree = ctx.build(to_device(T), sigma=96, tau=tau, leaf_len=leaf, rank_select=True)
+    _check_queries(tree, T, tau * 100 + leaf, m=40000)
+    S = int(np.unique(T).size)
+    rb = tree.rank_bytes()
+    assert 0 < rb <= 0.5 * _dense_support_bytes(tree, S), (rb, _dense_support_bytes(tree, S))
+    plain = ctx.build(to_device(T), sigma=96, tau=tau, leaf_len=leaf)
+    assert plain.rank_bytes() == 0
+    assert plain.serialize() == tree.serialize()
