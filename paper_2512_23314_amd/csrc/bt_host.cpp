@@ -1293,13 +1293,16 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         // counted only for the part beyond the tile.
         const double per_value = a.pre32 ? 4.0 : 8.0;
         const double partner = (double)std::min<uint64_t>(a.Lmain, kProbeTile) / (double)kProbeTile;
+        // spans: at least four per resident workgroup (512) for the level's
+        // window bound, 16 to 256 chunks, a multiple of the 16 waves
+        uint64_t span_chunks = (c * b) / kProbeTile / (4 * 512);
+        span_chunks = std::min<uint64_t>(256, std::max<uint64_t>(16, span_chunks & ~15ull));
+        if (ctx->tune.span_chunks) span_chunks = ctx->tune.span_chunks;
+        Buf<uint64_t> span_info;
+        if (text_local) span_info = alloc<uint64_t>(ctx, 3 * probe_text_spans(c * b, span_chunks));
         timed(ctx, "probe_scan", 0, 0, wst, per_value * (1.0 + partner), [&] {
-          // spans: at least four per resident workgroup (512) for the level's
-          // window bound, 16 to 256 chunks, a multiple of the 16 waves
-          uint64_t span_chunks = (c * b) / kProbeTile / (4 * 512);
-          span_chunks = std::min<uint64_t>(256, std::max<uint64_t>(16, span_chunks & ~15ull));
-          if (ctx->tune.span_chunks) span_chunks = ctx->tune.span_chunks;
-          return text_local ? launch_probe_text(as, swoff, has_odd, c * b, span_chunks, span_ctr.p, s)
+          return text_local ? launch_probe_text(as, swoff, has_odd, c * b, span_chunks, span_ctr.p,
+                                                span_info.p, s)
                             : launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
         }, a.Lmain);
       }

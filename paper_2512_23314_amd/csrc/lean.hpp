@@ -20,34 +20,38 @@ namespace bt {
 
 constexpr int kLeanK = 16;  // consecutive windows per lane
 
-// Segment holding window number w: the last r with woff[r] <= w.
-__device__ __forceinline__ uint64_t segment_of(const uint64_t* __restrict__ woff, uint64_t R,
-                                               uint64_t w) {
-  uint64_t lo = 0, hi = R;
+// Segment holding window number w among segments [lo, hi): the last r there
+// with woff[r] <= w (lo when none is).
+__device__ __forceinline__ uint64_t segment_in(const uint64_t* __restrict__ woff, uint64_t lo,
+                                               uint64_t hi, uint64_t w) {
   while (hi - lo > 1) {
     const uint64_t mid = (lo + hi) >> 1;
     if (woff[mid] <= w) lo = mid; else hi = mid;
   }
   return lo;
 }
+__device__ __forceinline__ uint64_t segment_of(const uint64_t* __restrict__ woff, uint64_t R,
+                                               uint64_t w) {
+  return segment_in(woff, 0, R, w);
+}
 
-// One lane's kLeanK windows from w0 (the whole wave calls it: push is
-// wave-wide).  TEXT: segments carry texts (the text table is read).  SALT: the
+// One lane's kLeanK windows from w0, whose segments lie in [rlo, rhi) (the
+// whole wave calls it: push is wave-wide).  TEXT: segments carry texts (the text table is read).  SALT: the
 // text's salt is added to every hash and fingerprint.  on_text(t) runs for the
 // first text and whenever the lane moves to another one; test8(hv, ok) tests
 // eight salted hashes at once, test1(h) one; push(cand, i, t) takes every
 // window slot (cand false where there is no window).
 template <bool ODD, bool TEXT, bool SALT, class OnText, class Test8, class Test1, class Push>
 __device__ __forceinline__ void lean_chunk(const PhaseArgs& a, const uint64_t* __restrict__ woff,
-                                           uint64_t R, uint64_t W, uint64_t w0, OnText on_text,
-                                           Test8 test8, Test1 test1, Push push) {
+                                           uint64_t rlo, uint64_t rhi, uint64_t W, uint64_t w0,
+                                           OnText on_text, Test8 test8, Test1 test1, Push push) {
   const uint32_t* __restrict__ Hs = a.Hs;
   const uint8_t* __restrict__ T = a.T;
   const uint64_t base = a.pbase, end = a.pend, L = a.Lmain, fmask = a.fpmask;
   const uint32_t x32 = a.x32, x32L = a.x32L, x32Lm1 = a.x32Lm1;
   const auto h32 = [&](uint64_t i) { return h32_at(Hs, T, base, end, x32, i); };
 
-  uint64_t r = segment_of(woff, R, w0);
+  uint64_t r = segment_in(woff, rlo, rhi, w0);
   uint64_t wo = woff[r], wn = woff[r + 1], rs = a.lv.rs[r], re = a.lv.re[r];
   // lanes past the last window hold no segment: they read no text entry
   uint32_t t = (TEXT && w0 < W) ? a.lv.rtext[r] : 0;

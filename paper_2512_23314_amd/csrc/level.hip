@@ -552,7 +552,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         }
       };
       const auto test1 = [&](uint32_t h) { return pass32(h) && (!f2words || pass2(h)); };
-      lean_chunk<ODD, ODD || SALT, SALT>(a, woff, R, W, ch * kScanChunk + (uint64_t)lane * kLeanK,
+      lean_chunk<ODD, ODD || SALT, SALT>(a, woff, 0, R, W, ch * kScanChunk + (uint64_t)lane * kLeanK,
                                          [](uint32_t) {}, test8, test1, push);
       continue;
     }
@@ -599,20 +599,30 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         for (int k0 = 0; k0 < kScanK; k0 += 8) {
           if (PRE) {
             const uint32_t s32 = SALT ? (uint32_t)salt : 0u;
-            uint32_t hv[8];
+            // the sixteen loads leave together: the scheduler would otherwise
+            // pair each load with its use and wait out every latency in turn
+            uint32_t ha[8], hb[8], hc[8];
+            // (and the short key's, H[i + oL], where the text has one)
+            const bool oddk = ODD && oL;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
               const uint64_t i = i0 + 64ull * (k0 + k);
-              hv[k] = H[i + L] - H[i] * x32L + s32;
+              hb[k] = H[i + L];
+              ha[k] = H[i];
+              if (oddk) hc[k] = H[i + oL];
             }
-            if (ODD && oL) {
-              // the short key's 32-bit hashes (H[i] again, from L1); the rare
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t hv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) hv[k] = hb[k] - ha[k] * x32L + s32;
+            if (oddk) {
+              // the short key's 32-bit hashes (loaded with the others); the rare
               // matches form their 61-bit fingerprints one at a time
               uint32_t om = 0;
 #pragma unroll
               for (int k = 0; k < 8; ++k) {
                 const uint64_t i = i0 + 64ull * (k0 + k);
-                if (i < opos && H[i + oL] - H[i] * ox + s32 == oh) om |= 1u << k;
+                if (i < opos && hc[k] - ha[k] * ox + s32 == oh) om |= 1u << k;
               }
               while (om) {
                 const int k = __builtin_ctz(om);

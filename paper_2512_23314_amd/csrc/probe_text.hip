@@ -45,12 +45,12 @@ static_assert(kLeanK == kTlK, "lean chunks are probe tiles too");
 template <bool ODD, bool LEAN>
 __global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(LEAN ? 4 : 8)))
 void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_chunks,
-                  uint64_t* __restrict__ span_ctr) {
+                  uint64_t* __restrict__ span_ctr, const uint64_t* __restrict__ span_info) {
   extern __shared__ uint64_t s_lds[];
   uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);  // up to 2^kTextFilterLdsLog2 words
   uint64_t* q = s_lds + (1u << (kTextFilterLdsLog2 - 1)) + (uint64_t)(threadIdx.x >> 6) * kTlQueue;
   const uint64_t span = span_chunks * kProbeTile;
-  __shared__ uint64_t s_span;
+  __shared__ uint64_t s_span, s_r0, s_r1;
   __shared__ uint32_t s_text;    // the span's text when its filter goes to LDS, else kNoText
   __shared__ uint32_t s_loaded;  // the text whose filter LDS holds, or kNoText
 
@@ -72,6 +72,8 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
   const uint32_t* __restrict__ tfw = a.tf_words;
   const uint64_t* __restrict__ tfo = a.tf_off;
   const uint32_t* __restrict__ tfl = a.tf_wl;
+  // segments of the current span: [span_r0, span_r1]
+  uint64_t span_r0 = 0, span_r1 = 0;
 
   const auto fp61 = [&](uint64_t i, uint64_t salt) {
     const uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
@@ -144,8 +146,9 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
       if (LDS && big && c) c = (tfw[toff + tfilter_word(h, twl)] & m) == m;
       return c;
     };
-    lean_chunk<ODD, true, true>(a, woff, R, W, ch * kProbeTile + (uint64_t)lane * kLeanK, on_text,
-                                test8, test1, push);
+    lean_chunk<ODD, true, true>(a, woff, span_r0, span_r1 + 1, W,
+                                ch * kProbeTile + (uint64_t)lane * kLeanK, on_text, test8, test1,
+                                push);
   };
 
   // One chunk of kProbeTile window numbers.  LDS (a compile-time tag): every
@@ -160,7 +163,7 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
       return;
     }
     const uint64_t w0 = ch * kProbeTile + lane;
-    uint64_t r = segment_of(woff, R, w0);
+    uint64_t r = segment_in(woff, span_r0, span_r1 + 1, w0);
     uint64_t wo = woff[r], wn = woff[r + 1], rs = rs_[r], re = re_[r];
     // lanes past the last window hold no segment: they read no text entry
     uint32_t t = w0 < W ? a.lv.rtext[r] : 0;
@@ -200,20 +203,30 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
         const uint32_t s32 = (uint32_t)salt;
 #pragma unroll
         for (int k0 = 0; k0 < kTlK; k0 += 8) {
-          uint32_t hv[8];
+          // the sixteen loads leave together: the scheduler would otherwise
+          // pair each load with its use and wait out every latency in turn
+          uint32_t ha[8], hb[8], hc[8];
+          // (and the short key's, H[i + oL], where the text has one)
+          const bool oddk = ODD && oL;
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const uint64_t i = i0 + 64ull * (k0 + k);
-            hv[k] = H[i + L] - H[i] * x32L + s32;
+            hb[k] = H[i + L];
+            ha[k] = H[i];
+            if (oddk) hc[k] = H[i + oL];
           }
-          if (ODD && oL) {
-            // the short key's 32-bit hashes (H[i] again, from L1); the rare
+          __builtin_amdgcn_sched_barrier(0);
+          uint32_t hv[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) hv[k] = hb[k] - ha[k] * x32L + s32;
+          if (oddk) {
+            // the short key's 32-bit hashes (loaded with the others); the rare
             // matches form their 61-bit fingerprints one at a time
             uint32_t om = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
               const uint64_t i = i0 + 64ull * (k0 + k);
-              if (i < opos && H[i + oL] - H[i] * ox + s32 == oh) om |= 1u << k;
+              if (i < opos && hc[k] - ha[k] * ox + s32 == oh) om |= 1u << k;
             }
             while (om) {
               const int k = __builtin_ctz(om);
@@ -290,21 +303,19 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
     __syncthreads();  // the previous span is done with s_filt and s_span
     if (threadIdx.x == 0) {
       const uint64_t sp = atomicAdd((unsigned long long*)span_ctr, 1ull);
-      uint32_t tt = kNoText;
       if (sp * span < W) {
-        const uint64_t w0 = sp * span;
-        const uint64_t w1 = (W - w0 < span ? W : w0 + span) - 1;
-        const uint32_t t0 = a.lv.rtext[segment_of(woff, R, w0)];
-        const uint32_t t1 = a.lv.rtext[segment_of(woff, R, w1)];
-        if (t0 == t1) tt = t0;
+        s_r0 = span_info[3 * sp];
+        s_r1 = span_info[3 * sp + 1];
+        s_text = (uint32_t)span_info[3 * sp + 2];
       }
       s_span = sp;
-      s_text = tt;
     }
     __syncthreads();
     const uint64_t sp = s_span;
     if (sp * span >= W) break;
     const uint32_t st = s_text;
+    span_r0 = s_r0;
+    span_r1 = s_r1;
     if (st != kNoText) {
       const uint32_t wl = tfl[st];
       const bool big = wl > kTextFilterLdsLog2;
@@ -339,13 +350,44 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
   if (a.pc && lane == 0 && ncand) atomicAdd((unsigned long long*)(a.pc + kPcCand), (unsigned long long)ncand);
 }
 
+// Per span of `span` window numbers (those below W): its first and last
+// segment and, when both belong to one text, that text (else kNoText), as
+// three words.  One thread per span, so that the resident workgroups of the
+// scan read a span's facts with one load instead of searching for them.
+__global__ void k_span_info(const uint64_t* __restrict__ woff, uint64_t R,
+                            const uint32_t* __restrict__ rtext, uint64_t span, uint64_t nspan,
+                            uint64_t* __restrict__ info) {
+  const uint64_t W = woff[R];
+  for (uint64_t sp = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; sp < nspan;
+       sp += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t w0 = sp * span;
+    if (w0 >= W) break;
+    const uint64_t w1 = (W - w0 < span ? W : w0 + span) - 1;
+    const uint64_t r0 = segment_of(woff, R, w0), r1 = segment_in(woff, r0, R, w1);
+    const uint32_t t0 = rtext[r0], t1 = rtext[r1];
+    info[3 * sp] = r0;
+    info[3 * sp + 1] = r1;
+    info[3 * sp + 2] = t0 == t1 ? t0 : kNoText;
+  }
+}
+
+uint64_t probe_text_spans(uint64_t max_windows, uint64_t span_chunks) {
+  const uint64_t span = span_chunks * kProbeTile;
+  return (max_windows + span - 1) / span;
+}
+
 hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
                              uint64_t max_windows, uint64_t span_chunks, uint64_t* span_ctr,
-                             hipStream_t s) {
+                             uint64_t* span_info, hipStream_t s) {
   if (a.lv.R == 0) return hipSuccess;
-  if (!a.tf_words || !a.pre32 || span_chunks == 0) return hipErrorInvalidValue;
+  if (!a.tf_words || !a.pre32 || span_chunks == 0 || !span_info) return hipErrorInvalidValue;
   const uint64_t span = span_chunks * kProbeTile;
-  const uint64_t spans = (max_windows + span - 1) / span;
+  const uint64_t spans = probe_text_spans(max_windows, span_chunks);
+  {
+    const uint64_t g = (spans + 255) / 256;
+    k_span_info<<<(unsigned)(g < 4096 ? (g ? g : 1) : 4096), 256, 0, s>>>(woff, a.lv.R, a.lv.rtext,
+                                                                          span, spans, span_info);
+  }
   // two resident 1024-thread workgroups per CU (256 CUs)
   const unsigned grid = (unsigned)(spans < 512 ? (spans ? spans : 1) : 512);
   const size_t lds = ((size_t)4 << kTextFilterLdsLog2) + (size_t)kTlWaves * kTlQueue * 8;
@@ -355,7 +397,7 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_probe_text<O, LN>), \
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     if (e != hipSuccess) return e;                                                          \
-    k_probe_text<O, LN><<<grid, kTlThreads, lds, s>>>(a, woff, span_chunks, span_ctr);     \
+    k_probe_text<O, LN><<<grid, kTlThreads, lds, s>>>(a, woff, span_chunks, span_ctr, span_info); \
   } while (0)
   if (has_odd) {
     if (lean) BT_TL_LAUNCH(true, true); else BT_TL_LAUNCH(true, false);

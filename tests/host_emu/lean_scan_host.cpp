@@ -144,7 +144,7 @@ int main(int argc, char** argv) {
           while (!(i >= rs[r] && i < rs[r] + (woff[r + 1] - woff[r]) && woff[r + 1] > woff[r])) ++r;
           seen[woff[r] + (i - rs[r])]++;
         };
-        lean_chunk<true, true, true>(a, woff, R, W, ch * 1024 + (uint64_t)lane * kLeanK, on_text,
+        lean_chunk<true, true, true>(a, woff, 0, R, W, ch * 1024 + (uint64_t)lane * kLeanK, on_text,
                                      test8, test1, push);
         if (fi != fifo.size()) { std::lock_guard<std::mutex> g(mu); ++bad; printf("fifo mismatch\n"); }
       }
