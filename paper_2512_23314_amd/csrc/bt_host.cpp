@@ -1112,6 +1112,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     if (has_salt && c && !(prm.debug_flags & (BT_DBG_SHARED_FILTERS | BT_DBG_SORT_PHASES))) {
       std::vector<uint64_t> h_off(T), h_foff(T, 0);
       std::vector<uint32_t> h_wl(T), h_big;
+      const uint32_t tf_lds = text_filter_lds_log2(lean);
       for (uint32_t t = 0; t < T; ++t) {
         uint32_t wl = 3;
         // 2^(bits_log2 - 5) words of 32 bits per block
@@ -1121,8 +1122,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         h_wl[t] = wl;
         h_off[t] = tf_total;
         tf_total += 1ull << wl;
-        if (wl > kTextFilterLdsLog2) {
-          h_foff[t] = (uint64_t)h_big.size() << kTextFilterLdsLog2;
+        if (wl > tf_lds) {
+          h_foff[t] = (uint64_t)h_big.size() << tf_lds;
           h_big.push_back(t);
         }
       }
@@ -1134,7 +1135,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       upload(ctx, tf_off.p, h_off.data(), T);
       upload(ctx, tf_wl.p, h_wl.data(), T);
       if (nbig) {
-        tf_fold = alloc<uint32_t>(ctx, (uint64_t)nbig << kTextFilterLdsLog2);
+        tf_fold = alloc<uint32_t>(ctx, (uint64_t)nbig << tf_lds);
         tf_fold_off = alloc<uint64_t>(ctx, T);
         tf_big = alloc<uint32_t>(ctx, nbig);
         upload(ctx, tf_fold_off.p, h_foff.data(), T);

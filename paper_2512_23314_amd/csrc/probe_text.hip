@@ -46,9 +46,10 @@ template <bool ODD, bool LEAN>
 __global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(LEAN ? 4 : 8)))
 void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_chunks,
                   uint64_t* __restrict__ span_ctr, const uint64_t* __restrict__ span_info) {
+  constexpr uint32_t FL = text_filter_lds_log2(LEAN);
   extern __shared__ uint64_t s_lds[];
-  uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);  // up to 2^kTextFilterLdsLog2 words
-  uint64_t* q = s_lds + (1u << (kTextFilterLdsLog2 - 1)) + (uint64_t)(threadIdx.x >> 6) * kTlQueue;
+  uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);  // up to 2^FL words
+  uint64_t* q = s_lds + (1u << (FL - 1)) + (uint64_t)(threadIdx.x >> 6) * kTlQueue;
   const uint64_t span = span_chunks * kProbeTile;
   __shared__ uint64_t s_span, s_r0, s_r1;
   __shared__ uint32_t s_text;    // the span's text when its filter goes to LDS, else kNoText
@@ -318,8 +319,8 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
     span_r1 = s_r1;
     if (st != kNoText) {
       const uint32_t wl = tfl[st];
-      const bool big = wl > kTextFilterLdsLog2;
-      const uint32_t lwl = big ? kTextFilterLdsLog2 : wl;
+      const bool big = wl > FL;
+      const uint32_t lwl = big ? FL : wl;
       if (st != s_loaded) {
         // 2^lwl >= 8 words: whole 16-byte groups
         const uint64_t ng = (1ull << lwl) / 4;
@@ -390,8 +391,8 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
   }
   // two resident 1024-thread workgroups per CU (256 CUs)
   const unsigned grid = (unsigned)(spans < 512 ? (spans ? spans : 1) : 512);
-  const size_t lds = ((size_t)4 << kTextFilterLdsLog2) + (size_t)kTlWaves * kTlQueue * 8;
   const bool lean = a.P == nullptr;
+  const size_t lds = ((size_t)4 << text_filter_lds_log2(lean)) + (size_t)kTlWaves * kTlQueue * 8;
 #define BT_TL_LAUNCH(O, LN)                                                                 \
   do {                                                                                      \
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_probe_text<O, LN>), \
@@ -409,17 +410,20 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
 }
 
 // Word k of text big[b]'s folded filter: the OR of the 2^d full-filter words
-// k 2^d .. (k + 1) 2^d - 1, d = wl - kTextFilterLdsLog2.  A window's folded
-// word index is its full index shifted right by d (both take the top bits of
-// the same product), so the fold passes every window the full filter passes.
-__global__ void k_fold_filters(PhaseArgs a, const uint32_t* __restrict__ big, uint32_t nbig) {
-  const uint64_t per = 1ull << kTextFilterLdsLog2;
+// k 2^d .. (k + 1) 2^d - 1, d = wl - F (F = the scan's LDS filter size, log2
+// of its words; larger for lean builds, whose scan runs one workgroup per CU).
+// A window's folded word index is its full index shifted right by d (both
+// take the top bits of the same product), so the fold passes every window the
+// full filter passes.
+__global__ void k_fold_filters(PhaseArgs a, const uint32_t* __restrict__ big, uint32_t nbig,
+                               uint32_t F) {
+  const uint64_t per = 1ull << F;
   const uint64_t n = (uint64_t)nbig * per;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t t = big[i >> kTextFilterLdsLog2];
+    const uint32_t t = big[i >> F];
     const uint64_t k = i & (per - 1);
-    const uint32_t d = a.tf_wl[t] - kTextFilterLdsLog2;
+    const uint32_t d = a.tf_wl[t] - F;
     const uint32_t* src = a.tf_words + a.tf_off[t] + (k << d);
     uint32_t v = 0;
     for (uint64_t j = 0; j < (1ull << d); ++j) v |= src[j];
@@ -430,9 +434,10 @@ __global__ void k_fold_filters(PhaseArgs a, const uint32_t* __restrict__ big, ui
 hipError_t launch_fold_filters(const PhaseArgs& a, const uint32_t* big, uint32_t nbig,
                                hipStream_t s) {
   if (!nbig) return hipSuccess;
-  const uint64_t n = (uint64_t)nbig << kTextFilterLdsLog2;
+  const uint32_t F = text_filter_lds_log2(a.P == nullptr);
+  const uint64_t n = (uint64_t)nbig << F;
   const uint64_t g = (n + 255) / 256;
-  k_fold_filters<<<(unsigned)(g < 8192 ? g : 8192), 256, 0, s>>>(a, big, nbig);
+  k_fold_filters<<<(unsigned)(g < 8192 ? g : 8192), 256, 0, s>>>(a, big, nbig, F);
   return hipGetLastError();
 }
 
