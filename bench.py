@@ -325,8 +325,7 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
         return ctx.build_batch(d, offs, sigma=sigma, tau=tau, leaf_len=leaf)
 
     for _ in range(args.warmup):
-        for tr in batched():
-            tr.free()
+        bt.free_trees(batched())
     torch.cuda.synchronize()
     ctx.reset_stats()
     ctx.profile(True)
@@ -334,8 +333,7 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
     for k in range(args.steps):
         trees = batched()
         if k + 1 < args.steps:
-            for tr in trees:
-                tr.free()
+            bt.free_trees(trees)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(args.steps, 1)
     ctx.profile(False)
@@ -347,8 +345,7 @@ def bench_batch(args, sigma, tau, leaf, golden, desc):
         with open(args.launch_log, "w") as f:
             json.dump({"workload": "batch4096", "probe_scan": pl}, f)
     parity = check_batch(trees, golden, insha)
-    for tr in trees:
-        tr.free()
+    bt.free_trees(trees)
     log("batched %.1f ms (%.0f MB/s); parity: %d trees equal the expected ones" % (
         dt * 1e3, n / 1e6 / dt, parity["trees"]))
     plain = None
@@ -776,6 +773,7 @@ def batch_lean_leg(ctx, d, offs, n, sigma, tau, leaf, golden, insha, steps=2):
     one in 16): parity of every tree, rate, and peak pool bytes of one build
     against the dense build's."""
     import torch
+    import paper_2512_23314_amd as bt
 
     def build(lean):
         return ctx.build_batch(d, offs, sigma=sigma, tau=tau, leaf_len=leaf, lean=lean)
@@ -786,18 +784,15 @@ def batch_lean_leg(ctx, d, offs, n, sigma, tau, leaf, golden, insha, steps=2):
         ctx.reset_peak()
         trees = build(lean)
         p = ctx.memory()["peak"] - base
-        for tr in trees:
-            tr.free()
+        bt.free_trees(trees)
         return p
     trees = build(True)
     parity = check_batch(trees, golden, insha)
-    for tr in trees:
-        tr.free()
+    bt.free_trees(trees)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        for tr in build(True):
-            tr.free()
+        bt.free_trees(build(True))
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     dense, lean = peak(False), peak(True)

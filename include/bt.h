@@ -370,6 +370,9 @@ BT_API int bt_tree_device_bytes(const bt_tree* tree, uint64_t* bytes);
  * marked block and the block starts. */
 BT_API int bt_tree_rank_bytes(const bt_tree* tree, uint64_t* bytes);
 BT_API void bt_tree_free(bt_tree* tree);
+/* bt_tree_free of trees[0 .. n) (null entries are skipped): one call for the
+ * trees of a batch.  Errors: BT_E_INVAL (trees null with n > 0). */
+BT_API int bt_trees_free(bt_tree* const* trees, uint64_t n);
 BT_API const char* bt_strerror(int status);
 
 #ifdef __cplusplus

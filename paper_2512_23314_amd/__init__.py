@@ -141,6 +141,7 @@ SIGNATURES = {
     "bt_select": (_i32, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "bt_tree_device_bytes": (_i32, [_vp, _pu64]),
     "bt_tree_rank_bytes": (_i32, [_vp, _pu64]),
+    "bt_trees_free": (_i32, [_vp, _u64]),
     "bt_tree_free": (None, [_vp]),
     "bt_strerror": (ctypes.c_char_p, [_i32]),
 }
@@ -370,13 +371,40 @@ class Context:
         return [Tree(self, ctypes.c_void_p(outs[i])) for i in range(num)]
 
 
+def free_trees(trees):
+    """Free many trees with one call (bt_trees_free)."""
+    hs = [t.h for t in trees if t.h]
+    if hs:
+        arr = (ctypes.c_void_p * len(hs))(*[h.value for h in hs])
+        lib().bt_trees_free(arr, len(hs))
+    for t in trees:
+        t.h = None
+
+
 class Tree:
     def __init__(self, ctx, handle):
         self.ctx = ctx
         self.h = handle
-        n, hh, b1 = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
-        lib().bt_tree_info(self.h, ctypes.byref(n), ctypes.byref(hh), ctypes.byref(b1))
-        self.n, self.height, self.b1 = n.value, hh.value, b1.value
+        self._info = None
+
+    def _tree_info(self):
+        if self._info is None:
+            n, hh, b1 = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
+            lib().bt_tree_info(self.h, ctypes.byref(n), ctypes.byref(hh), ctypes.byref(b1))
+            self._info = (n.value, hh.value, b1.value)
+        return self._info
+
+    @property
+    def n(self):
+        return self._tree_info()[0]
+
+    @property
+    def height(self):
+        return self._tree_info()[1]
+
+    @property
+    def b1(self):
+        return self._tree_info()[2]
 
     def free(self):
         if self.h:

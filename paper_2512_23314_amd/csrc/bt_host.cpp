@@ -2112,6 +2112,12 @@ int bt_tree_rank_bytes(const bt_tree* t, uint64_t* bytes) {
 
 void bt_tree_free(bt_tree* t) { delete t; }
 
+int bt_trees_free(bt_tree* const* trees, uint64_t n) {
+  if (!trees && n) return BT_E_INVAL;
+  for (uint64_t i = 0; i < n; ++i) delete trees[i];
+  return BT_OK;
+}
+
 const char* bt_strerror(int status) {
   switch (status) {
     case BT_OK: return "ok";

@@ -1475,19 +1475,52 @@ hipError_t launch_pack_marks(const uint8_t* marked, uint32_t T, const uint64_t* 
 }
 
 // Leaf bytes: block j of the last level lands at j*b (texts' regions are
-// contiguous; only a text-final block is short, and it ends its region).
-__global__ void k_leaves(const uint8_t* T, LevelDev lv, TextsDev tx, uint8_t* out) {
-  GRID_STRIDE(j, lv.c) {
-    const uint64_t len = block_len(lv, tx, j);
-    const uint64_t st = lv.st[j];
-    for (uint64_t o = 0; o < len; ++o) out[j * lv.b + o] = T[st + o];
+// contiguous; only a text-final block is short, and it ends its region; the
+// bytes after its end are written as zeros).  Thread k writes output bytes
+// [16k, 16k + 16) with one 16-byte store (the last, partial chunk byte by
+// byte).  A chunk inside one block, with 24 bytes of the buffer after its
+// source, is read as three aligned 8-byte words; any other chunk byte by byte.
+__global__ void k_leaves(const uint8_t* __restrict__ T, LevelDev lv, TextsDev tx,
+                         uint8_t* __restrict__ out) {
+  const uint64_t total = lv.c * lv.b;
+  const uint64_t end = tx.tend[tx.T - 1];  // the buffer's end (texts are in order)
+  GRID_STRIDE(k, (total + 15) / 16) {
+    const uint64_t p = 16 * k;
+    uint64_t j = p / lv.b, r = p - j * lv.b;
+    uint64_t len = block_len(lv, tx, j), src = lv.st[j];
+    uint64_t lo = 0, hi = 0;
+    if (r + 16 <= len && src + r + 24 <= end) {
+      bytes16_at(T, end, src + r, lo, hi);
+    } else {
+      for (int e = 0; e < 16 && p + e < total; ++e) {
+        if (r == lv.b) {
+          ++j;
+          r = 0;
+          len = block_len(lv, tx, j);
+          src = lv.st[j];
+        }
+        const uint64_t v = r < len ? T[src + r] : 0;
+        (e < 8 ? lo : hi) |= v << (8 * (e & 7));
+        ++r;
+      }
+    }
+    if (p + 16 <= total) {
+      uint4 w;
+      w.x = (uint32_t)lo;
+      w.y = (uint32_t)(lo >> 32);
+      w.z = (uint32_t)hi;
+      w.w = (uint32_t)(hi >> 32);
+      *reinterpret_cast<uint4*>(out + p) = w;
+    } else {
+      for (uint64_t e = 0; p + e < total; ++e) out[p + e] = (uint8_t)((e < 8 ? lo : hi) >> (8 * (e & 7)));
+    }
   }
 }
 
 hipError_t launch_leaves(const uint8_t* T, const LevelDev& lv, const TextsDev& tx, uint8_t* out,
                          hipStream_t s) {
   if (!lv.c) return hipSuccess;
-  k_leaves<<<grid_for(lv.c, 256), 256, 0, s>>>(T, lv, tx, out);
+  k_leaves<<<grid_for((lv.c * lv.b + 15) / 16, 256), 256, 0, s>>>(T, lv, tx, out);
   return hipGetLastError();
 }
 

@@ -46,3 +46,10 @@ def test_ctx_create_ex_rejects_incomplete_allocator():
     h = ctypes.c_void_p()
     assert bt.lib().bt_ctx_create_ex(0, None, ctypes.byref(al), ctypes.byref(h)) == bt.BT_E_INVAL
     assert not h.value
+
+
+def test_trees_free_argument_checks():
+    """bt_trees_free: nothing to free is fine; a null array with a count is not."""
+    L = bt.lib()
+    assert L.bt_trees_free(None, 0) == bt.BT_OK
+    assert L.bt_trees_free(None, 3) == bt.BT_E_INVAL

@@ -124,6 +124,26 @@ def test_batch_on_reused_pool_memory(ctx):
             tr.free()
 
 
+def test_free_trees_returns_the_storage(ctx):
+    """free_trees (bt_trees_free) on a batch's trees: every tree is freed in one
+    call, and the pool holds no more in-use bytes than before the build."""
+    torch = torch_cuda()
+    import paper_2512_23314_amd as bt
+    texts = _texts(31, 40)
+    concat, offs = _concat(texts)
+    d = to_device(concat)
+    torch.cuda.synchronize()
+    base = ctx.memory()["in_use"]
+    trees = ctx.build_batch(d, offs, tau=4, leaf_len=16)
+    assert ctx.memory()["in_use"] > base
+    want = [oracle.build_tree(T, 4, 16).canonical for T in texts[:3]]
+    assert [tr.serialize() for tr in trees[:3]] == want
+    bt.free_trees(trees)
+    assert all(tr.h is None for tr in trees)
+    torch.cuda.synchronize()
+    assert ctx.memory()["in_use"] == base
+
+
 def test_batch_unqueued_scan(ctx):
     """The unqueued 61-bit scan on a batch with short final keys and salts."""
     import paper_2512_23314_amd as bt
