@@ -29,7 +29,7 @@ CANDIDATES = {
     "single-small": {"table_load_log2": [1, 2], "filter2_max_log2": [20, 22, 24]},
     "single-large": {"table_load_log2": [1, 2], "filter2_max_log2": [22, 24, 26]},
     "batch": {"table_load_log2": [1, 2], "text_filter_bits_log2": [4, 5, 6],
-              "span_chunks": [0, 32, 128]},
+              "span_chunks": [0, 32, 64, 128, 256]},
 }
 
 
@@ -69,7 +69,7 @@ def _samples():
     dev = "cuda:0"
     small = torch.from_numpy(synth.cfg1_text()).to(dev)
     large = torch.from_numpy(synth.cfg2_text()[:64 << 20]).to(dev)
-    texts = [synth.batch_text(i) for i in range(384)]
+    texts = [synth.batch_text(i) for i in range(2048)]
     offs = np.zeros(len(texts) + 1, np.uint64)
     offs[1:] = np.cumsum([t.size for t in texts])
     batch = torch.from_numpy(np.concatenate(texts)).to(dev)
@@ -79,7 +79,7 @@ def _samples():
         "single-large": (lambda ctx: ctx.build(large, sigma=96, tau=4, leaf_len=16, tuned=False),
                          "first 64 MiB of the versioned text, tau 4, leaf 16"),
         "batch": (lambda ctx: ctx.build_batch(batch, offs, sigma=4, tau=4, leaf_len=16, tuned=False),
-                  "the first 384 texts of the 4096-text batch (%.0f MiB), tau 4, leaf 16"
+                  "the first 2048 texts of the 4096-text batch (%.0f MiB), tau 4, leaf 16"
                   % (int(offs[-1]) / 2**20)),
     }
 

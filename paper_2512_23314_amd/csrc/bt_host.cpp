@@ -1112,7 +1112,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     if (has_salt && c && !(prm.debug_flags & (BT_DBG_SHARED_FILTERS | BT_DBG_SORT_PHASES))) {
       std::vector<uint64_t> h_off(T), h_foff(T, 0);
       std::vector<uint32_t> h_wl(T), h_big;
-      const uint32_t tf_lds = text_filter_lds_log2(lean);
+      const uint32_t tf_lds = kTextFilterLdsLog2;
       for (uint32_t t = 0; t < T; ++t) {
         uint32_t wl = 3;
         // 2^(bits_log2 - 5) words of 32 bits per block
@@ -1294,9 +1294,9 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         // counted only for the part beyond the tile.
         const double per_value = a.pre32 ? 4.0 : 8.0;
         const double partner = (double)std::min<uint64_t>(a.Lmain, kProbeTile) / (double)kProbeTile;
-        // spans: at least four per resident workgroup (512) for the level's
+        // spans: at least four per resident workgroup (256) for the level's
         // window bound, 16 to 256 chunks, a multiple of the 16 waves
-        uint64_t span_chunks = (c * b) / kProbeTile / (4 * 512);
+        uint64_t span_chunks = (c * b) / kProbeTile / (4 * 256);
         span_chunks = std::min<uint64_t>(256, std::max<uint64_t>(16, span_chunks & ~15ull));
         if (ctx->tune.span_chunks) span_chunks = ctx->tune.span_chunks;
         Buf<uint64_t> span_info;

@@ -149,8 +149,8 @@ struct PhaseArgs {
   const uint64_t* tf_off;  // [T]
   const uint32_t* tf_wl;   // [T], at least 3
   // For a text whose filter is larger than LDS (tf_wl[t] > F, F =
-  // text_filter_lds_log2 of the build): the same filter folded to 2^F words at
-  // tf_fold + tf_fold_off[t] (word k = OR of the 2^(wl - F) words
+  // kTextFilterLdsLog2): the same filter folded to 2^F words at tf_fold +
+  // tf_fold_off[t] (word k = OR of the 2^(wl - F) words
   // k 2^d .., a superset test: a window failing it fails the full filter).
   uint32_t* tf_fold;
   const uint64_t* tf_fold_off;  // [T] (read only for such texts)
@@ -280,9 +280,9 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
 hipError_t launch_fold_filters(const PhaseArgs& a, const uint32_t* big, uint32_t nbig,
                                hipStream_t s);
 // log2 of the 32-bit words of the largest text-local filter a span loads into
-// LDS: 64 KiB where two 1024-thread workgroups share a CU's LDS with their
-// queues (dense scans), 128 KiB where registers allow one (lean scans).
-constexpr uint32_t text_filter_lds_log2(bool lean) { return lean ? 15u : 14u; }
+// LDS: 128 KiB (the scan runs one 1024-thread workgroup per CU, which leaves
+// room for the filter and the queues in the CU's 160 KiB).
+constexpr uint32_t kTextFilterLdsLog2 = 15;
 
 struct VerifyBufs {
   uint32_t* vlist;  // [c]

@@ -450,10 +450,13 @@ __device__ __forceinline__ bool filter_has(const uint32_t* s_filt, uint64_t b1, 
 // segment (the usual case on long runs) takes a straight-line path that issues
 // eight windows' loads before using any of them.
 //
-// Two 1024-thread workgroups per CU need 8 waves per SIMD: the register budget
-// (SGPRs included) is held to that.
+// Instances without a short final key hold their registers (SGPRs included)
+// to two 1024-thread workgroups per CU, 8 waves per SIMD.  Instances with one
+// carry more live values (and load the short key's hashes with the main ones):
+// they run one workgroup per CU with up to 128 VGPRs, which measured faster
+// than spilling at 64.
 template <int MODE, bool ODD, bool SALT, bool PRE, bool LEAN>
-__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu((LEAN && ODD) ? 4 : 8)))
+__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(ODD ? 4 : 8)))
 void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   constexpr bool FILTER = MODE != 0;
   static_assert(!PRE || MODE == 1, "the 32-bit hash feeds the queued filter only");

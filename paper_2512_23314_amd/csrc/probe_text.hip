@@ -43,10 +43,10 @@ static_assert(64ull * kTlK == kProbeTile, "a chunk is one probe tile");
 static_assert(kLeanK == kTlK, "lean chunks are probe tiles too");
 
 template <bool ODD, bool LEAN>
-__global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(LEAN ? 4 : 8)))
+__global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_chunks,
                   uint64_t* __restrict__ span_ctr, const uint64_t* __restrict__ span_info) {
-  constexpr uint32_t FL = text_filter_lds_log2(LEAN);
+  constexpr uint32_t FL = kTextFilterLdsLog2;
   extern __shared__ uint64_t s_lds[];
   uint32_t* s_filt = reinterpret_cast<uint32_t*>(s_lds);  // up to 2^FL words
   uint64_t* q = s_lds + (1u << (FL - 1)) + (uint64_t)(threadIdx.x >> 6) * kTlQueue;
@@ -389,10 +389,11 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
     k_span_info<<<(unsigned)(g < 4096 ? (g ? g : 1) : 4096), 256, 0, s>>>(woff, a.lv.R, a.lv.rtext,
                                                                           span, spans, span_info);
   }
-  // two resident 1024-thread workgroups per CU (256 CUs)
-  const unsigned grid = (unsigned)(spans < 512 ? (spans ? spans : 1) : 512);
+  // one resident 1024-thread workgroup per CU (256 CUs): registers (up to 128
+  // VGPRs) and LDS (128 KiB of filter plus the queues) allow one
+  const unsigned grid = (unsigned)(spans < 256 ? (spans ? spans : 1) : 256);
   const bool lean = a.P == nullptr;
-  const size_t lds = ((size_t)4 << text_filter_lds_log2(lean)) + (size_t)kTlWaves * kTlQueue * 8;
+  const size_t lds = ((size_t)4 << kTextFilterLdsLog2) + (size_t)kTlWaves * kTlQueue * 8;
 #define BT_TL_LAUNCH(O, LN)                                                                 \
   do {                                                                                      \
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_probe_text<O, LN>), \
@@ -410,8 +411,7 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
 }
 
 // Word k of text big[b]'s folded filter: the OR of the 2^d full-filter words
-// k 2^d .. (k + 1) 2^d - 1, d = wl - F (F = the scan's LDS filter size, log2
-// of its words; larger for lean builds, whose scan runs one workgroup per CU).
+// k 2^d .. (k + 1) 2^d - 1, d = wl - F (F = kTextFilterLdsLog2).
 // A window's folded word index is its full index shifted right by d (both
 // take the top bits of the same product), so the fold passes every window the
 // full filter passes.
@@ -434,7 +434,7 @@ __global__ void k_fold_filters(PhaseArgs a, const uint32_t* __restrict__ big, ui
 hipError_t launch_fold_filters(const PhaseArgs& a, const uint32_t* big, uint32_t nbig,
                                hipStream_t s) {
   if (!nbig) return hipSuccess;
-  const uint32_t F = text_filter_lds_log2(a.P == nullptr);
+  const uint32_t F = kTextFilterLdsLog2;
   const uint64_t n = (uint64_t)nbig << F;
   const uint64_t g = (n + 255) / 256;
   k_fold_filters<<<(unsigned)(g < 8192 ? g : 8192), 256, 0, s>>>(a, big, nbig, F);
