@@ -34,6 +34,8 @@ namespace bt {
 constexpr int kTlThreads = 1024;
 constexpr uint32_t kTlWaves = kTlThreads / 64;
 constexpr int kTlK = 16;  // windows per lane per chunk
+// Windows per lane whose loads the dense fast path issues together.
+constexpr int kTlGroup = 16;
 // Queue entries per wave: at most 63 wait between flushes and a step adds at
 // most 63 more (indices up to 126), so 127 suffice; the byte this saves per
 // wave leaves room for the workgroup's shared words beside a 64 KiB filter.
@@ -203,29 +205,30 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
         const uint64_t i0 = rs + (w0 - wo);
         const uint32_t s32 = (uint32_t)salt;
 #pragma unroll
-        for (int k0 = 0; k0 < kTlK; k0 += 8) {
-          // the sixteen loads leave together: the scheduler would otherwise
-          // pair each load with its use and wait out every latency in turn
-          uint32_t ha[8], hb[8], hc[8];
+        for (int k0 = 0; k0 < kTlK; k0 += kTlGroup) {
+          // the group's loads (two per window, three with a short key) leave
+          // together: the scheduler would otherwise pair each load with its
+          // use and wait out every latency in turn
+          uint32_t ha[kTlGroup], hb[kTlGroup], hc[kTlGroup];
           // (and the short key's, H[i + oL], where the text has one)
           const bool oddk = ODD && oL;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
+          for (int k = 0; k < kTlGroup; ++k) {
             const uint64_t i = i0 + 64ull * (k0 + k);
             hb[k] = H[i + L];
             ha[k] = H[i];
             if (oddk) hc[k] = H[i + oL];
           }
           __builtin_amdgcn_sched_barrier(0);
-          uint32_t hv[8];
+          uint32_t hv[kTlGroup];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) hv[k] = hb[k] - ha[k] * x32L + s32;
+          for (int k = 0; k < kTlGroup; ++k) hv[k] = hb[k] - ha[k] * x32L + s32;
           if (oddk) {
             // the short key's 32-bit hashes (loaded with the others); the rare
             // matches form their 61-bit fingerprints one at a time
             uint32_t om = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < kTlGroup; ++k) {
               const uint64_t i = i0 + 64ull * (k0 + k);
               if (i < opos && hc[k] - ha[k] * ox + s32 == oh) om |= 1u << k;
             }
@@ -235,27 +238,27 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
               odd61(i0 + 64ull * (k0 + k), salt);
             }
           }
-          uint32_t wv[8];
+          uint32_t wv[kTlGroup];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) wv[k] = pass_word(hv[k]);
-          bool ok[8];
+          for (int k = 0; k < kTlGroup; ++k) wv[k] = pass_word(hv[k]);
+          bool ok[kTlGroup];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
+          for (int k = 0; k < kTlGroup; ++k) {
             const uint32_t m = tfilter_mask(hv[k]);
             ok[k] = (wv[k] & m) == m;
           }
           if (LDS && big) {
             // passed the folded filter: the full one, the loads issued together
 #pragma unroll
-            for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? tfw[toff + tfilter_word(hv[k], twl)] : 0u;
+            for (int k = 0; k < kTlGroup; ++k) wv[k] = ok[k] ? tfw[toff + tfilter_word(hv[k], twl)] : 0u;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < kTlGroup; ++k) {
               const uint32_t m = tfilter_mask(hv[k]);
               ok[k] = ok[k] && (wv[k] & m) == m;
             }
           }
 #pragma unroll
-          for (int k = 0; k < 8; ++k) push(ok[k], i0 + 64ull * (k0 + k), t);
+          for (int k = 0; k < kTlGroup; ++k) push(ok[k], i0 + 64ull * (k0 + k), t);
         }
         return;
       }
