@@ -638,6 +638,34 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, be
     print("wrote", out_md, out_json)
 
 
+def summarize_calibration(copy_fetch, copy_write, read_fetch, gather_fetch, mib, cmds, out_md):
+    """The FETCH_SIZE scale factor from three access patterns of known size: a
+    copy (stream in, stream out), a streaming read, and random 8-byte gathers
+    (a cache line fetched per row)."""
+    nb = int(mib) << 20
+    cf, _ = _counter_per_launch(copy_fetch, "copyBuffer")
+    cw, _ = _counter_per_launch(copy_write, "copyBuffer")
+    rf, _ = _counter_per_launch(read_fetch, "reduce")
+    gf, _ = _counter_per_launch(gather_fetch, "index")
+    rows = 1 << 24
+    lines = ["# FETCH_SIZE and WRITE_SIZE calibration on MI355X", "",
+             "Commands (repository root, one MI355X, each its own run):", ""]
+    lines += ["    " + c for c in cmds]
+    lines += ["", "| kernel | known bytes | counter, KiB per dispatch | known / counter |",
+              "|---|---:|---:|---:|",
+              "| copy of %d MiB, FETCH_SIZE | %d read | %.1f | %.4f |" % (mib, nb, cf, nb / (cf * 1024.0)),
+              "| copy of %d MiB, WRITE_SIZE | %d written | %.1f | %.4f |" % (mib, nb, cw, nb / (cw * 1024.0)),
+              "| streaming read of %d MiB, FETCH_SIZE | %d read | %.1f | %.4f |" % (
+                  mib, nb, rf, nb / (rf * 1024.0)),
+              "", "Random gathers: 2^24 rows of 8 bytes from %d MiB; the indices (8 B each) stream "
+              "in. With the copy's fetch factor, FETCH_SIZE gives %.1f bytes per row beyond the "
+              "indices (a row costs one cache line from HBM)." % (
+                  mib, (gf * 1024.0 * nb / (cf * 1024.0) - rows * 8) / rows)]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
 def bench_serve(args, sigma, tau, leaf, desc, seconds=10.0):
     """Open-loop serving: Poisson build arrivals at 0.8x the capacity measured by a
     closed-loop burst, 1M-query batches (a third each of access, rank, select)
@@ -956,6 +984,13 @@ def main():
                     help="write the probe-scan launches of the last timed step as JSON")
     ap.add_argument("--phase-log", metavar="FILE",
                     help="write the per-phase device counters of the last timed step as JSON lines")
+    ap.add_argument("--calibrate-read", type=int, default=0, metavar="MIB",
+                    help="run a streaming read of MIB MiB three times (traffic calibration)")
+    ap.add_argument("--calibrate-gather", type=int, default=0, metavar="MIB",
+                    help="gather 2^24 random 8-byte rows from MIB MiB three times (traffic calibration)")
+    ap.add_argument("--summarize-calibration", nargs=5,
+                    metavar=("COPY_FETCH", "COPY_WRITE", "READ_FETCH", "GATHER_FETCH", "MIB"),
+                    help="counter directories of the copy, read and gather runs, and their MiB")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
                          "known-size reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -979,6 +1014,8 @@ def main():
     if args.summarize_traffic:
         return summarize_traffic(*args.summarize_traffic, args.copy_mib, args.bench_json,
                                  args.profile_cmd, args.out[0], args.out[1])
+    if args.summarize_calibration:
+        return summarize_calibration(*args.summarize_calibration, args.profile_cmd, args.out[0])
     if args.summarize_launches:
         calib = (args.copy_mib,) + tuple(args.calib_dirs) if args.calib_dirs else None
         return summarize_launches(args.summarize_launches[0], args.summarize_launches[1:], calib,
@@ -992,6 +1029,31 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": nb, "launches": 3}))
+        return
+    if args.calibrate_read:
+        # a streaming read: the sum of MIB MiB of 64-bit words
+        import torch
+        nb = args.calibrate_read << 20
+        src = torch.ones(nb // 8, dtype=torch.int64, device="cuda:0")
+        for _ in range(3):
+            src.sum()
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_read_bytes": nb, "launches": 3}))
+        return
+    if args.calibrate_gather:
+        # random 8-byte gathers: 2^24 rows of 8 bytes from an array of MIB MiB
+        # (far beyond the caches), indices read as a stream, rows written as one
+        import torch
+        nb = args.calibrate_gather << 20
+        src = torch.ones(nb // 8, dtype=torch.int64, device="cuda:0")
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(7)
+        idx = torch.randint(0, nb // 8, (1 << 24,), device="cuda:0", generator=g)
+        for _ in range(3):
+            torch.index_select(src, 0, idx)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_gather_rows": 1 << 24, "row_bytes": 8, "array_bytes": nb,
+                          "launches": 3}))
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "

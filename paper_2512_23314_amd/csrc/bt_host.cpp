@@ -1300,7 +1300,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         span_chunks = std::min<uint64_t>(256, std::max<uint64_t>(16, span_chunks & ~15ull));
         if (ctx->tune.span_chunks) span_chunks = ctx->tune.span_chunks;
         Buf<uint64_t> span_info;
-        if (text_local) span_info = alloc<uint64_t>(ctx, 3 * probe_text_spans(c * b, span_chunks));
+        if (text_local) {
+          span_info = alloc<uint64_t>(ctx, 3 * probe_text_spans(c * b, span_chunks));
+          HIPCHK(ctx, launch_span_info(as, swoff, c * b, span_chunks, span_info.p, s));
+        }
         timed(ctx, "probe_scan", 0, 0, wst, per_value * (1.0 + partner), [&] {
           return text_local ? launch_probe_text(as, swoff, has_odd, c * b, span_chunks, span_ctr.p,
                                                 span_info.p, s)

@@ -269,13 +269,16 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
 // (zeroed by the caller); a window is tested against its own text's filter,
 // from LDS when the span lies in one text (its filter, or the folded filter of
 // a text whose filter does not fit, then the full one in global memory).
-// Needs pre32, text-local filters, salts.  span_info: 3 * probe_text_spans(...)
-// words of scratch, where a first kernel puts each span's first and last
-// segment and its text.
+// Needs pre32, text-local filters, salts, and span_info as launch_span_info
+// left it (same window bound and span length).
 uint64_t probe_text_spans(uint64_t max_windows, uint64_t span_chunks);
+// Each span's first and last segment and its text (or none), three words per
+// span into span_info (3 * probe_text_spans(...) words).
+hipError_t launch_span_info(const PhaseArgs& a, const uint64_t* woff, uint64_t max_windows,
+                            uint64_t span_chunks, uint64_t* span_info, hipStream_t s);
 hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
                              uint64_t max_windows, uint64_t span_chunks, uint64_t* span_ctr,
-                             uint64_t* span_info, hipStream_t s);
+                             const uint64_t* span_info, hipStream_t s);
 // Folds the filters of the nbig texts listed in big (see PhaseArgs.tf_fold).
 hipError_t launch_fold_filters(const PhaseArgs& a, const uint32_t* big, uint32_t nbig,
                                hipStream_t s);

@@ -380,18 +380,23 @@ uint64_t probe_text_spans(uint64_t max_windows, uint64_t span_chunks) {
   return (max_windows + span - 1) / span;
 }
 
+hipError_t launch_span_info(const PhaseArgs& a, const uint64_t* woff, uint64_t max_windows,
+                            uint64_t span_chunks, uint64_t* span_info, hipStream_t s) {
+  if (a.lv.R == 0) return hipSuccess;
+  if (span_chunks == 0 || !span_info) return hipErrorInvalidValue;
+  const uint64_t spans = probe_text_spans(max_windows, span_chunks);
+  const uint64_t g = (spans + 255) / 256;
+  k_span_info<<<(unsigned)(g < 4096 ? (g ? g : 1) : 4096), 256, 0, s>>>(
+      woff, a.lv.R, a.lv.rtext, span_chunks * kProbeTile, spans, span_info);
+  return hipGetLastError();
+}
+
 hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
                              uint64_t max_windows, uint64_t span_chunks, uint64_t* span_ctr,
-                             uint64_t* span_info, hipStream_t s) {
+                             const uint64_t* span_info, hipStream_t s) {
   if (a.lv.R == 0) return hipSuccess;
   if (!a.tf_words || !a.pre32 || span_chunks == 0 || !span_info) return hipErrorInvalidValue;
-  const uint64_t span = span_chunks * kProbeTile;
   const uint64_t spans = probe_text_spans(max_windows, span_chunks);
-  {
-    const uint64_t g = (spans + 255) / 256;
-    k_span_info<<<(unsigned)(g < 4096 ? (g ? g : 1) : 4096), 256, 0, s>>>(woff, a.lv.R, a.lv.rtext,
-                                                                          span, spans, span_info);
-  }
   // one resident 1024-thread workgroup per CU (256 CUs): registers (up to 128
   // VGPRs) and LDS (128 KiB of filter plus the queues) allow one
   const unsigned grid = (unsigned)(spans < 256 ? (spans ? spans : 1) : 256);
