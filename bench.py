@@ -645,8 +645,19 @@ def summarize_calibration(copy_fetch, copy_write, read_fetch, gather_fetch, mib,
     nb = int(mib) << 20
     cf, _ = _counter_per_launch(copy_fetch, "copyBuffer")
     cw, _ = _counter_per_launch(copy_write, "copyBuffer")
-    rf, _ = _counter_per_launch(read_fetch, "reduce")
-    gf, _ = _counter_per_launch(gather_fetch, "index")
+
+    def largest(d, needle):
+        # the main dispatch of a library operation (a reduction may add a small
+        # second pass): the largest per-dispatch value among those named so
+        per = {}
+        for r in _csv_rows(_find_csv(d, "counter_collection.csv")):
+            if needle in r["Kernel_Name"]:
+                per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        if not per:
+            raise ValueError("no %s dispatches in %s" % (needle, d))
+        return max(per.values())
+    rf = largest(read_fetch, "reduce")
+    gf = largest(gather_fetch, "ndex")
     rows = 1 << 24
     lines = ["# FETCH_SIZE and WRITE_SIZE calibration on MI355X", "",
              "Commands (repository root, one MI355X, each its own run):", ""]
@@ -657,10 +668,38 @@ def summarize_calibration(copy_fetch, copy_write, read_fetch, gather_fetch, mib,
               "| copy of %d MiB, WRITE_SIZE | %d written | %.1f | %.4f |" % (mib, nb, cw, nb / (cw * 1024.0)),
               "| streaming read of %d MiB, FETCH_SIZE | %d read | %.1f | %.4f |" % (
                   mib, nb, rf, nb / (rf * 1024.0)),
-              "", "Random gathers: 2^24 rows of 8 bytes from %d MiB; the indices (8 B each) stream "
-              "in. With the copy's fetch factor, FETCH_SIZE gives %.1f bytes per row beyond the "
+              "", "Random gathers: 2^24 rows of 8 bytes from an array far larger than the caches "
+              "(its size is in the command); the indices (8 B each) stream in.  FETCH_SIZE %.1f KiB "
+              "per dispatch; with the copy's fetch factor that is %.1f bytes per row beyond the "
               "indices (a row costs one cache line from HBM)." % (
-                  mib, (gf * 1024.0 * nb / (cf * 1024.0) - rows * 8) / rows)]
+                  gf, (gf * 1024.0 * nb / (cf * 1024.0) - rows * 8) / rows)]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
+def summarize_phases(jsonl, cmd, out_md):
+    """Markdown table of the per-phase device counters that --phase-log wrote
+    (one build; phases with keys only)."""
+    rows = [json.loads(line) for line in open(jsonl) if line.strip()]
+    wl = rows[0].get("workload", "?") if rows else "?"
+    lines = ["# Per-phase device counters, one %s build" % wl, "",
+             "Command (repository root, one MI355X):", "", "    " + cmd, "",
+             "From bt_ctx_phase_record (the JSON lines are in %s beside this file).  keys: keys "
+             "inserted (those the level above proved copies stay out); candidates: windows that "
+             "passed the filters and probed the table; verified: keys whose leftmost hit is not "
+             "their own start, compared byte by byte; collisions: verifications that failed, "
+             "resolved by the exact retry walk." % os.path.basename(jsonl), "",
+             "| b | phase | blocks | keys | windows | candidates | candidates / window | "
+             "candidates / key | verified | collisions |",
+             "|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        if not r["keys"]:
+            continue
+        lines.append("| %d | %d | %d | %d | %d | %d | %.4f | %.2f | %d | %d |" % (
+            r["b"], r["phase"], r["blocks"], r["keys"], r["windows"], r["candidates"],
+            r["candidates"] / max(r["windows"], 1), r["candidates"] / max(r["keys"], 1),
+            r["verified"], r["collisions"]))
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", out_md)
@@ -988,6 +1027,8 @@ def main():
                     help="run a streaming read of MIB MiB three times (traffic calibration)")
     ap.add_argument("--calibrate-gather", type=int, default=0, metavar="MIB",
                     help="gather 2^24 random 8-byte rows from MIB MiB three times (traffic calibration)")
+    ap.add_argument("--summarize-phases", metavar="JSONL",
+                    help="markdown table of the per-phase counters that --phase-log wrote")
     ap.add_argument("--summarize-calibration", nargs=5,
                     metavar=("COPY_FETCH", "COPY_WRITE", "READ_FETCH", "GATHER_FETCH", "MIB"),
                     help="counter directories of the copy, read and gather runs, and their MiB")
@@ -1014,6 +1055,8 @@ def main():
     if args.summarize_traffic:
         return summarize_traffic(*args.summarize_traffic, args.copy_mib, args.bench_json,
                                  args.profile_cmd, args.out[0], args.out[1])
+    if args.summarize_phases:
+        return summarize_phases(args.summarize_phases, args.profile_cmd[0], args.out[0])
     if args.summarize_calibration:
         return summarize_calibration(*args.summarize_calibration, args.profile_cmd, args.out[0])
     if args.summarize_launches:
