@@ -642,22 +642,22 @@ def summarize_calibration(copy_fetch, copy_write, read_fetch, gather_fetch, mib,
     """The FETCH_SIZE scale factor from three access patterns of known size: a
     copy (stream in, stream out), a streaming read, and random 8-byte gathers
     (a cache line fetched per row)."""
-    nb = int(mib) << 20
+    mib = int(mib)
+    nb = mib << 20
     cf, _ = _counter_per_launch(copy_fetch, "copyBuffer")
     cw, _ = _counter_per_launch(copy_write, "copyBuffer")
 
-    def largest(d, needle):
-        # the main dispatch of a library operation (a reduction may add a small
-        # second pass): the largest per-dispatch value among those named so
+    def largest(d):
+        # the run's main dispatch: the fills that make its inputs only write, and
+        # a reduction's second pass is small, so it is the one that fetches most
         per = {}
         for r in _csv_rows(_find_csv(d, "counter_collection.csv")):
-            if needle in r["Kernel_Name"]:
-                per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+            per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
         if not per:
-            raise ValueError("no %s dispatches in %s" % (needle, d))
+            raise ValueError("no dispatches in %s" % d)
         return max(per.values())
-    rf = largest(read_fetch, "reduce")
-    gf = largest(gather_fetch, "ndex")
+    rf = largest(read_fetch)
+    gf = largest(gather_fetch)
     rows = 1 << 24
     lines = ["# FETCH_SIZE and WRITE_SIZE calibration on MI355X", "",
              "Commands (repository root, one MI355X, each its own run):", ""]

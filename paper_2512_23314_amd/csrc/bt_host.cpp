@@ -1039,7 +1039,6 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
 
     const uint64_t cap = std::max<uint64_t>(1024, pow2_at_least(c << ctx->tune.table_load_log2));
     Buf<Slot> tab = alloc<Slot>(ctx, cap);
-    Buf<uint64_t> tags = alloc<uint64_t>(ctx, cap / 8);
     Buf<uint64_t> kfp = alloc<uint64_t>(ctx, c), klen = alloc<uint64_t>(ctx, c),
                   klm = alloc<uint64_t>(ctx, c);
     Buf<uint32_t> kslot = alloc<uint32_t>(ctx, c);
@@ -1077,7 +1076,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     a.odd = OddDev{oddb.p,         oddb.p + T,     oddb.p + 2 * T, oddb.p + 3 * T,
                    oddb.p + 4 * T, oddb.p + 5 * T, oddb.p + 6 * T};
     a.x32 = x32;
-    a.tab = TableDev{tab.p, cap - 1, reinterpret_cast<uint8_t*>(tags.p)};
+    a.tab = TableDev{tab.p, cap - 1};
     a.x = x;
     a.fpmask = fpmask;
     a.marked = marked.p;
@@ -1158,8 +1157,8 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       // about 32 bits per key (at most 2^24 bits, L2-resident; beyond 2^19
       // keys it is what rejects most windows).  Queue entries pack a position
       // below 2^40 and a text below 2^24; past that, a 2^19-bit filter on
-      // 61-bit fingerprints without queues (mode 2), where the table's tag
-      // bytes are the second test.
+      // 61-bit fingerprints without queues (mode 2), whose passes probe the
+      // table at once.
       fbits = 12;
       while (fbits < 19 && (1ull << fbits) < 32 * nkeys) ++fbits;
       uint32_t f2words = 0;
@@ -1216,7 +1215,6 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
       {
         FillList f;
         f.add(tab.p, 4 * cap, ~0u);  // empty slots: fp = best = ~0
-        f.add(tags.p, cap / 4, 0);
         f.add(oddb.p, 14 * (uint64_t)T, 0);
         f.add(vcnt.p, 4, 0);
         f.add(filt.p, (1ull << (byte_scan ? bbits : fbits)) / 32, 0);

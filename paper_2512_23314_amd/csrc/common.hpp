@@ -70,14 +70,6 @@ __device__ __forceinline__ uint64_t slot_of(uint64_t fp, uint64_t mask) {
   return (fp ^ (fp >> 29) ^ (fp >> 47)) & mask;
 }
 
-// Tag byte of a fingerprint in the table's tag array (never 0, which marks an
-// empty slot); taken from the top byte of a multiplicative mix so that it is
-// independent of the slot index.
-__device__ __forceinline__ uint32_t tag_of(uint64_t fp) {
-  const uint32_t t = (uint32_t)((fp * 0x9E3779B97F4A7C15ull) >> 56);
-  return t ? t : 1u;
-}
-
 // The two bits of a fingerprint in a key filter of 2^bits bits.
 __device__ __forceinline__ uint64_t filter_bit(uint64_t fp, uint32_t bits) {
   return (fp ^ (fp >> 31)) & ((1ull << bits) - 1);

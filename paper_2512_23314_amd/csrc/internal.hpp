@@ -87,13 +87,10 @@ struct Slot {
   uint64_t best;  // smallest position with this fingerprint seen so far
 };
 
-// Slots plus one tag byte per slot (0 = empty, else tag_of(fp) of the slot's
-// key): lookups scan the small tag array eight slots per load and touch a slot
-// only where its tag matches.
+// Open addressing with linear probing; an empty slot has fp = kEmpty.
 struct TableDev {
   Slot* slots;
   uint64_t mask;  // capacity - 1 (capacity a power of two, at least 1024)
-  uint8_t* tag;   // capacity bytes, 8-byte aligned
 };
 
 struct PhaseArgs {

@@ -115,7 +115,6 @@ __global__ void k_keys(PhaseArgs a) {
         h = (h + 1) & a.tab.mask;
       }
       a.k.slot[j] = (uint32_t)h;
-      a.tab.tag[h] = (uint8_t)tag_of(fp);  // every key of the slot writes the same byte
       atomicMin((unsigned long long*)&a.tab.slots[h].best, (unsigned long long)st);
       if (a.tf_words) {
         // text-local filter: this text's keys only
@@ -487,7 +486,6 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
   const uint32_t x32L = a.x32L;
   Slot* __restrict__ slots = a.tab.slots;
-  const uint8_t* __restrict__ tags = a.tab.tag;
   const uint64_t mask = a.tab.mask;
 
   const auto fp61 = [&](uint64_t i, uint64_t salt) {
@@ -513,7 +511,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   const auto probe_entry = [&](uint64_t e) {
     const uint64_t i = e & kQPosMask;
     const uint64_t salt = SALT ? a.tx.tsalt[e >> kQPosBits] : 0;
-    probe(slots, tags, mask, fp61(i, salt), i);
+    probe(slots, mask, fp61(i, salt), i);
   };
   // whole wave: append the lanes' candidates; probe 64 once 64 are waiting
   uint64_t ncand = 0;  // wave-uniform: windows that passed the filters
@@ -661,7 +659,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
                 push(cand, i, t);
               } else {
                 ncand += (uint64_t)__popcll(__ballot(cand));
-                if (cand) probe(slots, tags, mask, fv[k], i);
+                if (cand) probe(slots, mask, fv[k], i);
               }
             }
           }
@@ -694,7 +692,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         } else {
           const uint64_t f = fp61(i, salt);
           cand = FILTER ? pass61(f) : true;
-          if (MODE != 1 && cand) probe(slots, tags, mask, f, i);
+          if (MODE != 1 && cand) probe(slots, mask, f, i);
         }
       }
       if (MODE == 1) push(cand, i, t);
@@ -818,7 +816,6 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   const uint64_t* __restrict__ P = a.P;
   const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
   Slot* __restrict__ slots = a.tab.slots;
-  const uint8_t* __restrict__ tags = a.tab.tag;
   const uint64_t mask = a.tab.mask;
   const auto has = [&](uint32_t lo, uint32_t hi) {
     const uint32_t b = prefix8_bit(lo, hi, bits);
@@ -835,7 +832,7 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     if (!(e >> 63)) {
       uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
       if (SALT) f = add61(f, salt);
-      probe(slots, tags, mask, f & fmask, i);
+      probe(slots, mask, f & fmask, i);
     }
     if (ODD) {
       const uint64_t oL = a.odd.L[t];

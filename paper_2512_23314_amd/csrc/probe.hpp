@@ -6,35 +6,22 @@
 
 namespace bt {
 
-// Linear probing over the tag array, one aligned group of eight tags per load:
-// the slots from the home slot up to the first empty one are exactly those a
-// key with this fingerprint could occupy; only those whose tag matches are read.
-__device__ __forceinline__ void probe(Slot* __restrict__ slots, const uint8_t* __restrict__ tags,
-                                      uint64_t mask, uint64_t fp, uint64_t i) {
-  constexpr uint64_t kLo7 = 0x7F7F7F7F7F7F7F7Full;
-  const uint64_t h = slot_of(fp, mask);
-  const uint64_t tb = 0x0101010101010101ull * tag_of(fp);
-  uint64_t g = h >> 3;
-  uint64_t valid = ~0ull << (8 * (h & 7));  // bytes at or after the home slot
+// Linear probing from the home slot: the slots up to the first empty one are
+// exactly those a key with this fingerprint could occupy.  A slot is 16 bytes
+// and eight share a 128-byte line, so a probe that ends near its home slot (the
+// usual case at the table's load) reads one line.  Most probes at the deep
+// levels, where probes are most numerous, hit a key.
+__device__ __forceinline__ void probe(Slot* __restrict__ slots, uint64_t mask, uint64_t fp,
+                                      uint64_t i) {
+  uint64_t h = slot_of(fp, mask);
   while (true) {
-    const uint64_t w = *reinterpret_cast<const uint64_t*>(tags + 8 * g);
-    // bit 8k+7 set exactly where byte k is zero (empty) / equals the tag
-    const uint64_t emp = ~(((w & kLo7) + kLo7) | w | kLo7) & valid;
-    const uint64_t x = w ^ tb;
-    uint64_t mat = ~(((x & kLo7) + kLo7) | x | kLo7) & valid;
-    if (emp) mat &= (emp & (0 - emp)) - 1;  // matches before the first empty slot
-    while (mat) {
-      const uint64_t j = 8 * g + (__builtin_ctzll(mat) >> 3);
-      const Slot s = slots[j];
-      if (s.fp == fp) {
-        if (i < s.best) atomicMin((unsigned long long*)&slots[j].best, (unsigned long long)i);
-        return;
-      }
-      mat &= mat - 1;
+    const Slot s = slots[h];
+    if (s.fp == fp) {
+      if (i < s.best) atomicMin((unsigned long long*)&slots[h].best, (unsigned long long)i);
+      return;
     }
-    if (emp) return;
-    g = (g + 1) & (mask >> 3);
-    valid = ~0ull;
+    if (s.fp == kEmpty) return;
+    h = (h + 1) & mask;
   }
 }
 

@@ -70,7 +70,6 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
   const uint64_t L = a.Lmain, xL = a.xLmain, fmask = a.fpmask;
   const uint32_t x32L = a.x32L;
   Slot* __restrict__ slots = a.tab.slots;
-  const uint8_t* __restrict__ tags = a.tab.tag;
   const uint64_t mask = a.tab.mask;
   const uint32_t* __restrict__ tfw = a.tf_words;
   const uint64_t* __restrict__ tfo = a.tf_off;
@@ -85,7 +84,7 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
   // the entry this lane holds: form its fingerprint and probe
   const auto probe_entry = [&](uint64_t e) {
     const uint64_t i = e & kQPosMask;
-    probe(slots, tags, mask, fp61(i, a.tx.tsalt[e >> kQPosBits]), i);
+    probe(slots, mask, fp61(i, a.tx.tsalt[e >> kQPosBits]), i);
   };
   // whole wave: append the lanes' candidates; probe 64 once 64 are waiting
   uint64_t ncand = 0;  // wave-uniform: windows that passed the filters
