@@ -695,19 +695,22 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
   // candidates and retries.  Only the queued scan takes candidates that way.
   // It samples the 32-bit hashes too (0.25 instead of 4 bytes per text byte):
   // the scans roll them along consecutive windows.
-  const bool lean = (prm.flags & BT_LEAN) && T <= (1u << 24) && offs[T] < (1ull << 40) &&
-                    !(prm.debug_flags & BT_DBG_NO_QUEUE);
+  const bool can_sample = T <= (1u << 24) && offs[T] < (1ull << 40) &&
+                          !(prm.debug_flags & BT_DBG_NO_QUEUE);
+  const bool lean = (prm.flags & BT_LEAN) && can_sample;  // both kinds sampled
+  const bool sample_p = lean;  // the fingerprints sampled
   const uint32_t x32 = base32_from_seed(prm.hash_seed);
-  Buf<uint64_t> d_P = alloc<uint64_t>(ctx, lean ? N / 16 + 1 : N + 1);
-  Buf<uint32_t> d_H = alloc<uint32_t>(ctx, lean ? N / 16 + 1 : N + 1);
+  const uint64_t np = sample_p ? N / 16 + 1 : N + 1, nh = lean ? N / 16 + 1 : N + 1;
+  Buf<uint64_t> d_P = alloc<uint64_t>(ctx, np);
+  Buf<uint32_t> d_H = alloc<uint32_t>(ctx, nh);
   Buf<PfTab> d_tab = alloc<PfTab>(ctx, 1);
   fill_tab(ctx->h_tab, x, x32);
   HIPCHK(ctx, hipMemcpyAsync(d_tab.p, ctx->h_tab, sizeof(PfTab), hipMemcpyHostToDevice, s));
   Buf<uint64_t> d_status = alloc<uint64_t>(ctx, prefix_status_words(N));
-  timed(ctx, "prefix_fp", (double)N + 12.0 * (double)(lean ? N / 16 + 1 : N + 1), (double)N, nullptr, 0,
-        [&] { return launch_prefix(d_base + o0, N, d_P.p, lean, d_H.p, d_tab.p, d_status.p, s, lean); });
+  timed(ctx, "prefix_fp", (double)N + 8.0 * (double)np + 4.0 * (double)nh, (double)N, nullptr, 0,
+        [&] { return launch_prefix(d_base + o0, N, d_P.p, sample_p, d_H.p, d_tab.p, d_status.p, s, lean); });
   // P[i] belongs to text position i (never read below o0); null when sampled
-  const uint64_t* P = lean ? nullptr : d_P.p - o0;
+  const uint64_t* P = sample_p ? nullptr : d_P.p - o0;
 
   // ---- distinct byte values must not exceed sigma; dense symbols for rank/select
   std::vector<uint64_t> seen;
@@ -1064,7 +1067,7 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
     PhaseArgs a{};
     a.T = d_base;
     a.P = P;
-    a.Ps = lean ? d_P.p : nullptr;
+    a.Ps = sample_p ? d_P.p : nullptr;
     a.pbase = o0;
     a.pend = offs[T];
     a.P32 = H32;

@@ -447,7 +447,12 @@ __device__ __forceinline__ bool filter_has(const uint32_t* s_filt, uint64_t b1, 
 //
 // A chunk in which every lane's 16 windows lie inside that lane's current
 // segment (the usual case on long runs) takes a straight-line path that issues
-// eight windows' loads before using any of them.
+// eight windows' hash loads together, before using any of them.
+//
+// LEAN: the 32-bit hashes are sampled (memory-lean builds) and lanes roll them
+// along consecutive windows (lean.hpp).  Queued windows form their 61-bit
+// fingerprints from dense prefix fingerprints when the build keeps them, else
+// from the samples.
 //
 // Instances without a short final key hold their registers (SGPRs included)
 // to two 1024-thread workgroups per CU, 8 waves per SIMD.  Instances with one
@@ -489,7 +494,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
   const uint64_t mask = a.tab.mask;
 
   const auto fp61 = [&](uint64_t i, uint64_t salt) {
-    uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
+    uint64_t f = P ? sub61(P[i + L], mul61(P[i], xL)) : win61<true>(a, i, L, xL);
     if (SALT) f = add61(f, salt);
     return f & fmask;
   };
@@ -583,7 +588,7 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     if (ODD && w0 < W) load_odd();
     // the short key's 61-bit fingerprint at i, against the key's (text t)
     const auto odd61 = [&](uint64_t i, uint64_t sl) {
-      uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+      uint64_t g = P ? sub61(P[i + oL], mul61(P[i], a.odd.xp[t])) : win61<true>(a, i, oL, a.odd.xp[t]);
       if (SALT) g = add61(g, sl);
       if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
         atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
@@ -742,8 +747,10 @@ hipError_t launch_probe_scan(const PhaseArgs& a, const uint64_t* woff, bool has_
   } while (0)
 #define BT_PROBE_SALT(M, O, Q, LN) \
   if (has_salt) BT_PROBE_LAUNCH(M, O, true, Q, LN); else BT_PROBE_LAUNCH(M, O, false, Q, LN);
-  const bool lean = a.P == nullptr;
-  if (lean && mode != 1) return hipErrorInvalidValue;  // sampled prefixes need the queue
+  // sampled fingerprints serve queued candidates only; sampled 32-bit hashes
+  // take the rolled window loop (the LEAN instances)
+  if (a.P == nullptr && mode != 1) return hipErrorInvalidValue;
+  const bool lean = a.P32 == nullptr;
   if (mode == 1) {
     if (!pre) return hipErrorInvalidValue;  // queued scans always pre-filter
     if (lean) {
@@ -830,14 +837,14 @@ void k_byte_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
     const uint32_t t = (uint32_t)((e >> kQPosBits) & kByteTextMask);  // bit 63 is the fit bit
     const uint64_t salt = SALT ? a.tx.tsalt[t] : 0;
     if (!(e >> 63)) {
-      uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
+      uint64_t f = P ? sub61(P[i + L], mul61(P[i], xL)) : win61<true>(a, i, L, xL);
       if (SALT) f = add61(f, salt);
       probe(slots, mask, f & fmask, i);
     }
     if (ODD) {
       const uint64_t oL = a.odd.L[t];
       if (oL && i + oL <= a.tx.tend[t] && i < a.odd.pos[t]) {
-        uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+        uint64_t g = P ? sub61(P[i + oL], mul61(P[i], a.odd.xp[t])) : win61<true>(a, i, oL, a.odd.xp[t]);
         if (SALT) g = add61(g, salt);
         if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
           atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);

@@ -78,7 +78,7 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
   uint64_t span_r0 = 0, span_r1 = 0;
 
   const auto fp61 = [&](uint64_t i, uint64_t salt) {
-    const uint64_t f = LEAN ? win61<true>(a, i, L, xL) : sub61(P[i + L], mul61(P[i], xL));
+    const uint64_t f = P ? sub61(P[i + L], mul61(P[i], xL)) : win61<true>(a, i, L, xL);
     return add61(f, salt) & fmask;
   };
   // the entry this lane holds: form its fingerprint and probe
@@ -190,7 +190,7 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
     if (ODD && w0 < W) load_odd();
     // the short key's 61-bit fingerprint at i, against the key's (text t)
     const auto odd61 = [&](uint64_t i, uint64_t sl) {
-      uint64_t g = LEAN ? win61<true>(a, i, oL, a.odd.xp[t]) : sub61(P[i + oL], mul61(P[i], a.odd.xp[t]));
+      uint64_t g = P ? sub61(P[i + oL], mul61(P[i], a.odd.xp[t])) : win61<true>(a, i, oL, a.odd.xp[t]);
       g = add61(g, sl);
       if ((g & fmask) == a.odd.fp[t] && i < a.odd.best[t])
         atomicMin((unsigned long long*)&a.odd.best[t], (unsigned long long)i);
@@ -399,7 +399,7 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
   // one resident 1024-thread workgroup per CU (256 CUs): registers (up to 128
   // VGPRs) and LDS (128 KiB of filter plus the queues) allow one
   const unsigned grid = (unsigned)(spans < 256 ? (spans ? spans : 1) : 256);
-  const bool lean = a.P == nullptr;
+  const bool lean = a.P32 == nullptr;  // sampled 32-bit hashes: the rolled window loop
   const size_t lds = ((size_t)4 << kTextFilterLdsLog2) + (size_t)kTlWaves * kTlQueue * 8;
 #define BT_TL_LAUNCH(O, LN)                                                                 \
   do {                                                                                      \
