@@ -372,7 +372,8 @@ class Context:
 
 
 def free_trees(trees):
-    """Free many trees with one call (bt_trees_free)."""
+    """Free many trees with one call (bt_trees_free).  A tree's n, height and b1
+    stay readable only if they were read before."""
     hs = [t.h for t in trees if t.h]
     if hs:
         arr = (ctypes.c_void_p * len(hs))(*[h.value for h in hs])
@@ -389,10 +390,17 @@ class Tree:
 
     def _tree_info(self):
         if self._info is None:
+            if not self.h:
+                raise BtError(BT_E_INVAL, "tree freed (by free_trees) before its size was read")
             n, hh, b1 = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
-            lib().bt_tree_info(self.h, ctypes.byref(n), ctypes.byref(hh), ctypes.byref(b1))
+            self._check_rc(lib().bt_tree_info(self.h, ctypes.byref(n), ctypes.byref(hh), ctypes.byref(b1)))
             self._info = (n.value, hh.value, b1.value)
         return self._info
+
+    @staticmethod
+    def _check_rc(rc):
+        if rc != 0:
+            raise BtError(rc, "bt_tree_info")
 
     @property
     def n(self):
@@ -407,7 +415,9 @@ class Tree:
         return self._tree_info()[2]
 
     def free(self):
+        """Free the tree's device memory; its n, height and b1 stay readable."""
         if self.h:
+            self._tree_info()
             lib().bt_tree_free(self.h)
             self.h = None
 

@@ -138,10 +138,21 @@ def test_free_trees_returns_the_storage(ctx):
     assert ctx.memory()["in_use"] > base
     want = [oracle.build_tree(T, 4, 16).canonical for T in texts[:3]]
     assert [tr.serialize() for tr in trees[:3]] == want
+    h0 = trees[0].height  # read before the batch free: stays readable
     bt.free_trees(trees)
     assert all(tr.h is None for tr in trees)
+    assert trees[0].height == h0
+    with pytest.raises(bt.BtError):
+        trees[1].height  # never read before the free
     torch.cuda.synchronize()
     assert ctx.memory()["in_use"] == base
+    # a single tree's size stays readable after tree.free()
+    one = ctx.build(to_device(texts[0]), tau=4, leaf_len=16)
+    n, h, b1 = one.n, one.height, one.b1
+    one2 = ctx.build(to_device(texts[0]), tau=4, leaf_len=16)
+    one2.free()
+    assert (one2.n, one2.height, one2.b1) == (n, h, b1)
+    one.free()
 
 
 def test_batch_unqueued_scan(ctx):
