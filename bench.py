@@ -678,6 +678,29 @@ def summarize_calibration(copy_fetch, copy_write, read_fetch, gather_fetch, mib,
     print("wrote", out_md)
 
 
+def summarize_sweep(bench_json, cmd, out_md):
+    """Markdown table of a --workload dna2g_sweep line."""
+    b = _bench_line(bench_json)
+    lines = ["# 2 GiB DNA collection: the tau x leaf_len sweep", "",
+             "Command (repository root, one MI355X):", "", "    " + cmd, "",
+             "Each point's tree was first compared with its expected tree "
+             "(tests/golden/fullsize_trees.json, written by the threaded oracle construction): "
+             "all twelve equal.  Then 1 warm-up and %d timed builds per point, text resident in HBM; "
+             "probe-scan fraction = algorithmic bytes (same-tile rule) over HIP-event time, against "
+             "8 TB/s." % b["steps"], "",
+             "| tau | leaf | levels | ms per build | MB/s | probe scan ms | probe scan frac | "
+             "tree SHA-256 (first 16) |", "|---:|---:|---:|---:|---:|---:|---:|---|"]
+    for r in b["sweep"]:
+        lines.append("| %d | %d | %d | %.1f | %.0f | %.1f | %.3f | %s |" % (
+            r["tau"], r["leaf_len"], r["levels"], r["ms_per_build"], r["mb_s"], r["probe_scan_ms"],
+            r["probe_scan_frac"], r["tree_sha256"]))
+    lines += ["", "All twelve builds: %.0f MB/s (%.1f ms per build on average)." % (
+        b["value"], b["ms_per_step"])]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
 def summarize_phases(jsonl, cmd, out_md):
     """Markdown table of the per-phase device counters that --phase-log wrote
     (one build; phases with keys only)."""
@@ -1027,6 +1050,8 @@ def main():
                     help="run a streaming read of MIB MiB three times (traffic calibration)")
     ap.add_argument("--calibrate-gather", type=int, default=0, metavar="MIB",
                     help="gather 2^24 random 8-byte rows from MIB MiB three times (traffic calibration)")
+    ap.add_argument("--summarize-sweep", metavar="BENCH_JSON",
+                    help="markdown table of a --workload dna2g_sweep run's JSON line")
     ap.add_argument("--summarize-phases", metavar="JSONL",
                     help="markdown table of the per-phase counters that --phase-log wrote")
     ap.add_argument("--summarize-calibration", nargs=5,
@@ -1055,6 +1080,8 @@ def main():
     if args.summarize_traffic:
         return summarize_traffic(*args.summarize_traffic, args.copy_mib, args.bench_json,
                                  args.profile_cmd, args.out[0], args.out[1])
+    if args.summarize_sweep:
+        return summarize_sweep(args.summarize_sweep, args.profile_cmd[0], args.out[0])
     if args.summarize_phases:
         return summarize_phases(args.summarize_phases, args.profile_cmd[0], args.out[0])
     if args.summarize_calibration:
