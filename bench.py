@@ -173,7 +173,7 @@ def traffic_record(kernel, workload):
 # the files the probe scan is compiled from, and the host code that sizes its
 # launches; a change to any of them retires the traffic record
 PROBE_SOURCES = ["level.hip", "probe_text.hip", "probe.hpp", "common.hpp", "window.hpp",
-                 "internal.hpp", "bt_host.cpp"]
+                 "lean.hpp", "internal.hpp", "bt_host.cpp"]
 
 
 def _sources_sha(names):
