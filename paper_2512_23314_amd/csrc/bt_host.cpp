@@ -1242,6 +1242,17 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
         as.lv.rs = seg_ws.p;
         as.lv.re = seg_re.p;
         as.lv.rtext = seg_text.p;
+        if (E_ent && E_ent <= c) {
+          // entries whose starts continue the previous entry's join its
+          // segment (phase 2's segment arrays are free until then)
+          HIPCHK(ctx, launch_seg_heads(sg, woff.p, bhd.p, s));
+          scan(bhd.p, E_ent);
+          HIPCHK(ctx, launch_seg_merge(sg, woff.p, bhd.p, bws.p, bre.p, btext.p, bwoff.p, s));
+          swoff = bwoff.p;
+          as.lv.rs = bws.p;
+          as.lv.re = bre.p;
+          as.lv.rtext = btext.p;
+        }
       } else {
         HIPCHK(ctx, launch_block_seg_counts(a, facts.p, bwc.p, bhd.p, s));
         scan(bwc.p, c);

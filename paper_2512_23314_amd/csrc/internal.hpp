@@ -233,6 +233,12 @@ hipError_t launch_child_flags(const SegDev& sg, uint64_t b, const uint64_t* echi
                               hipStream_t s);
 // Per-segment window counts into woff[0..E) (then scanned by the caller).
 hipError_t launch_segments(const PhaseArgs& a, const SegDev& sg, uint64_t* woff, hipStream_t s);
+// Phase-1 segments merged where one entry's window starts continue the previous
+// entry's (see level.hip): head[0..E) then scanned by the caller (total at E),
+// then the merged arrays, E of them (E + 1 offsets), padded past the last.
+hipError_t launch_seg_heads(const SegDev& sg, const uint64_t* woff, uint64_t* head, hipStream_t s);
+hipError_t launch_seg_merge(const SegDev& sg, const uint64_t* woff, const uint64_t* hs, uint64_t* ws,
+                            uint64_t* sre, uint32_t* stext, uint64_t* woff2, hipStream_t s);
 // Phase-2 segments from this level's pair facts (bit 0 of pf); see level.hip.
 hipError_t launch_block_seg_counts(const PhaseArgs& a, const uint8_t* pf, uint64_t* wc,
                                    uint64_t* head, hipStream_t s);

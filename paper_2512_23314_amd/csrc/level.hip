@@ -407,6 +407,62 @@ hipError_t launch_block_segments(const PhaseArgs& a, const uint64_t* wcs, const 
   return hipGetLastError();
 }
 
+// Phase-1 segments are one per entry (a parent, at most tau b window starts),
+// so at the lower levels a tile of the scan would cross several of them.  An
+// entry whose starts continue those of the previous entry (same run, first
+// start one past the previous entry's last: adjacent parents that no fact cut
+// apart) joins its segment.  Window numbers and positions stay the same; only
+// the boundaries the scan has to walk go.
+//   k_seg_heads: head[k] = 1 where entry k opens a merged segment (woff: the
+//   scanned window counts, total at E);
+//   k_seg_merge: merged segment g from the entry that opens it; entries S..E
+//   repeat the window total (and name text 0), as the scan expects E of them.
+__global__ void k_seg_heads(SegDev sg, const uint64_t* woff, uint64_t* head) {
+  GRID_STRIDE(k, sg.E) {
+    const uint64_t cnt = woff[k + 1] - woff[k];
+    bool h = cnt != 0;
+    if (h && k > 0) {
+      const uint64_t pc = woff[k] - woff[k - 1];
+      if (pc && sg.erun[k - 1] == sg.erun[k] && sg.ws[k - 1] + pc == sg.ws[k]) h = false;
+    }
+    head[k] = h ? 1 : 0;
+  }
+}
+
+__global__ void k_seg_merge(SegDev sg, const uint64_t* woff, const uint64_t* hs, uint64_t* ws,
+                            uint64_t* sre, uint32_t* stext, uint64_t* woff2) {
+  const uint64_t S = hs[sg.E], W = woff[sg.E];
+  GRID_STRIDE(k, sg.E + 1) {
+    if (k < sg.E && hs[k + 1] != hs[k]) {
+      const uint64_t g = hs[k];
+      woff2[g] = woff[k];
+      ws[g] = sg.ws[k];
+      sre[g] = sg.sre[k];
+      stext[g] = sg.stext[k];
+    }
+    if (k >= S) {
+      woff2[k] = W;
+      if (k < sg.E) {
+        ws[k] = 0;
+        sre[k] = 0;
+        stext[k] = 0;
+      }
+    }
+  }
+}
+
+hipError_t launch_seg_heads(const SegDev& sg, const uint64_t* woff, uint64_t* head, hipStream_t s) {
+  if (!sg.E) return hipSuccess;
+  k_seg_heads<<<grid_for(sg.E, 256), 256, 0, s>>>(sg, woff, head);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_merge(const SegDev& sg, const uint64_t* woff, const uint64_t* hs, uint64_t* ws,
+                            uint64_t* sre, uint32_t* stext, uint64_t* woff2, hipStream_t s) {
+  k_seg_merge<<<grid_for(sg.E + 1, 256), 256, 0, s>>>(sg, woff, hs, ws, sre, stext, woff2);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- probe scan (a4, a6)
 
 constexpr int kScanK = 16;                      // windows per lane per chunk
