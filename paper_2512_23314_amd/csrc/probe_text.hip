@@ -34,8 +34,10 @@ namespace bt {
 constexpr int kTlThreads = 1024;
 constexpr uint32_t kTlWaves = kTlThreads / 64;
 constexpr int kTlK = 16;  // windows per lane per chunk
-// Windows per lane whose loads the dense fast path issues together.
+// Windows per lane whose loads the dense fast path issues together, and the
+// same for chunks that cross segments (each step's position kept).
 constexpr int kTlGroup = 16;
+constexpr int kTlSlowGroup = 4;
 // Queue entries per wave: at most 63 wait between flushes and a step adds at
 // most 63 more (indices up to 126), so 127 suffice; the byte this saves per
 // wave leaves room for the workgroup's shared words beside a 64 KiB filter.
@@ -261,6 +263,79 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
         }
         return;
       }
+    }
+
+    if constexpr (LDS) {
+      // The chunk crosses segments, all of the span's one text (salt, filter
+      // and short key stay).  Per group of steps each lane first follows its
+      // windows across the segments, then the group's loads leave together.
+      const uint32_t s32 = (uint32_t)salt;
+#pragma unroll
+      for (int k0 = 0; k0 < kTlK; k0 += kTlSlowGroup) {
+        uint64_t ik[kTlSlowGroup];
+        uint32_t vm = 0, om = 0;  // steps with a main-length window, with a short-key window
+#pragma unroll
+        for (int k = 0; k < kTlSlowGroup; ++k) {
+          const uint64_t w = w0 + 64ull * (k0 + k);
+          const bool live = w < W;
+          if (live && w >= wn) {
+            do {
+              ++r;
+              wo = wn;
+              wn = woff[r + 1];
+            } while (w >= wn);
+            rs = rs_[r];
+            re = re_[r];
+          }
+          const uint64_t i = rs + (w - wo);
+          ik[k] = i;
+          if (live && i + L <= re) vm |= 1u << k;
+          if (ODD && live && oL && i + oL <= re && i < opos) om |= 1u << k;
+        }
+        uint32_t ha[kTlSlowGroup], hb[kTlSlowGroup], hc[kTlSlowGroup];
+#pragma unroll
+        for (int k = 0; k < kTlSlowGroup; ++k) {
+          hb[k] = ((vm >> k) & 1) ? H[ik[k] + L] : 0u;
+          ha[k] = (((vm | om) >> k) & 1) ? H[ik[k]] : 0u;
+          if (ODD) hc[k] = ((om >> k) & 1) ? H[ik[k] + oL] : 0u;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (ODD) {
+          uint32_t mm = 0;
+#pragma unroll
+          for (int k = 0; k < kTlSlowGroup; ++k)
+            if (((om >> k) & 1) && hc[k] - ha[k] * ox + s32 == oh) mm |= 1u << k;
+          while (mm) {
+            const int k = __builtin_ctz(mm);
+            mm &= mm - 1;
+            odd61(ik[k], salt);
+          }
+        }
+        uint32_t hv[kTlSlowGroup], wv[kTlSlowGroup];
+        bool ok[kTlSlowGroup];
+#pragma unroll
+        for (int k = 0; k < kTlSlowGroup; ++k) {
+          hv[k] = hb[k] - ha[k] * x32L + s32;
+          wv[k] = ((vm >> k) & 1) ? pass_word(hv[k]) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kTlSlowGroup; ++k) {
+          const uint32_t m = tfilter_mask(hv[k]);
+          ok[k] = ((vm >> k) & 1) && (wv[k] & m) == m;
+        }
+        if (big) {
+#pragma unroll
+          for (int k = 0; k < kTlSlowGroup; ++k) wv[k] = ok[k] ? tfw[toff + tfilter_word(hv[k], twl)] : 0u;
+#pragma unroll
+          for (int k = 0; k < kTlSlowGroup; ++k) {
+            const uint32_t m = tfilter_mask(hv[k]);
+            ok[k] = ok[k] && (wv[k] & m) == m;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kTlSlowGroup; ++k) push(ok[k], ik[k], t);
+      }
+      return;
     }
 
     // per step, following each lane across segment (and text) boundaries
