@@ -466,6 +466,7 @@ hipError_t launch_seg_merge(const SegDev& sg, const uint64_t* woff, const uint64
 // ---------------------------------------------------------------- probe scan (a4, a6)
 
 constexpr int kScanK = 16;                      // windows per lane per chunk
+constexpr int kScanSlowGroup = 4;                // steps whose loads leave together where a chunk crosses segments
 constexpr uint64_t kScanChunk = 64ull * kScanK;  // windows per wave per chunk
 static_assert(kScanChunk == kProbeTile, "the host counts algorithmic bytes per tile of kProbeTile windows");
 static_assert(kLeanK == kScanK, "lean scans take the same chunks");
@@ -727,6 +728,74 @@ void k_probe_scan(PhaseArgs a, const uint64_t* __restrict__ woff) {
         }
         continue;
       }
+    }
+
+    if constexpr (PRE && !SALT) {
+      // One text (its short key stays): the chunk crosses segments.  Per group
+      // of steps each lane first follows its windows across the segments, then
+      // the group's loads leave together.
+#pragma unroll
+      for (int k0 = 0; k0 < kScanK; k0 += kScanSlowGroup) {
+        uint64_t ik[kScanSlowGroup];
+        uint32_t vm = 0, om = 0;  // steps with a main-length window, with a short-key window
+#pragma unroll
+        for (int k = 0; k < kScanSlowGroup; ++k) {
+          const uint64_t w = w0 + 64ull * (k0 + k);
+          const bool live = w < W;
+          if (live && w >= wn) {
+            do {
+              ++r;
+              wo = wn;
+              wn = woff[r + 1];
+            } while (w >= wn);
+            rs = rs_[r];
+            re = re_[r];
+          }
+          const uint64_t i = rs + (w - wo);
+          ik[k] = i;
+          if (live && i + L <= re) vm |= 1u << k;
+          if (ODD && live && oL && i + oL <= re && i < opos) om |= 1u << k;
+        }
+        uint32_t ha[kScanSlowGroup], hb[kScanSlowGroup], hc[kScanSlowGroup];
+#pragma unroll
+        for (int k = 0; k < kScanSlowGroup; ++k) {
+          hb[k] = ((vm >> k) & 1) ? H[ik[k] + L] : 0u;
+          ha[k] = (((vm | om) >> k) & 1) ? H[ik[k]] : 0u;
+          if (ODD) hc[k] = ((om >> k) & 1) ? H[ik[k] + oL] : 0u;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (ODD) {
+          uint32_t mm = 0;
+#pragma unroll
+          for (int k = 0; k < kScanSlowGroup; ++k)
+            if (((om >> k) & 1) && hc[k] - ha[k] * ox == oh) mm |= 1u << k;
+          while (mm) {
+            const int k = __builtin_ctz(mm);
+            mm &= mm - 1;
+            odd61(ik[k], 0);
+          }
+        }
+        uint32_t hv[kScanSlowGroup];
+        bool ok[kScanSlowGroup];
+#pragma unroll
+        for (int k = 0; k < kScanSlowGroup; ++k) {
+          hv[k] = hb[k] - ha[k] * x32L;
+          ok[k] = ((vm >> k) & 1) && pass32(hv[k]);
+        }
+        if (f2words) {
+          uint64_t wv[kScanSlowGroup];
+#pragma unroll
+          for (int k = 0; k < kScanSlowGroup; ++k) wv[k] = ok[k] ? filt2[filter2_word(hv[k], f2words)] : ~0ull;
+#pragma unroll
+          for (int k = 0; k < kScanSlowGroup; ++k) {
+            const uint64_t m = filter2_mask(hv[k]);
+            ok[k] = ok[k] && (wv[k] & m) == m;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kScanSlowGroup; ++k) push(ok[k], ik[k], t);
+      }
+      continue;
     }
 
     for (int k = 0; k < kScanK; ++k) {
