@@ -1277,6 +1277,8 @@ hipError_t launch_verify(const PhaseArgs& a, const VerifyBufs& v, uint64_t max_l
   // lanes per item: about one 16-byte word per lane, at least 4 lanes
   if (max_len <= 64) {
     k_verify<4><<<grid_for(items * 4, 256, 2048), 256, 0, s>>>(a, v, cpk);
+  } else if (max_len <= 128) {
+    k_verify<8><<<grid_for(items * 8, 256, 2048), 256, 0, s>>>(a, v, cpk);
   } else if (max_len <= 256) {
     k_verify<16><<<grid_for(items * 16, 256, 2048), 256, 0, s>>>(a, v, cpk);
   } else if (max_len <= 512) {
