@@ -114,34 +114,55 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const uint64_t* __re
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Scan each tile in place and add its carry-in (carry == nullptr: none).
-// When write_total, the last tile also stores the grand total in a[n].
+// Scan each tile in place and add its carry-in (carry == nullptr: none); the
+// thread holding element n-1 (or the first thread when n == 0) also stores the
+// grand total in a[n].  Wave w of the tile owns its elements 512 w .. 512 w +
+// 511 as eight rows of 64 (lane l: element 64 k + l of row k), so every load
+// and store is one contiguous 512-byte run; each row is scanned with shuffles
+// and the rows are chained, then the waves' totals give their offsets.
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(uint64_t* __restrict__ a, uint64_t n,
                                                             const uint64_t* __restrict__ carry) {
   __shared__ uint64_t s_w[kScanThreads / 64];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-  const uint64_t first = base + (uint64_t)threadIdx.x * kScanItems;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t wbase = (uint64_t)blockIdx.x * kScanTile + (uint64_t)wv * (64 * kScanItems);
   uint64_t v[kScanItems];
-  uint64_t sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const uint64_t i = first + k;
+    const uint64_t i = wbase + 64ull * k + lane;
     v[k] = i < n ? a[i] : 0;
-    sum += v[k];
   }
-  uint64_t run = block_excl_scan(sum, s_w) + (carry ? carry[blockIdx.x] : 0);
+  // v[k] becomes the wave's exclusive prefix at its element; the element n-1
+  // keeps its inclusive prefix for a[n]
+  uint64_t run = 0, incl_last = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const uint64_t i = first + k;
-    if (i < n) a[i] = run;
-    run += v[k];
+    const uint64_t orig = v[k];
+    uint64_t x = orig;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t o = __shfl_up(x, d);
+      if (lane >= d) x += o;
+    }
+    v[k] = run + x - orig;
+    if (n && wbase + 64ull * k + lane == n - 1) incl_last = run + x;
+    run += __shfl(x, 63);
   }
-  // the thread holding element n-1 (or the first thread when n == 0) writes a[n]
-  const uint64_t last = n ? n - 1 : 0;
+  if (lane == 0) s_w[wv] = run;
+  __syncthreads();
+  uint64_t off = carry ? carry[blockIdx.x] : 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k)
+    if (k < wv) off += s_w[k];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = wbase + 64ull * k + lane;
+    if (i < n) a[i] = off + v[k];
+  }
   if (n == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) a[0] = carry ? carry[0] : 0;
-  } else if (last >= first && last < first + kScanItems) {
-    a[n] = run;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a[0] = off;
+  } else if (n - 1 >= wbase && n - 1 < wbase + 64ull * kScanItems &&
+             lane == (int)((n - 1 - wbase) & 63)) {
+    a[n] = off + incl_last;
   }
 }
 
