@@ -1434,13 +1434,16 @@ __global__ void k_pointers(PhaseArgs a, const uint8_t* marked, const uint64_t* u
   GRID_STRIDE(j, lv.c) {
     if (marked[j]) continue;
     const uint64_t p = a.k.lm[j];
-    uint64_t lo = 0, hi = lv.c;
+    const uint32_t tx = lv.text[j];
+    // the target block: the last one starting at or before p, searched among
+    // the blocks of j's own text before j (an occurrence lies in its text and
+    // ends by j's start; the checks below catch anything else)
+    uint64_t lo = tfirst[tx], hi = j;
     while (hi - lo > 1) {
       const uint64_t mid = (lo + hi) >> 1;
       if (lv.st[mid] <= p) lo = mid; else hi = mid;
     }
     const uint64_t t = lo;
-    const uint32_t tx = lv.text[j];
     const uint64_t lj = block_len(lv, a.tx, j), lt = block_len(lv, a.tx, t);
     bool ok = lv.st[t] <= p && p < lv.st[t] + lt && marked[t] && lv.text[t] == tx &&
               p + lj <= lv.st[j];
