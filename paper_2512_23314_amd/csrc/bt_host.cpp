@@ -1317,8 +1317,10 @@ int build_many(bt_ctx* ctx, const uint8_t* d_base, const std::vector<uint64_t>& 
           HIPCHK(ctx, launch_span_info(as, swoff, c * b, span_chunks, span_info.p, s));
         }
         timed(ctx, "probe_scan", 0, 0, wst, per_value * (1.0 + partner), [&] {
+          // phase 2's segments (runs of blocks whose pairs do not occur
+          // earlier) are short against a tile at the lowest levels
           return text_local ? launch_probe_text(as, swoff, has_odd, c * b, span_chunks, span_ctr.p,
-                                                span_info.p, s)
+                                                span_info.p, phase == 2 && b <= 64, s)
                             : launch_probe_scan(as, swoff, has_odd, has_salt, c * b, scan_mode, s);
         }, a.Lmain);
       }

@@ -202,6 +202,12 @@ __device__ __forceinline__ void st_relaxed(uint64_t* p, uint64_t v) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// v of lane src (every lane of the wave takes part), in two 32-bit halves.
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
+  const uint32_t lo = __shfl((uint32_t)v, (int)src), hi = __shfl((uint32_t)(v >> 32), (int)src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Sum of a 64-lane wave under add61.
 __device__ __forceinline__ uint64_t wave_sum61(uint64_t v) {
 #pragma unroll

@@ -279,9 +279,11 @@ uint64_t probe_text_spans(uint64_t max_windows, uint64_t span_chunks);
 // span into span_info (3 * probe_text_spans(...) words).
 hipError_t launch_span_info(const PhaseArgs& a, const uint64_t* woff, uint64_t max_windows,
                             uint64_t span_chunks, uint64_t* span_info, hipStream_t s);
+// short_segments: the segments are expected to be short against a tile (the
+// scan then walks them from registers; dense hashes only).
 hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
                              uint64_t max_windows, uint64_t span_chunks, uint64_t* span_ctr,
-                             const uint64_t* span_info, hipStream_t s);
+                             const uint64_t* span_info, bool short_segments, hipStream_t s);
 // Folds the filters of the nbig texts listed in big (see PhaseArgs.tf_fold).
 hipError_t launch_fold_filters(const PhaseArgs& a, const uint32_t* big, uint32_t nbig,
                                hipStream_t s);

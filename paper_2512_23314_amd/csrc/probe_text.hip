@@ -46,7 +46,10 @@ constexpr uint32_t kNoText = 0xFFFFFFFFu;
 static_assert(64ull * kTlK == kProbeTile, "a chunk is one probe tile");
 static_assert(kLeanK == kTlK, "lean chunks are probe tiles too");
 
-template <bool ODD, bool LEAN>
+// SEGT: where tiles cross many short segments (phase 2 of the lowest levels),
+// a tile's segments are loaded once into registers and walked by shuffles; a
+// separate instance, since the extra registers slow the other levels.
+template <bool ODD, bool LEAN, bool SEGT>
 __global__ __launch_bounds__(kTlThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_chunks,
                   uint64_t* __restrict__ span_ctr, const uint64_t* __restrict__ span_info) {
@@ -270,6 +273,22 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
       // and short key stay).  Per group of steps each lane first follows its
       // windows across the segments, then the group's loads leave together.
       const uint32_t s32 = (uint32_t)salt;
+      // (SEGT) the segments from lane 0's on, segment rb + s in lane s: its
+      // end as a window number relative to the tile (clamped) and its
+      // positions; past the 64th, a lane reads global memory
+      const uint64_t cw = ch * kProbeTile;
+      uint64_t rb = 0, trs = 0, tre = 0;
+      uint32_t tend = ~0u;
+      if constexpr (SEGT) {
+        rb = shfl64(r, 0);
+        const uint64_t q = rb + (uint64_t)lane;
+        if (q < R) {
+          const uint64_t e = woff[q + 1] - cw;
+          tend = e < 0xFFFFFFFFull ? (uint32_t)e : ~0u;
+          trs = rs_[q];
+          tre = re_[q];
+        }
+      }
 #pragma unroll
       for (int k0 = 0; k0 < kTlK; k0 += kTlSlowGroup) {
         uint64_t ik[kTlSlowGroup];
@@ -278,7 +297,30 @@ void k_probe_text(PhaseArgs a, const uint64_t* __restrict__ woff, uint64_t span_
         for (int k = 0; k < kTlSlowGroup; ++k) {
           const uint64_t w = w0 + 64ull * (k0 + k);
           const bool live = w < W;
-          if (live && w >= wn) {
+          if constexpr (SEGT) {
+            bool adv = live && w >= wn;
+            while (__ballot(adv)) {
+              // every lane takes part in the shuffles; those moving on use them
+              const uint64_t s = r + 1 - rb;
+              const uint32_t sl = (uint32_t)s & 63u;
+              const uint32_t ne = __shfl(tend, (int)sl);
+              const uint64_t nrs = shfl64(trs, sl), nre = shfl64(tre, sl);
+              if (adv) {
+                ++r;
+                wo = wn;
+                if (s < 64) {
+                  wn = cw + ne;
+                  rs = nrs;
+                  re = nre;
+                } else {
+                  wn = woff[r + 1];
+                  rs = rs_[r];
+                  re = re_[r];
+                }
+                adv = w >= wn;
+              }
+            }
+          } else if (live && w >= wn) {
             do {
               ++r;
               wo = wn;
@@ -467,7 +509,7 @@ hipError_t launch_span_info(const PhaseArgs& a, const uint64_t* woff, uint64_t m
 
 hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_odd,
                              uint64_t max_windows, uint64_t span_chunks, uint64_t* span_ctr,
-                             const uint64_t* span_info, hipStream_t s) {
+                             const uint64_t* span_info, bool short_segments, hipStream_t s) {
   if (a.lv.R == 0) return hipSuccess;
   if (!a.tf_words || !a.pre32 || span_chunks == 0 || !span_info) return hipErrorInvalidValue;
   const uint64_t spans = probe_text_spans(max_windows, span_chunks);
@@ -476,17 +518,24 @@ hipError_t launch_probe_text(const PhaseArgs& a, const uint64_t* woff, bool has_
   const unsigned grid = (unsigned)(spans < 256 ? (spans ? spans : 1) : 256);
   const bool lean = a.P32 == nullptr;  // sampled 32-bit hashes: the rolled window loop
   const size_t lds = ((size_t)4 << kTextFilterLdsLog2) + (size_t)kTlWaves * kTlQueue * 8;
-#define BT_TL_LAUNCH(O, LN)                                                                 \
+#define BT_TL_LAUNCH(O, LN, SG)                                                             \
   do {                                                                                      \
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_probe_text<O, LN>), \
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    const hipError_t e = hipFuncSetAttribute(                                               \
+        reinterpret_cast<const void*>(&k_probe_text<O, LN, SG>),                            \
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                              \
     if (e != hipSuccess) return e;                                                          \
-    k_probe_text<O, LN><<<grid, kTlThreads, lds, s>>>(a, woff, span_chunks, span_ctr, span_info); \
+    k_probe_text<O, LN, SG><<<grid, kTlThreads, lds, s>>>(a, woff, span_chunks, span_ctr,     \
+                                                         span_info);                        \
   } while (0)
+  const bool segt = short_segments && !lean;
   if (has_odd) {
-    if (lean) BT_TL_LAUNCH(true, true); else BT_TL_LAUNCH(true, false);
+    if (lean) BT_TL_LAUNCH(true, true, false);
+    else if (segt) BT_TL_LAUNCH(true, false, true);
+    else BT_TL_LAUNCH(true, false, false);
   } else {
-    if (lean) BT_TL_LAUNCH(false, true); else BT_TL_LAUNCH(false, false);
+    if (lean) BT_TL_LAUNCH(false, true, false);
+    else if (segt) BT_TL_LAUNCH(false, false, true);
+    else BT_TL_LAUNCH(false, false, false);
   }
 #undef BT_TL_LAUNCH
   return hipGetLastError();
