@@ -31,6 +31,7 @@ inline uint64_t __ballot(bool p) {
 inline int __popcll(uint64_t v) { return __builtin_popcountll(v); }
 template <class T> T __shfl_xor(T, int) { abort(); }
 template <class T> T __shfl_up(T, int) { abort(); }
+template <class T> T __shfl(T, int) { abort(); }
 inline unsigned long long atomicMin(unsigned long long* p, unsigned long long v) {
   unsigned long long o = __atomic_load_n(p, __ATOMIC_RELAXED);
   while (v < o && !__atomic_compare_exchange_n(p, &o, v, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {}
