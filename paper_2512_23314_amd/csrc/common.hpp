@@ -118,17 +118,17 @@ __device__ __forceinline__ uint32_t prefix8_bit(uint32_t lo, uint32_t hi, uint32
   return ((lo * 0x9E3779B1u) ^ (hi * 0x85EBCA77u)) >> (32 - bits);
 }
 
-// P[i] from prefix fingerprints sampled every 16 positions (Ps[q] = P[base +
-// 16 q]): the sample at or below i, then Horner's rule over the bytes between.
-// The up to 15 bytes come from three aligned 8-byte loads issued together (one
-// dependent byte load per step would wait a memory round trip each), when the
-// words lie inside the text [.., end); else byte by byte.
+// P[i] from prefix fingerprints sampled every 2^sh positions (Ps[q] = P[base +
+// 2^sh q], sh <= 4): the sample at or below i, then Horner's rule over the
+// bytes between.  The up to 15 bytes come from three aligned 8-byte loads
+// issued together (one dependent byte load per step would wait a memory round
+// trip each), when the words lie inside the text [.., end); else byte by byte.
 __device__ __forceinline__ uint64_t prefix_at(const uint64_t* __restrict__ Ps,
                                               const uint8_t* __restrict__ T, uint64_t base,
-                                              uint64_t end, uint64_t x, uint64_t i) {
+                                              uint64_t end, uint64_t x, uint64_t i, uint32_t sh) {
   const uint64_t r = i - base;
-  const uint32_t m = (uint32_t)(r & 15);
-  uint64_t v = Ps[r >> 4];
+  const uint32_t m = (uint32_t)(r & ((1u << sh) - 1));
+  uint64_t v = Ps[r >> sh];
   if (!m) return v;
   const uint64_t j0 = i - m;
   if (j0 + 24 <= end) {

@@ -34,12 +34,14 @@ inline uint64_t prefix_status_words(uint64_t n) {
 
 // P[0] = 0, P[i+1] = P[i] x + T[i] (mod 2^61 - 1) for i < n, stored dense
 // (n + 1 words) or, when sampled, as Ps[q] = P[16 q] for 16 q <= n (n / 16 + 1
-// words); and, when H is not null, H[0] = 0, H[i+1] = H[i] x32 + T[i] (mod
+// words), or with quarter (not sampled) as Ps[q] = P[4 q] for 4 q <= n (n / 4 +
+// 1 words); and, when H is not null, H[0] = 0, H[i+1] = H[i] x32 + T[i] (mod
 // 2^32), the pre-filter hashes of the probe scan (n + 1 words), from the same
 // pass over the text; hsampled (with sampled): H holds H[16 q] for 16 q <= n
 // instead (n / 16 + 1 words).  status: prefix_status_words(n) words.
 hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled, uint32_t* H,
-                         const PfTab* tab, uint64_t* status, hipStream_t s, bool hsampled = false);
+                         const PfTab* tab, uint64_t* status, hipStream_t s, bool hsampled = false,
+                         bool quarter = false);
 
 // ---- level data (device arrays; positions are offsets into the text base) ----
 struct TextsDev {
@@ -96,7 +98,8 @@ struct TableDev {
 struct PhaseArgs {
   const uint8_t* T;
   const uint64_t* P;      // prefix fingerprints by text position, or null when sampled:
-  const uint64_t* Ps;     // Ps[q] = P[pbase + 16 q] (memory-lean builds)
+  const uint64_t* Ps;     // Ps[q] = P[pbase + 2^pshift q]
+  uint32_t pshift;        // 4 (memory-lean builds), or 2 (dense 32-bit hashes beside them)
   uint64_t pbase;
   uint64_t pend;          // end of the text bytes (offset), for the lean loads
   TextsDev tx;

@@ -110,7 +110,8 @@ __device__ typename A::V look_back(uint64_t* status, uint64_t tile, typename A::
 }
 
 // Two waves per SIMD: the register budget of three spilled, and ran slower.
-template <bool SAMPLED, bool WH, bool HS>
+// Q4 (not SAMPLED): the fingerprints every 4th position, Ps[q] = P[4 q].
+template <bool SAMPLED, bool WH, bool HS, bool Q4>
 __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_prefix(
     const uint8_t* __restrict__ T, uint64_t n, uint64_t* __restrict__ P, uint32_t* __restrict__ H,
     const PfTab* __restrict__ tb, uint64_t* __restrict__ st61, uint64_t* __restrict__ st32,
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
   // chain starts P[16 m], H[16 m] of the tile (m = 0..1023), and per wave a
   // staging area: 64 rows of 8 fingerprints, or of 16 hashes (row strides 9
   // and 17 words keep the lanes on different banks)
-  constexpr bool DENSE = !SAMPLED;
+  constexpr bool DENSE = !SAMPLED && !Q4;
   __shared__ uint64_t s_st61[DENSE ? kPfTile / 16 : 1];
   __shared__ uint32_t s_st32[(WH && !HS) ? kPfTile / 16 : 1];
   __shared__ uint64_t s_out[(DENSE || (WH && !HS)) ? (kPfThreads / 64) * 64 * 9 : 1];
@@ -298,6 +299,24 @@ __global__ __launch_bounds__(kPfThreads) __attribute__((amdgpu_waves_per_eu(2)))
             if (pos + 16 * c <= n) P[(pos >> 4) + c] = v[c];
           if (pos + kPfBytes == n) P[n >> 4] = mad61(C, tb->t61[1], h61);
         }
+      } else if (Q4) {
+        // every 4th: from each P[pos + 16 c], four Horner steps at a time
+        if (pos <= n) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            uint64_t val = v[c];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              const uint64_t q = pos + 16 * c + 4 * d;
+              if (q <= n) P[q >> 2] = val;
+              if (d < 3) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) val = mad61(val, x1, byte_at(16 * c + 4 * d + e));
+              }
+            }
+          }
+          if (pos + kPfBytes == n) P[n >> 2] = mad61(C, tb->t61[1], h61);
+        }
       } else {
 #pragma unroll
         for (int c = 0; c < 4; ++c) s_st61[4 * t + c] = v[c];
@@ -383,7 +402,8 @@ __global__ void k_zero(V* p, uint64_t n) {
 }  // namespace
 
 hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled, uint32_t* H,
-                         const PfTab* tab, uint64_t* status, hipStream_t s, bool hsampled) {
+                         const PfTab* tab, uint64_t* status, hipStream_t s, bool hsampled,
+                         bool quarter) {
   const uint64_t tiles = (n + kPfTile - 1) / kPfTile;
   if (tiles == 0) {  // P[0] = 0 (and H[0] = 0) only
     k_zero<uint64_t><<<1, 64, 0, s>>>(P, 1);
@@ -397,16 +417,19 @@ hipError_t launch_prefix(const uint8_t* T, uint64_t n, uint64_t* P, bool sampled
   uint64_t* st32 = status + tiles + 1;
   uint32_t* ctr = reinterpret_cast<uint32_t*>(status + 2 * (tiles + 1));
   const unsigned grid = (unsigned)(tiles < kPfGrid ? tiles : kPfGrid);
+  if (quarter && (sampled || hsampled || !H)) return hipErrorInvalidValue;
   if (sampled && hsampled) {
     if (!H) return hipErrorInvalidValue;
-    k_prefix<true, true, true><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    k_prefix<true, true, true, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
   } else if (sampled) {
-    if (H) k_prefix<true, true, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
-    else k_prefix<true, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    if (H) k_prefix<true, true, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    else k_prefix<true, false, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+  } else if (quarter) {
+    k_prefix<false, true, false, true><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
   } else {
     if (hsampled) return hipErrorInvalidValue;
-    if (H) k_prefix<false, true, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
-    else k_prefix<false, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    if (H) k_prefix<false, true, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
+    else k_prefix<false, false, false, false><<<grid, kPfThreads, 0, s>>>(T, n, P, H, tab, st61, st32, ctr, tiles);
   }
   return hipGetLastError();
 }

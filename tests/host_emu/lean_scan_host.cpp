@@ -108,7 +108,7 @@ int main(int argc, char** argv) {
     }
     onk[0] = 1;
     PhaseArgs a{};
-    a.T = T; a.Ps = Ps; a.Hs = Hs; a.pbase = base; a.pend = end; a.x = x;
+    a.T = T; a.Ps = Ps; a.pshift = 4; a.Hs = Hs; a.pbase = base; a.pend = end; a.x = x;
     a.Lmain = L; a.fpmask = ~0ull; a.x32 = x32;
     uint32_t xl = 1; for (uint64_t k = 0; k < L; ++k) xl *= x32;
     uint32_t xlm1 = 1; for (uint64_t k = 0; k + 1 < L; ++k) xlm1 *= x32;

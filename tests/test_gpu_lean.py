@@ -84,8 +84,8 @@ def test_lean_unaligned_views_and_pruning(ctx):
 
 def test_lean_needs_less_memory(ctx):
     """Peak pool bytes of one build, lean against dense, on 32 MiB: the prefix
-    fingerprints shrink from 8 to 0.5 bytes per text byte and the 32-bit
-    prefix hashes from 4 to 0.25."""
+    fingerprints shrink from 2 (a single text's dense build keeps every 4th)
+    to 0.5 bytes per text byte and the 32-bit prefix hashes from 4 to 0.25."""
     torch = torch_cuda()
     T = synth.markov_versions(32 << 20, 1 << 18, 1 << 10, 5e-4, 64, 3)
     d = to_device(T)
@@ -98,5 +98,5 @@ def test_lean_needs_less_memory(ctx):
         tree = ctx.build(d, tau=4, leaf_len=16, lean=lean)
         peaks[lean] = ctx.memory()["peak"] - base
         tree.free()
-    assert peaks[False] - peaks[True] >= 11 * len(T), peaks
+    assert peaks[False] - peaks[True] >= 5 * len(T), peaks
     assert peaks[True] <= 3 * len(T), peaks
